@@ -1,0 +1,115 @@
+"""Invariant-subspace bases from the matrix sign function - oracle.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+* ``alg6_cholesky_bases``: Alg. 6 for a definite pseudosymmetric matrix with
+  Sigma = diag(I_p, -I_q).  Q_{1,+} = chol(P_+(1:p,1:p)) (upper factor, R^T R),
+  Q_+ = [Q_{1,+}^T; P_+(p+1:n,1:p) Q_{1,+}^{-1}].  For Q_- the printed formula
+  [Sigma Q_{1,-}^T; P_-(..) Q_{1,-}^{-1}] drops the factor hat Sigma_- = -I that
+  Thm. HRisLDL puts into H = Sigma R^T hat Sigma; without it the two blocks have
+  inconsistent signs and the columns leave range(P_-).  The oracle applies the
+  theorem as stated: with -Sigma P_- = R^T R (R from the Cholesky factor of the
+  leading q x q block, as printed), Q_- = Sigma R^T hat Sigma = -Sigma R^T.
+* ``alg7_ldl_bases``: Alg. 7, the truncated pivoted LDL^T variant: ldl(Sigma P_+)
+  = L D L^T, diagonalize the 1x1/2x2 blocks of D, keep the p largest entries,
+  Q_+ = Sigma L V(:,1:p) D(1:p,1:p)^{1/2}; likewise with ldl(-Sigma P_-).
+* ``alg4_orthogonal_bases``: Alg. 4 for a symmetric matrix: r_+ = trace(P_+),
+  lower Cholesky factor of the leading r_+ block of P_+ extended by
+  P_+(r_++1:n,1:r_+) Q_{1,+}^{-T}; the second half uses P_- throughout (the
+  printed final line refers to P_+, which cannot give a basis of range(P_-)).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def projectors(s: np.ndarray):
+    """P_+ = (I + S)/2, P_- = (I - S)/2 (Lemma SignProj)."""
+    n = s.shape[0]
+    eye = np.eye(n)
+    return 0.5 * (eye + s), 0.5 * (eye - s)
+
+
+def alg6_cholesky_bases(s: np.ndarray, p: int):
+    """Alg. 6 with Sigma = diag(I_p, -I_{n-p}).  Returns (Q_+, Q_-)."""
+    n = s.shape[0]
+    q = n - p
+    sigma = np.concatenate([np.ones(p), -np.ones(q)])
+    pp, pm = projectors(s)
+    # positive part: Q_{1,+} = chol(Sigma(1:p,1:p) P_+(1:p,1:p)), upper, R^T R
+    c_plus = sla.cholesky(sigma[:p, None] * pp[:p, :p], lower=False)
+    top = (sigma[:p, None] * c_plus.T)
+    bottom = sla.solve_triangular(c_plus, pp[p:, :p].T, trans="T", lower=False).T  # P21 C^{-1}
+    q_plus = np.vstack([top, bottom])
+    # negative part: -Sigma P_- = R^T R with R = [C, C^{-T} T_12] (pivot on the leading q rows)
+    t = -(sigma[:, None] * pm)
+    c_minus = sla.cholesky(t[:q, :q], lower=False)
+    r_rest = sla.solve_triangular(c_minus, t[:q, q:], trans="T", lower=False)    # C^{-T} T_12
+    rt = np.vstack([c_minus.T, r_rest.T])            # R^T (n x q)
+    q_minus = -(sigma[:, None] * rt)                 # Sigma R^T hat Sigma_-, hat Sigma_- = -I
+    return q_plus, q_minus
+
+
+def alg6_cholesky_bases_plus(s: np.ndarray, p: int):
+    """The Q_+ half of Alg. 6 only."""
+    n = s.shape[0]
+    sigma = np.concatenate([np.ones(p), -np.ones(n - p)])
+    pp, _ = projectors(s)
+    c_plus = sla.cholesky(sigma[:p, None] * pp[:p, :p], lower=False)
+    bottom = sla.solve_triangular(c_plus, pp[p:, :p].T, trans="T", lower=False).T
+    return np.vstack([sigma[:p, None] * c_plus.T, bottom])
+
+
+def alg6_cholesky_bases_as_printed(s: np.ndarray, p: int):
+    """Alg. 6 exactly as printed (kept only to document the sign error of Q_-)."""
+    n = s.shape[0]
+    q = n - p
+    sigma = np.concatenate([np.ones(p), -np.ones(q)])
+    pp, pm = projectors(s)
+    c_plus = sla.cholesky(sigma[:p, None] * pp[:p, :p], lower=False)
+    q_plus = np.vstack([sigma[:p, None] * c_plus.T,
+                        sla.solve_triangular(c_plus, pp[p:, :p].T, trans="T").T])
+    c_minus = sla.cholesky(-(sigma[:q, None] * pm[:q, :q]), lower=False)
+    q_minus = np.vstack([sigma[:q, None] * c_minus.T,
+                         sla.solve_triangular(c_minus, pm[q:, :q].T, trans="T").T])
+    return q_plus, q_minus
+
+
+def _truncated_ldl_basis(mat: np.ndarray, keep: int, sigma: np.ndarray):
+    """Sigma L V(:,1:keep) D(1:keep,1:keep)^{1/2} from ldl(mat) (Alg. 7 steps 3-5)."""
+    lu, d, _perm = sla.ldl(mat, lower=True)
+    w, v = np.linalg.eigh(0.5 * (d + d.T))      # D is block diagonal: its eigen-decomposition
+    order = np.argsort(w)[::-1]                  # descending
+    w = w[order][:keep]
+    v = v[:, order][:, :keep]
+    if np.any(w <= 0):
+        raise np.linalg.LinAlgError("truncated LDL^T: non-positive retained pivot")
+    return sigma[:, None] * ((lu @ v) * np.sqrt(w)[None, :])
+
+
+def alg7_ldl_bases(s: np.ndarray, sigma: np.ndarray):
+    """Alg. 7 for general Sigma (p = number of +1 entries).  Returns (Q_+, Q_-)."""
+    p = int(np.sum(sigma > 0))
+    q = s.shape[0] - p
+    pp, pm = projectors(s)
+    q_plus = _truncated_ldl_basis(sigma[:, None] * pp, p, sigma)
+    q_minus = _truncated_ldl_basis(-(sigma[:, None] * pm), q, sigma)
+    return q_plus, q_minus
+
+
+def alg4_orthogonal_bases(s: np.ndarray):
+    """Alg. 4 for symmetric A with S = sign(A).  Returns (Q_+, Q_-), Q^T Q = I."""
+    n = s.shape[0]
+    pp, pm = projectors(s)
+    r_plus = int(round(np.trace(pp)))
+    r_minus = n - r_plus
+    out = []
+    for proj, rk in ((pp, r_plus), (pm, r_minus)):
+        if rk == 0:
+            out.append(np.zeros((n, 0)))
+            continue
+        l1 = sla.cholesky(proj[:rk, :rk], lower=True)        # Q_1 Q_1^T = P(1:rk,1:rk)
+        lower = sla.solve_triangular(l1, proj[rk:, :rk].T, lower=True).T  # P21 Q_1^{-T}
+        out.append(np.vstack([l1, lower]))
+    return out[0], out[1]
