@@ -1,0 +1,151 @@
+/*
+ * pseudosym - structure-preserving spectral division of definite pseudosymmetric
+ * matrices on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Benner, Nakatsukasa, Penke, "A Structure-Preserving Divide-and-Conquer
+ * Method for Pseudosymmetric Matrices" (arXiv 2203.08900).  The library handles
+ * the Casida / real Bethe-Salpeter form (Sec. 5, Eq:Casida)
+ *
+ *        H = [[ A,  B],       A = A^T,  B = B^T  (m x m),  n = 2m,
+ *             [-B, -A]]       Sigma = diag(I_m, -I_m),
+ *
+ * in the definite case, i.e. Sigma*H positive definite, which for this form means
+ * A + B and A - B are both symmetric positive definite.  Then (Thm. EVREalSigmaOrth)
+ * H has m positive and m negative real eigenvalues, they come in pairs +-lambda,
+ * and one spectral division step decouples H into a symmetric positive definite
+ * block and its negative (Thm. DefDivConq).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are double precision, column-major, with leading dimension >= rows.
+ *    All matrix pointers are DEVICE pointers on the device that is current when
+ *    the handle was created; the caller owns every input and output buffer.
+ *  - A and B are read through their upper triangles and are not modified.
+ *  - Work is enqueued on the handle's stream.  Every call synchronizes that stream
+ *    once before returning, because the stopping test of the iteration and the
+ *    info record are host data; outputs are complete when the call returns.
+ *  - Return value: 0 on success; a negative value -k means argument k (1-based,
+ *    the handle being argument 1) is invalid and nothing was launched; a positive
+ *    value is one of the PS_* status codes below, in which case the outputs are
+ *    undefined and `info` (if given) says where the failure happened.
+ *  - Device memory: the library draws its scratch space from a workspace that the
+ *    caller can provide with ps_set_workspace(); without one, the handle allocates
+ *    (and keeps) what it needs on first use.
+ */
+#ifndef PSEUDOSYM_H
+#define PSEUDOSYM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_handle_s* ps_handle;
+
+/* status codes (positive: numerical or runtime failure) */
+enum {
+  PS_OK = 0,
+  PS_NOT_DEFINITE = 1,     /* Cholesky of A+B or A-B failed: Sigma*H is not positive definite */
+  PS_SHIFT_BREAKDOWN = 2,  /* Cholesky of a shifted Gram matrix X^T X + c I failed */
+  PS_NOT_CONVERGED = 3,    /* the stopping test of Alg. 8 failed after max_restarts restarts */
+  PS_HIP_ERROR = 4,        /* a HIP runtime call failed */
+  PS_NO_WORKSPACE = 5,     /* the caller-provided workspace is too small */
+  PS_BASIS_BREAKDOWN = 6   /* Cholesky of the leading block of P_+ failed (Alg. 6) */
+};
+
+/* arithmetic of the Zolotarev steps */
+enum {
+  PS_PREC_FP64 = 0,        /* everything in FP64 (plain form) */
+  PS_PREC_MIXED = 1        /* FP32 matrix-core bulk, FP64 for ill-conditioned shifts,
+                              FP64 refinement and subspace orthogonalization */
+};
+
+typedef struct {
+  int precision;       /* PS_PREC_*                                               */
+  int r;               /* Zolotarev degree parameter (type (2r+1, 2r)), 1..8;    */
+                       /* 0 picks the smallest r that converges in two steps     */
+  int max_restarts;    /* restarts allowed by the stopping test of Alg. 8 (>= 0) */
+  int max_steps;       /* 0: full method.  1: stop after the first Zolotarev step */
+                       /* and return that iterate in place of sign(H) (the blocks */
+                       /* of X_1 = hat Z(H/alpha)); only honoured by pseudosym_sign */
+  int lanczos_steps;   /* Golub-Kahan steps of the alpha/beta estimator (>= 4)   */
+  int timing;          /* nonzero: fill info->phase_ms with per-phase GPU times  */
+  double alpha;        /* > 0: caller's upper bound of max|lambda(H)| (skips the  */
+  double beta;         /* estimator); > 0: caller's lower bound of min|lambda(H)| */
+  double mixed_kappa;  /* mixed precision: shifts whose condition number          */
+                       /* (1 + c)/(l^2 + c) exceeds this run in FP64               */
+} ps_opts;
+
+typedef struct {
+  int status;
+  int steps;               /* Zolotarev steps taken (2 per attempt)                 */
+  int restarts;
+  int r;
+  int shifts_fp64[2];      /* shifts per step that ran in FP64                      */
+  int failed_step;         /* step whose Cholesky failed (-1: none)                 */
+  int failed_mask;         /* batch bitmask of the failing Cholesky factorizations  */
+  double alpha, beta;      /* bounds actually used                                  */
+  double ell[4];           /* l at the start of each step (attempt-major)           */
+  double step_change;      /* ||X2 - X1||_F / ||X2||_F of the accepted attempt      */
+  double sigma_est[2];     /* estimator output: sigma_max(Y0), 1/sigma_max(Y0^{-1}) */
+  double phase_ms[8];      /* setup, estimate, step1, step2, refine, assemble,      */
+                           /* bases, decouple (when opts->timing)                    */
+} ps_info;
+
+/* Fill *o with the defaults: FP64, r = 8, 2 restarts, full method, 20 Lanczos
+ * steps, no timing, estimated alpha/beta, mixed_kappa = 20. */
+void ps_opts_default(ps_opts* o);
+
+/* Create a handle bound to `stream` (a hipStream_t, NULL = default stream) on
+ * the current device.  Returns 0 or PS_HIP_ERROR. */
+int ps_create(ps_handle* h, void* stream);
+int ps_destroy(ps_handle h);
+int ps_set_stream(ps_handle h, void* stream);
+
+/* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig)
+ * needs at half-size m with options o (NULL = defaults). */
+size_t ps_workspace_size(int m, const ps_opts* o, int what);
+
+/* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the
+ * workspace from now on; NULL reverts to library-owned memory.  The buffer must
+ * outlive every call that uses it. */
+int ps_set_workspace(ps_handle h, void* dptr, size_t bytes);
+
+/* Host-only: coefficients of the scaled Zolotarev function hat Z_{2r+1}(x; ell)
+ * (Eq:Compcis, Eq:hatZ, Eq:ZPartialFrac2): c[0..2r-1] = c_1..c_2r,
+ * a[0..r-1] = a_1..a_r, *chat = hat C, *ell_next = hat Z(ell; ell) (the l update
+ * of Alg. 8).  0 < ell < 1, 1 <= r <= 8.  Returns 0 or -1 on bad arguments. */
+int ps_zolotarev_coeffs(double ell, int r, double* c, double* a, double* chat,
+                        double* ell_next);
+
+/* sign(H) by the Zolotarev iteration of Alg. 8 (two steps of r independent shifted
+ * factorizations each, with the stopping test and restart of Alg. 8).  Output:
+ * the blocks of sign(H) = [[SA, SB], [-SB, -SA]] (the odd function of H keeps the
+ * Casida form), SA and SB symmetric m x m with leading dimension lds. */
+int pseudosym_sign(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                   double* SA, double* SB, int lds, const ps_opts* opts, ps_info* info);
+
+/* One step of structure-preserving spectral division (Alg. 3 with sigma = 0 for a
+ * definite H): sign(H) as above, then the (Sigma, I)-orthogonal basis Q_+ of the
+ * invariant subspace of the m positive eigenvalues by Alg. 6, and the decoupled
+ * block H_+ = Q_+^T Sigma H Q_+ (Thm. DefDivConq).
+ * Outputs: Qp, 2m x m with leading dimension ldq >= 2m, Q_+^T Sigma Q_+ = I, whose
+ * top m x m block is lower triangular with positive diagonal (the Cholesky form of
+ * Alg. 6, which makes Q_+ unique); Hp, m x m symmetric positive definite with
+ * leading dimension ldh, whose eigenvalues are the m positive eigenvalues of H.
+ * The negative half follows from the structure: Q_- = Pi Q_+ with
+ * Pi = [[0, I], [I, 0]] spans the negative invariant subspace, Q_-^T Sigma Q_- = -I,
+ * and H_- = -H_+. */
+int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                     double* Qp, int ldq, double* Hp, int ldh, const ps_opts* opts,
+                     ps_info* info);
+
+/* Human-readable name of a status code. */
+const char* ps_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSEUDOSYM_H */

@@ -1,0 +1,276 @@
+"""ctypes binding of libpseudosym.so (C-ABI in include/pseudosym.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.
+PyTorch supplies device memory (inputs, outputs, the workspace) and the stream.
+Tensors are float64 on a ROCm device; symmetric m x m inputs can be passed in
+either memory order.  Matrices returned by the library are column-major, which the
+functions expose as transposed views of row-major tensors.
+
+The library must have been built (``python -m paper_2203_08900_amd.build``);
+loading fails loudly otherwise.  There is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpseudosym.so")
+
+PS_PREC_FP64 = 0
+PS_PREC_MIXED = 1
+
+STATUS = {
+    0: "ok", 1: "not definite", 2: "shift breakdown", 3: "not converged",
+    4: "HIP error", 5: "no workspace", 6: "basis breakdown",
+}
+
+
+class PsOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("r", ctypes.c_int),
+        ("max_restarts", ctypes.c_int),
+        ("max_steps", ctypes.c_int),
+        ("lanczos_steps", ctypes.c_int),
+        ("timing", ctypes.c_int),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("mixed_kappa", ctypes.c_double),
+    ]
+
+
+class PsInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("steps", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("r", ctypes.c_int),
+        ("shifts_fp64", ctypes.c_int * 2),
+        ("failed_step", ctypes.c_int),
+        ("failed_mask", ctypes.c_int),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("ell", ctypes.c_double * 4),
+        ("step_change", ctypes.c_double),
+        ("sigma_est", ctypes.c_double * 2),
+        ("phase_ms", ctypes.c_double * 8),
+    ]
+
+    def as_dict(self):
+        return {
+            "status": self.status, "steps": self.steps, "restarts": self.restarts,
+            "r": self.r, "shifts_fp64": list(self.shifts_fp64),
+            "failed_step": self.failed_step, "failed_mask": self.failed_mask,
+            "alpha": self.alpha, "beta": self.beta, "ell": list(self.ell),
+            "step_change": self.step_change, "sigma_est": list(self.sigma_est),
+            "phase_ms": list(self.phase_ms),
+        }
+
+
+EXPORTS = [
+    "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
+    "ps_set_workspace", "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
+    "pseudosym_eig", "ps_status_string",
+]
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Load libpseudosym.so and declare the C signatures (raises if not built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2203_08900_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, ip, dp, sz = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t
+        hp = ctypes.c_void_p
+        lib.ps_opts_default.argtypes = [ctypes.POINTER(PsOpts)]
+        lib.ps_opts_default.restype = None
+        lib.ps_create.argtypes = [ctypes.POINTER(hp), vp]
+        lib.ps_create.restype = ip
+        lib.ps_destroy.argtypes = [hp]
+        lib.ps_destroy.restype = ip
+        lib.ps_set_stream.argtypes = [hp, vp]
+        lib.ps_set_stream.restype = ip
+        lib.ps_workspace_size.argtypes = [ip, ctypes.POINTER(PsOpts), ip]
+        lib.ps_workspace_size.restype = sz
+        lib.ps_set_workspace.argtypes = [hp, vp, sz]
+        lib.ps_set_workspace.restype = ip
+        lib.ps_zolotarev_coeffs.argtypes = [ctypes.c_double, ip, dp, dp, dp, dp]
+        lib.ps_zolotarev_coeffs.restype = ip
+        mat = [hp, ip, vp, ip, vp, ip]
+        lib.pseudosym_sign.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts), ctypes.POINTER(PsInfo)]
+        lib.pseudosym_sign.restype = ip
+        lib.pseudosym_divide.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
+                                               ctypes.POINTER(PsInfo)]
+        lib.pseudosym_divide.restype = ip
+        if hasattr(lib, "pseudosym_eig"):
+            lib.pseudosym_eig.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts),
+                                                ctypes.POINTER(PsInfo)]
+            lib.pseudosym_eig.restype = ip
+        lib.ps_status_string.argtypes = [ip]
+        lib.ps_status_string.restype = ctypes.c_char_p
+        _lib = lib
+        return lib
+
+
+def zolotarev_coeffs(ell: float, r: int):
+    """Host-side coefficients (no GPU needed): dict with c, a, chat, ell_next."""
+    lib = load()
+    c = (ctypes.c_double * 16)()
+    a = (ctypes.c_double * 8)()
+    chat = ctypes.c_double()
+    nxt = ctypes.c_double()
+    rc = lib.ps_zolotarev_coeffs(float(ell), int(r), c, a, ctypes.byref(chat), ctypes.byref(nxt))
+    if rc != 0:
+        raise ValueError(f"ps_zolotarev_coeffs({ell}, {r}) failed")
+    return {"c": list(c[:2 * r]), "a": list(a[:r]), "chat": chat.value, "ell_next": nxt.value}
+
+
+def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=20,
+              timing=False, alpha=0.0, beta=0.0, mixed_kappa=20.0) -> PsOpts:
+    lib = load()
+    o = PsOpts()
+    lib.ps_opts_default(ctypes.byref(o))
+    o.precision = {"fp64": PS_PREC_FP64, "mixed": PS_PREC_MIXED}[precision] \
+        if isinstance(precision, str) else int(precision)
+    o.r = int(r)
+    o.max_restarts = int(max_restarts)
+    o.max_steps = int(max_steps)
+    o.lanczos_steps = int(lanczos_steps)
+    o.timing = 1 if timing else 0
+    o.alpha = float(alpha or 0.0)
+    o.beta = float(beta or 0.0)
+    o.mixed_kappa = float(mixed_kappa)
+    return o
+
+
+class PseudosymError(RuntimeError):
+    def __init__(self, code, info=None):
+        self.code = code
+        self.info = info
+        super().__init__(f"pseudosym status {code}: {STATUS.get(code, 'invalid argument')}")
+
+
+@dataclass
+class _HandleState:
+    handle: ctypes.c_void_p
+    workspace: object
+    ws_bytes: int
+
+
+_handles = {}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _handle(device, stream_ptr):
+    """One library handle per (device, stream), with a torch-owned workspace."""
+    key = (device, stream_ptr)
+    st = _handles.get(key)
+    if st is None:
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.ps_create(ctypes.byref(h), ctypes.c_void_p(stream_ptr))
+        if rc != 0:
+            raise PseudosymError(rc)
+        st = _HandleState(h, None, 0)
+        _handles[key] = st
+    return st
+
+
+def _prepare(A, B):
+    torch = _torch()
+    for t, name in ((A, "A"), (B, "B")):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name} must be a float64 tensor on a ROCm device")
+        if t.dim() != 2 or t.shape[0] != t.shape[1]:
+            raise ValueError(f"{name} must be square")
+    if A.shape != B.shape or A.device != B.device:
+        raise ValueError("A and B must have the same shape and device")
+    return A.contiguous(), B.contiguous()
+
+
+def _ensure_workspace(st, lib, m, opts, what, device):
+    torch = _torch()
+    need = int(lib.ps_workspace_size(int(m), ctypes.byref(opts), int(what)))
+    if st.ws_bytes < need:
+        st.workspace = torch.empty(need + 256, dtype=torch.uint8, device=device)
+        st.ws_bytes = need
+        base = st.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        rc = lib.ps_set_workspace(st.handle, ctypes.c_void_p(aligned), ctypes.c_size_t(need))
+        if rc != 0:
+            raise PseudosymError(rc)
+
+
+def _call_setup(A, B, opts, what):
+    torch = _torch()
+    lib = load()
+    A, B = _prepare(A, B)
+    m = A.shape[0]
+    dev = A.device
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        st = _handle(dev.index, stream.cuda_stream)
+        _ensure_workspace(st, lib, m, opts, what, dev)
+    return lib, st, A, B, m
+
+
+def sign(A, B, raise_on_error=True, **kw):
+    """Blocks (SA, SB) of sign(H), H = [[A, B], [-B, -A]].  Returns (SA, SB, info)."""
+    torch = _torch()
+    opts = make_opts(**kw)
+    lib, st, A, B, m = _call_setup(A, B, opts, 0)
+    SA = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    SB = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    info = PsInfo()
+    rc = lib.pseudosym_sign(st.handle, m, A.data_ptr(), m, B.data_ptr(), m, SA.data_ptr(),
+                            SB.data_ptr(), m, ctypes.byref(opts), ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    # the library writes column-major; SA, SB are symmetric up to rounding, return the
+    # column-major view so that entry (i, j) is the library's (i, j)
+    return SA.t(), SB.t(), info.as_dict() | {"rc": rc}
+
+
+def divide(A, B, raise_on_error=True, **kw):
+    """Q_+ (2m x m) and H_+ (m x m) of one spectral division step.  Returns (Qp, Hp, info)."""
+    torch = _torch()
+    opts = make_opts(**kw)
+    lib, st, A, B, m = _call_setup(A, B, opts, 1)
+    Qt = torch.empty((m, 2 * m), dtype=torch.float64, device=A.device)  # column-major 2m x m
+    Hp = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    info = PsInfo()
+    rc = lib.pseudosym_divide(st.handle, m, A.data_ptr(), m, B.data_ptr(), m, Qt.data_ptr(),
+                              2 * m, Hp.data_ptr(), m, ctypes.byref(opts), ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    return Qt.t(), Hp.t(), info.as_dict() | {"rc": rc}
+
+
+def eig(A, B, want_vectors=True, raise_on_error=True, **kw):
+    """Eigenvalues (2m) and, optionally, eigenvectors (2m x 2m) of H.  Returns (lam, V, info)."""
+    torch = _torch()
+    opts = make_opts(**kw)
+    lib, st, A, B, m = _call_setup(A, B, opts, 2)
+    lam = torch.empty(2 * m, dtype=torch.float64, device=A.device)
+    Vt = torch.empty((2 * m, 2 * m), dtype=torch.float64, device=A.device) if want_vectors else None
+    info = PsInfo()
+    rc = lib.pseudosym_eig(st.handle, m, A.data_ptr(), m, B.data_ptr(), m, lam.data_ptr(),
+                           Vt.data_ptr() if Vt is not None else None, 2 * m,
+                           ctypes.byref(opts), ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    return lam, (Vt.t() if Vt is not None else None), info.as_dict() | {"rc": rc}

@@ -1,0 +1,391 @@
+// Element-wise, copy and reduction kernels of the pseudosym pipeline (FP64).
+#include "ps_internal.h"
+
+namespace ps {
+
+namespace {
+constexpr int NT = 256;
+inline unsigned blocks_for(size_t n, int per = NT) {
+  size_t b = (n + per - 1) / per;
+  return (unsigned)(b > 65535u * 64u ? 65535u * 64u : b);
+}
+
+__device__ inline double warp_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// block-wide sum (NT threads); result valid in thread 0
+__device__ inline double block_sum(double v, double* sh) {
+  v = warp_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+}  // namespace
+
+// mk[0] = upper(A + B), mk[1] = upper(A - B); padded diagonal 1, strictly lower 0.
+__global__ void pack_casida_kernel(int m, int mp, const double* A, int lda, const double* B,
+                                   int ldb, double* mk) {
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    double sp = 0.0, sm = 0.0;
+    if (i <= j) {
+      if (j < m) {
+        const double a = A[i + (size_t)j * lda], b = B[i + (size_t)j * ldb];
+        sp = a + b;
+        sm = a - b;
+      } else if (i == j) {
+        sp = 1.0;
+        sm = 1.0;
+      }
+    }
+    mk[e] = sp;
+    mk[n + e] = sm;
+  }
+}
+
+void pack_casida(hipStream_t s, int m, int mp, const double* A, int lda, const double* B,
+                 int ldb, double* mk) {
+  hipLaunchKernelGGL(pack_casida_kernel, dim3(blocks_for((size_t)mp * mp)), dim3(NT), 0, s, m,
+                     mp, A, lda, B, ldb, mk);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void mask_pad_kernel(double* x, int m, int mp, long long stride) {
+  double* X = x + blockIdx.y * stride;
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    if (i >= m || j >= m) X[e] = 0.0;
+  }
+}
+
+void mask_pad(hipStream_t s, double* x, int m, int mp, long long stride, int batch) {
+  if (m == mp) return;
+  hipLaunchKernelGGL(mask_pad_kernel, dim3(blocks_for((size_t)mp * mp), batch), dim3(NT), 0, s,
+                     x, m, mp, stride);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void fill_kernel(double* x, size_t n, double v) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    x[e] = v;
+}
+
+void fill_zero(hipStream_t s, double* x, size_t n) {
+  if (!n) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, x, n, 0.0);
+  PS_HIP(hipGetLastError());
+}
+
+// 64 x 64 tiles through LDS
+__global__ void transpose_kernel(const double* x, double* y, int mp, long long stride) {
+  __shared__ double t[64][65];
+  const double* X = x + blockIdx.z * stride;
+  double* Y = y + blockIdx.z * stride;
+  const int bi = blockIdx.x * 64, bj = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int j = ty; j < 64; j += 4) t[j][tx] = X[(bi + tx) + (size_t)(bj + j) * mp];
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) Y[(bj + tx) + (size_t)(bi + i) * mp] = t[tx][i];
+}
+
+void transpose(hipStream_t s, const double* x, double* y, int mp, long long stride, int batch) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(mp / 64, mp / 64, batch), dim3(NT), 0, s, x, y, mp,
+                     stride);
+  PS_HIP(hipGetLastError());
+}
+
+// z[j] = upper(G) + shifts[j] I with strictly lower part zero (G holds its upper triangle)
+__global__ void form_shifts_kernel(const double* g, double* z, int mp, const double* shifts) {
+  const size_t n = (size_t)mp * mp;
+  const double c = shifts[blockIdx.y];
+  double* Z = z + blockIdx.y * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    Z[e] = (i < j) ? g[e] : ((i == j) ? g[e] + c : 0.0);
+  }
+}
+
+void form_shifts(hipStream_t s, const double* g, double* z, int mp, const double* shifts,
+                 int r) {
+  hipLaunchKernelGGL(form_shifts_kernel, dim3(blocks_for((size_t)mp * mp), r), dim3(NT), 0, s,
+                     g, z, mp, shifts);
+  PS_HIP(hipGetLastError());
+}
+
+struct ShiftList {
+  double c[kMaxSeg];
+};
+
+// same as form_shifts_kernel with the shifts passed by value (no host-device copy)
+__global__ void form_shifts_v_kernel(const double* g, double* z, int mp, ShiftList sl) {
+  const size_t n = (size_t)mp * mp;
+  const double c = sl.c[blockIdx.y];
+  double* Z = z + blockIdx.y * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    Z[e] = (i < j) ? g[e] : ((i == j) ? g[e] + c : 0.0);
+  }
+}
+
+void form_shifts_v(hipStream_t s, const double* g, double* z, int mp, const double* shifts_host,
+                   int r) {
+  ShiftList sl{};
+  for (int j = 0; j < r && j < kMaxSeg; ++j) sl.c[j] = shifts_host[j];
+  hipLaunchKernelGGL(form_shifts_v_kernel, dim3(blocks_for((size_t)mp * mp), r), dim3(NT), 0, s,
+                     g, z, mp, sl);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void fill_int_kernel(int* x, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = 0;
+}
+
+void fill_int_zero(hipStream_t s, int* x, int n) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + NT - 1) / NT), dim3(NT), 0, s, x, n);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void scale_copy_kernel(const double* x, double* y, double a, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    y[e] = a * x[e];
+}
+
+void scale_copy(hipStream_t s, const double* x, double* y, double a, size_t n) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, x, y, a, n);
+  PS_HIP(hipGetLastError());
+}
+
+// A_s = sym(S21 + S12)/2, B_s = sym(S21 - S12)/2 (the blocks of sign(H))
+__global__ void sign_blocks_kernel(const double* s12, const double* s21, double* as,
+                                   double* bs, int mp) {
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    const size_t et = j + (size_t)i * mp;
+    const double p = 0.5 * (s12[e] + s12[et]);
+    const double q = 0.5 * (s21[e] + s21[et]);
+    as[e] = 0.5 * (q + p);
+    bs[e] = 0.5 * (q - p);
+  }
+}
+
+void sign_blocks(hipStream_t s, const double* s12, const double* s21, double* as, double* bs,
+                 int mp) {
+  hipLaunchKernelGGL(sign_blocks_kernel, dim3(blocks_for((size_t)mp * mp)), dim3(NT), 0, s,
+                     s12, s21, as, bs, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// p11 = upper((I + A_s)/2), strictly lower zero (padded A_s is zero: padded diagonal 1/2)
+__global__ void half_shift_upper_kernel(const double* as, double* p11, int mp) {
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    p11[e] = (i < j) ? 0.5 * as[e] : ((i == j) ? 0.5 * (1.0 + as[e]) : 0.0);
+  }
+}
+
+void half_shift_upper(hipStream_t s, const double* as, double* p11, int mp) {
+  hipLaunchKernelGGL(half_shift_upper_kernel, dim3(blocks_for((size_t)mp * mp)), dim3(NT), 0, s,
+                     as, p11, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// top = C^T;  ab[0] = (top + qbot)/sqrt2, ab[1] = (top - qbot)/sqrt2
+__global__ void basis_mix_kernel(const double* c, const double* qbot, double* top_out,
+                                 double* ab, int mp) {
+  const size_t n = (size_t)mp * mp;
+  const double h = 0.70710678118654752440;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    const double tv = (i >= j) ? c[j + (size_t)i * mp] : 0.0;
+    const double bv = qbot[e];
+    top_out[e] = tv;
+    ab[e] = h * (tv + bv);
+    ab[n + e] = h * (tv - bv);
+  }
+}
+
+void basis_mix(hipStream_t s, const double* c, const double* qbot, double* top_out, double* ab,
+               int mp) {
+  hipLaunchKernelGGL(basis_mix_kernel, dim3(blocks_for((size_t)mp * mp)), dim3(NT), 0, s, c,
+                     qbot, top_out, ab, mp);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void copy_out_kernel(const double* x, int ldx, double* y, int ldy, int rows,
+                                int cols) {
+  const size_t n = (size_t)rows * cols;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    y[i + (size_t)j * ldy] = x[i + (size_t)j * ldx];
+  }
+}
+
+void copy_out(hipStream_t s, const double* x, int ldx, double* y, int ldy, int rows, int cols) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(copy_out_kernel, dim3(blocks_for((size_t)rows * cols)), dim3(NT), 0, s, x,
+                     ldx, y, ldy, rows, cols);
+  PS_HIP(hipGetLastError());
+}
+
+// out2[0] += ||x2 - x1||^2 partials, out2[1] += ||x2||^2 partials: two-pass (per-block
+// partials then a single-block sum) for a deterministic result.
+__global__ void diff_norm_partial_kernel(const double* x1, const double* x2, size_t n,
+                                         double* part) {
+  __shared__ double sh[NT / 64];
+  double d = 0.0, q = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double a = x1[e], b = x2[e];
+    d += (b - a) * (b - a);
+    q += b * b;
+  }
+  const double sd = block_sum(d, sh);
+  const double sq = block_sum(q, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd;
+    part[2 * blockIdx.x + 1] = sq;
+  }
+}
+
+__global__ void sum_pairs_kernel(const double* part, int nb, double* out2) {
+  __shared__ double sh[NT / 64];
+  double d = 0.0, q = 0.0;
+  for (int e = threadIdx.x; e < nb; e += blockDim.x) {
+    d += part[2 * e];
+    q += part[2 * e + 1];
+  }
+  const double sd = block_sum(d, sh);
+  const double sq = block_sum(q, sh);
+  if (threadIdx.x == 0) {
+    out2[0] = sd;
+    out2[1] = sq;
+  }
+}
+
+void diff_norms(hipStream_t s, const double* x1, const double* x2, size_t n, double* out2) {
+  // out2 must have room for 2 + 2*1024 doubles (partials after the two results)
+  const int nb = 1024;
+  hipLaunchKernelGGL(diff_norm_partial_kernel, dim3(nb), dim3(NT), 0, s, x1, x2, n, out2 + 2);
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(NT), 0, s, out2 + 2, nb, out2);
+  PS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ Golub-Kahan bidiagonalization
+// deterministic unit start vector per batch item (entries of the padding are zero)
+__global__ void gk_init_kernel(double* v, int m, int mp) {
+  __shared__ double sh[NT / 64];
+  double* V = v + blockIdx.x * (size_t)mp;
+  double q = 0.0;
+  for (int i = threadIdx.x; i < mp; i += blockDim.x) {
+    double x = 0.0;
+    if (i < m) {
+      unsigned h = (unsigned)i * 2654435761u + 0x9e3779b9u * (blockIdx.x + 1);
+      h ^= h >> 16;
+      h *= 0x85ebca6bu;
+      h ^= h >> 13;
+      x = 1.0 + (double)(h & 0xffff) / 65536.0;   // positive, well spread
+    }
+    V[i] = x;
+    q += x * x;
+  }
+  __shared__ double tot;
+  const double s = block_sum(q, sh);
+  if (threadIdx.x == 0) tot = s;
+  __syncthreads();
+  const double inv = 1.0 / sqrt(tot);
+  for (int i = threadIdx.x; i < mp; i += blockDim.x) V[i] *= inv;
+}
+
+void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned) {
+  hipLaunchKernelGGL(gk_init_kernel, dim3(batch), dim3(NT), 0, s, v, m, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// y_b[j] = sum_i M_b(i, j) x_b[i]: one wave per column
+__global__ void coldots_kernel(const double* mat, long long mstride, const double* x,
+                               long long xstride, double* y, long long ystride, int mp) {
+  const int b = blockIdx.y;
+  const int col = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= mp) return;
+  const double* Mc = mat + b * mstride + (size_t)col * mp;
+  const double* X = x + b * xstride;
+  double acc = 0.0;
+  for (int i = lane; i < mp; i += 64) acc += Mc[i] * X[i];
+  acc = warp_sum(acc);
+  if (lane == 0) y[b * ystride + col] = acc;
+}
+
+void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
+             long long xstride, double* y, long long ystride, int mp, int batch) {
+  hipLaunchKernelGGL(coldots_kernel, dim3((mp + 3) / 4, batch), dim3(NT), 0, s, mat, mstride, x,
+                     xstride, y, ystride, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// w = p - hist[prev] * wprev;  hist[out] = ||w||;  w /= ||w||   (one block per batch item)
+__global__ void gk_update_kernel(const double* p, long long pstride, double* w,
+                                 long long wstride, const double* wprev, long long wpstride,
+                                 double* hist, int hist_prev, int hist_out, int hist_ld, int m) {
+  __shared__ double sh[1024 / 64];
+  __shared__ double tot;
+  const int b = blockIdx.x;
+  const double* P = p + b * pstride;
+  double* Wv = w + b * wstride;
+  const double* Wp = wprev ? wprev + b * wpstride : nullptr;
+  double* Hs = hist + (size_t)b * hist_ld;
+  const double g = (Wp && hist_prev >= 0) ? Hs[hist_prev] : 0.0;
+  double q = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    double v = P[i];
+    if (Wp) v -= g * Wp[i];
+    Wv[i] = v;
+    q += v * v;
+  }
+  // block_sum for blockDim 1024
+  double v = warp_sum(q);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    tot = sqrt(r);
+    Hs[hist_out] = tot;
+  }
+  __syncthreads();
+  const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) Wv[i] *= inv;
+}
+
+void gk_update(hipStream_t s, const double* p, long long pstride, double* w, long long wstride,
+               const double* wprev, long long wpstride, double* hist, int hist_prev,
+               int hist_out, int hist_ld, int m, int batch) {
+  hipLaunchKernelGGL(gk_update_kernel, dim3(batch), dim3(1024), 0, s, p, pstride, w, wstride,
+                     wprev, wpstride, hist, hist_prev, hist_out, hist_ld, m);
+  PS_HIP(hipGetLastError());
+}
+
+}  // namespace ps

@@ -1,0 +1,592 @@
+// Host driver of the pseudosym pipeline and the C-ABI entry points.
+//
+// The Zolotarev iteration runs on the half-size core of H.  With
+//   M = A + B = R^T R,   K = A - B = L L^T  (L = R_K^T),   Y0 = R L,
+// Q_h = [[I, I], [I, -I]]/sqrt(2) gives Q_h H Q_h = [[0, K], [M, 0]], so the
+// eigenvalues of H are +-sigma(Y0), and every odd function f(x) = x h(x^2) of H is
+//   f(H) = Q_h [[0, R^{-1} f(Y0) L^T], [R^T f(Y0) L^{-1}, 0]] Q_h,  f(Y0) = Y0 h(Y0^T Y0).
+// Alg. 8 applied to H therefore equals the Zolotarev polar iteration applied to Y0,
+//   Y <- hat C (Y + sum_j a_j Y (Y^T Y + c_{2j-1} I)^{-1}),
+// whose shifted matrices are symmetric positive definite (SYRK, Cholesky and the
+// triangular inverse, all on matrix cores).  The blocks of sign(H) are assembled
+// from the polar factor U of Y0 as A_s = (S21 + S12)/2, B_s = (S21 - S12)/2 with
+// S12 = R^{-1} U L^T and S21 = R^T U L^{-1}; the bases follow Alg. 6 and the
+// decoupled block is H_+ = Q_+^T Sigma H Q_+ = (Q_h Q_+)^T diag(M, K) (Q_h Q_+).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/pseudosym.h"
+#include "ps_internal.h"
+
+namespace ps {
+void fill_int_zero(hipStream_t s, int* x, int n);
+void form_shifts_v(hipStream_t s, const double* g, double* z, int mp, const double* shifts_host,
+                   int r);
+}  // namespace ps
+
+struct ps_handle_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* own_ws = nullptr;
+  size_t own_bytes = 0;
+  void* user_ws = nullptr;
+  size_t user_bytes = 0;
+  double* pinned = nullptr;  // host staging for scalars
+  hipEvent_t ev[10] = {};
+  bool events = false;
+};
+
+namespace ps {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kPinned = 4096;  // doubles
+
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  bool dry = true;
+  template <class T>
+  T* take(size_t n) {
+    const size_t bytes = (n * sizeof(T) + kAlign - 1) / kAlign * kAlign;
+    T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+struct Buffers {
+  int m = 0, mp = 0, r = 0;
+  size_t S = 0;
+  double *mk, *wmk, *tmp, *y, *yt, *x0, *x1, *x2, *g, *z, *w, *nmat;
+  double *t1, *t2, *s12, *s21, *as, *bs, *p11, *wc, *qbot, *top, *ab, *F, *hp;
+  double *vv, *uu, *pp, *hist, *norms;
+  int* dinfo;
+};
+
+void carve(Arena& a, Buffers& b, int m, int r, int what) {
+  b.m = m;
+  b.mp = pad_to(m);
+  b.r = r;
+  const size_t S = (size_t)b.mp * b.mp;
+  b.S = S;
+  const int rr = std::max(r, 2);
+  b.mk = a.take<double>(2 * S);
+  b.wmk = a.take<double>(2 * S);
+  b.tmp = a.take<double>((size_t)rr * b.mp * kNb);
+  b.y = a.take<double>(2 * S);
+  b.yt = a.take<double>(2 * S);
+  b.x0 = a.take<double>(S);
+  b.x1 = a.take<double>(S);
+  b.x2 = a.take<double>(S);
+  b.g = a.take<double>(S);
+  b.z = a.take<double>((size_t)rr * S);
+  b.w = a.take<double>((size_t)rr * S);
+  b.nmat = a.take<double>(S);
+  b.t1 = a.take<double>(S);
+  b.t2 = a.take<double>(S);
+  b.s12 = a.take<double>(S);
+  b.s21 = a.take<double>(S);
+  b.as = a.take<double>(S);
+  b.bs = a.take<double>(S);
+  if (what >= 1) {
+    b.p11 = a.take<double>(S);
+    b.wc = a.take<double>(S);
+    b.qbot = a.take<double>(S);
+    b.top = a.take<double>(S);
+    b.ab = a.take<double>(2 * S);
+    b.F = a.take<double>(2 * S);
+    b.hp = a.take<double>(S);
+  } else {
+    b.p11 = b.wc = b.qbot = b.top = b.ab = b.F = b.hp = nullptr;
+  }
+  b.vv = a.take<double>(2 * (size_t)b.mp);
+  b.uu = a.take<double>(2 * (size_t)b.mp);
+  b.pp = a.take<double>(2 * (size_t)b.mp);
+  b.hist = a.take<double>(2 * 256);
+  b.norms = a.take<double>(2 + 2 * 1024 + 16);
+  b.dinfo = a.take<int>(16);
+}
+
+// r = 0: the smallest r for which the two steps map [l, 1] into [1 - 1e-15, 1] (the
+// criterion the paper takes from a table of its reference [NakF16]); workspace sizing
+// assumes the largest r.
+int auto_r(double ell) {
+  for (int r = 1; r < 8; ++r) {
+    ZoloHost c1, c2;
+    if (zolotarev_host(ell, r, &c1)) continue;
+    const double e1 = std::min(c1.ell_next, 1.0 - 1e-16);
+    if (zolotarev_host(e1, r, &c2)) continue;
+    if (1.0 - c2.ell_next <= 1e-15) return r;
+  }
+  return 8;
+}
+
+int resolve_r(const ps_opts& o) { return o.r <= 0 ? 8 : std::min(o.r, 8); }
+
+size_t workspace_bytes(int m, const ps_opts& o, int what) {
+  Arena a;
+  Buffers b;
+  carve(a, b, m, resolve_r(o), what);
+  return a.off + kAlign;
+}
+
+struct Timer {
+  ps_handle h;
+  bool on;
+  int n = 0;
+  int phase_of[10];
+  void mark(int phase) {
+    if (!on || n >= 10) return;
+    PS_HIP(hipEventRecord(h->ev[n], h->stream));
+    phase_of[n] = phase;
+    ++n;
+  }
+  void finish(double* ms) {
+    if (!on) return;
+    for (int i = 0; i < 8; ++i) ms[i] = 0.0;
+    for (int i = 1; i < n; ++i) {
+      float t = 0.f;
+      PS_HIP(hipEventElapsedTime(&t, h->ev[i - 1], h->ev[i]));
+      if (phase_of[i] >= 0 && phase_of[i] < 8) ms[phase_of[i]] += t;
+    }
+  }
+};
+
+// Golub-Kahan bidiagonalization of two matrices at once: M_0 = mats[0], M_1 = mats[S],
+// transposes in mats_t.  Returns sigma_max of each bidiagonal projection.
+void gk_estimate(hipStream_t s, Buffers& b, const double* mats, const double* mats_t, int steps,
+                 double* pinned, double smax[2]) {
+  const int mp = b.mp;
+  const long long S = (long long)b.S;
+  gk_init(s, b.vv, b.m, mp, 2, 0);
+  for (int k = 0; k < steps; ++k) {
+    // u_k = M v_k - beta_{k-1} u_{k-1}   (M x = column dots of M^T)
+    coldots(s, mats_t, S, b.vv, mp, b.pp, mp, mp, 2);
+    gk_update(s, b.pp, mp, b.uu, mp, k > 0 ? b.uu : nullptr, mp, b.hist, 2 * k - 1, 2 * k, 256,
+              mp, 2);
+    // v_{k+1} = M^T u_k - alpha_k v_k
+    coldots(s, mats, S, b.uu, mp, b.pp, mp, mp, 2);
+    gk_update(s, b.pp, mp, b.vv, mp, b.vv, mp, b.hist, 2 * k, 2 * k + 1, 256, mp, 2);
+  }
+  PS_HIP(hipMemcpyAsync(pinned, b.hist, 2 * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < 2; ++q) {
+    double d[128], e[128];
+    for (int k = 0; k < steps; ++k) {
+      d[k] = pinned[q * 256 + 2 * k];
+      e[k] = pinned[q * 256 + 2 * k + 1];
+    }
+    double smn;
+    bidiag_extreme_sv(d, e, steps, &smax[q], &smn);
+  }
+}
+
+// One Zolotarev step on the core: xn = hat C x (I + sum_j a_j (x^T x + c_{2j-1} I)^{-1})
+void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const ZoloHost& co,
+                   int* dinfo_slot) {
+  const int mp = b.mp, r = co.r;
+  const long long S = (long long)b.S;
+  gemm_f64(s, gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
+                           kOutUpper));
+  double shifts[8];
+  for (int j = 0; j < r; ++j) shifts[j] = co.c[2 * j];
+  form_shifts_v(s, b.g, b.z, mp, shifts, r);
+  potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, r, dinfo_slot);
+  GemmProblem pn = gemm_problem(mp, mp, r * mp, b.w, mp, 0, b.w, mp, 1, b.nmat, mp, 1.0, 0.0,
+                                nullptr, 0, kAUpper | kBLower | kOutUpper | kMirror);
+  pn.kseg = mp;
+  pn.nseg = r;
+  for (int j = 0; j < r; ++j) pn.kscale[j] = co.a[j];
+  gemm_f64(s, pn);
+  gemm_f64(s, gemm_problem(mp, mp, mp, x, mp, 0, b.nmat, mp, 0, xn, mp, co.chat, co.chat, x, mp,
+                           0));
+}
+
+// alpha, beta for the core matrix: sigma_max(Y) and 1/sigma_max(Y^{-1}) by Golub-Kahan.
+void estimate_bounds(hipStream_t s, Buffers& b, const double* ymats, int steps, double* pinned,
+                     double* alpha, double* beta, double est[2]) {
+  transpose(s, ymats, b.yt, b.mp, (long long)b.S, 2);
+  double smax[2];
+  gk_estimate(s, b, ymats, b.yt, steps, pinned, smax);
+  est[0] = smax[0];
+  est[1] = smax[1] > 0 ? 1.0 / smax[1] : 0.0;
+  *alpha = 1.01 * smax[0];
+  *beta = 0.99 / smax[1];
+}
+
+int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
+        int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what) {
+  hipStream_t s = h->stream;
+  const int r = resolve_r(o);
+  // workspace
+  const size_t need = workspace_bytes(m, o, what);
+  char* base;
+  if (h->user_ws) {
+    if (h->user_bytes < need) return PS_NO_WORKSPACE;
+    base = (char*)h->user_ws;
+  } else {
+    if (h->own_bytes < need) {
+      if (h->own_ws) PS_HIP(hipFree(h->own_ws));
+      h->own_ws = nullptr;
+      h->own_bytes = 0;
+      PS_HIP(hipMalloc(&h->own_ws, need));
+      h->own_bytes = need;
+    }
+    base = (char*)h->own_ws;
+  }
+  base = (char*)(((uintptr_t)base + kAlign - 1) / kAlign * kAlign);
+  Arena ar;
+  ar.base = base;
+  ar.dry = false;
+  Buffers b;
+  carve(ar, b, m, r, what);
+  const int mp = b.mp;
+  const long long S = (long long)b.S;
+  double* pin = h->pinned;
+
+  ps_info inf{};
+  inf.failed_step = -1;
+  inf.r = r;
+  Timer tm{h, o.timing != 0};
+  tm.mark(-1);
+
+  fill_int_zero(s, b.dinfo, 16);
+  // ---- setup: M = A + B = R_M^T R_M, K = A - B = R_K^T R_K, Y0 = R_M R_K^T, Y0^{-1} = W_K^T W_M
+  pack_casida(s, m, mp, A, lda, B, ldb, b.mk);
+  potrf_inv_f64(s, b.mk, S, b.wmk, S, b.tmp, mp, 2, b.dinfo + 0);
+  {
+    GemmProblem pg[2];
+    pg[0] = gemm_problem(mp, mp, mp, b.mk, mp, 0, b.mk + S, mp, 1, b.y, mp, 1.0, 0.0, nullptr, 0,
+                         kAUpper | kBLower);
+    pg[1] = gemm_problem(mp, mp, mp, b.wmk + S, mp, 1, b.wmk, mp, 0, b.y + S, mp, 1.0, 0.0,
+                         nullptr, 0, kALower | kBUpper);
+    gemm_f64(s, pg, 2);
+  }
+  mask_pad(s, b.y, m, mp, S, 2);
+  tm.mark(0);
+
+  // ---- parameter estimation (Alg. 8 step 1)
+  double alpha = o.alpha, beta = o.beta;
+  inf.sigma_est[0] = inf.sigma_est[1] = 0.0;
+  if (!(alpha > 0.0) || !(beta > 0.0)) {
+    double a_est, b_est;
+    estimate_bounds(s, b, b.y, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a_est, &b_est,
+                    inf.sigma_est);
+    if (!(alpha > 0.0)) alpha = a_est;
+    if (!(beta > 0.0)) beta = b_est;
+  }
+  // a failed setup Cholesky shows up as non-finite estimates; check the flag now
+  PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  if (((int*)pin)[0] != 0) {
+    inf.status = PS_NOT_DEFINITE;
+    inf.failed_step = 0;
+    inf.failed_mask = ((int*)pin)[0];
+    if (info) *info = inf;
+    return PS_NOT_DEFINITE;
+  }
+  inf.alpha = alpha;
+  inf.beta = beta;
+  tm.mark(1);
+
+  // ---- Zolotarev steps with the stopping test of Alg. 8
+  scale_copy(s, b.y, b.x0, 1.0 / alpha, b.S);
+
+  double ell = std::min(beta / alpha, 1.0 - 1e-15);
+  const int r_run = (o.r <= 0) ? auto_r(ell) : r;
+  inf.r = r_run;
+  const double tol = std::pow(std::ldexp(1.0, -53), 1.0 / (2 * r_run + 1));
+  int status = PS_OK;
+  const double* xin = b.x0;
+  int attempt = 0;
+  int ell_slot = 0;
+  for (;; ++attempt) {
+    ZoloHost c1, c2;
+    if (zolotarev_host(ell, r_run, &c1)) return PS_HIP_ERROR;
+    double ell1 = std::min(c1.ell_next, 1.0 - 1e-15);
+    if (zolotarev_host(ell1, r_run, &c2)) return PS_HIP_ERROR;
+    if (ell_slot < 4) inf.ell[ell_slot++] = ell;
+    if (ell_slot < 4) inf.ell[ell_slot++] = ell1;
+    zolo_step_f64(s, b, xin, b.x1, c1, b.dinfo + 1);
+    tm.mark(2);
+    if (o.max_steps == 1) {
+      inf.steps += 1;
+      std::swap(b.x1, b.x2);  // the sign assembly reads x2
+      break;
+    }
+    zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
+    tm.mark(3);
+    inf.steps += 2;
+    diff_norms(s, b.x1, b.x2, b.S, b.norms);
+    PS_HIP(hipMemcpyAsync(pin, b.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipStreamSynchronize(s));
+    const int* di = (const int*)(pin + 8);
+    if (di[1] || di[2]) {
+      status = PS_SHIFT_BREAKDOWN;
+      inf.failed_step = di[1] ? 1 : 2;
+      inf.failed_mask = di[1] ? di[1] : di[2];
+      break;
+    }
+    const double change = std::sqrt(pin[0]) / std::sqrt(pin[1]);
+    inf.step_change = change;
+    if (change <= tol) break;
+    if (attempt >= o.max_restarts) {
+      status = PS_NOT_CONVERGED;
+      break;
+    }
+    // restart from X2: new bounds from Golub-Kahan on X2 and on chol(X2^T X2)^{-1}
+    inf.restarts += 1;
+    {
+      gemm_f64(s, gemm_problem(mp, mp, mp, b.x2, mp, 1, b.x2, mp, 0, b.g, mp, 1.0, 0.0, nullptr,
+                               0, kOutUpper));
+      double one = 0.0;
+      form_shifts_v(s, b.g, b.z, mp, &one, 1);
+      potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, 1, b.dinfo + 3);
+      // estimator pair: y = [X2, W_G]
+      PS_HIP(hipMemcpyAsync(b.y, b.x2, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PS_HIP(hipMemcpyAsync(b.y + S, b.w, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
+      double est[2], a2, b2;
+      estimate_bounds(s, b, b.y, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a2, &b2,
+                      est);
+      // sigma_max(W_G) = 1 / sigma_min(X2)
+      scale_copy(s, b.x2, b.x0, 1.0 / a2, b.S);
+      xin = b.x0;
+      ell = std::min(b2 / a2, 1.0 - 1e-15);
+    }
+  }
+  if (status != PS_OK) {
+    inf.status = status;
+    tm.finish(inf.phase_ms);
+    if (info) *info = inf;
+    return status;
+  }
+
+  // ---- blocks of sign(H):  S12 = W_M U R_K,  S21 = R_M^T U W_K^T
+  const double* U = b.x2;
+  {
+    GemmProblem pg[2];
+    pg[0] = gemm_problem(mp, mp, mp, U, mp, 0, b.mk + S, mp, 0, b.t1, mp, 1.0, 0.0, nullptr, 0,
+                         kBUpper);
+    pg[1] = gemm_problem(mp, mp, mp, U, mp, 0, b.wmk + S, mp, 1, b.t2, mp, 1.0, 0.0, nullptr, 0,
+                         kBLower);
+    gemm_f64(s, pg, 2);
+    pg[0] = gemm_problem(mp, mp, mp, b.wmk, mp, 0, b.t1, mp, 0, b.s12, mp, 1.0, 0.0, nullptr, 0,
+                         kAUpper);
+    pg[1] = gemm_problem(mp, mp, mp, b.mk, mp, 1, b.t2, mp, 0, b.s21, mp, 1.0, 0.0, nullptr, 0,
+                         kALower);
+    gemm_f64(s, pg, 2);
+    sign_blocks(s, b.s12, b.s21, b.as, b.bs, mp);
+  }
+  tm.mark(5);
+
+  if (what == 0) {
+    copy_out(s, b.as, mp, out1, ld1, m, m);
+    copy_out(s, b.bs, mp, out2, ld2, m, m);
+  } else {
+    // ---- Alg. 6: C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
+    half_shift_upper(s, b.as, b.p11, mp);
+    potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4);
+    gemm_f64(s, gemm_problem(mp, mp, mp, b.bs, mp, 0, b.wc, mp, 0, b.qbot, mp, -0.5, 0.0, nullptr,
+                             0, kBUpper));
+    mask_pad(s, b.qbot, m, mp, S, 1);
+    basis_mix(s, b.p11, b.qbot, b.top, b.ab, mp);
+    mask_pad(s, b.ab, m, mp, S, 2);
+    tm.mark(6);
+    // ---- decoupling: H_+ = (R_M a)^T (R_M a) + (R_K b)^T (R_K b)
+    {
+      GemmProblem pf = gemm_problem(mp, mp, mp, b.mk, mp, 0, b.ab, mp, 0, b.F, 2 * mp, 1.0, 0.0,
+                                    nullptr, 0, kAUpper);
+      pf.nb1 = 2;
+      pf.sA[0] = S;
+      pf.sB[0] = S;
+      pf.sC[0] = mp;
+      pf.sD[0] = mp;
+      gemm_f64(s, pf);
+      gemm_f64(s, gemm_problem(mp, mp, 2 * mp, b.F, 2 * mp, 1, b.F, 2 * mp, 0, b.hp, mp, 1.0, 0.0,
+                               nullptr, 0, kOutUpper | kMirror));
+    }
+    tm.mark(7);
+    copy_out(s, b.top, mp, out1, ld1, m, m);
+    copy_out(s, b.qbot, mp, out1 + m, ld1, m, m);
+    copy_out(s, b.hp, mp, out2, ld2, m, m);
+  }
+  PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  const int* di = (const int*)(pin + 8);
+  if (what >= 1 && di[4]) {
+    inf.status = PS_BASIS_BREAKDOWN;
+    inf.failed_step = 4;
+    inf.failed_mask = di[4];
+    if (info) *info = inf;
+    return PS_BASIS_BREAKDOWN;
+  }
+  tm.finish(inf.phase_ms);
+  inf.status = PS_OK;
+  if (info) *info = inf;
+  return PS_OK;
+}
+
+int check_common(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                 const ps_opts* o) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!B) return -5;
+  if (ldb < m) return -6;
+  if (o && (o->r < 0 || o->r > 8 || o->max_restarts < 0 || o->max_steps < 0 ||
+            o->max_steps > 1 || o->precision != PS_PREC_FP64))
+    return -11;
+  return 0;
+}
+
+template <class F>
+int guarded(ps_handle h, F&& f) {
+  try {
+    int dev = 0;
+    PS_HIP(hipGetDevice(&dev));
+    if (dev != h->device) PS_HIP(hipSetDevice(h->device));
+    return f();
+  } catch (const HipError&) {
+    return PS_HIP_ERROR;
+  } catch (...) {
+    return PS_HIP_ERROR;
+  }
+}
+
+}  // namespace
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" {
+
+void ps_opts_default(ps_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = PS_PREC_FP64;
+  o->r = 8;
+  o->max_restarts = 2;
+  o->max_steps = 0;
+  o->lanczos_steps = 20;
+  o->timing = 0;
+  o->alpha = 0.0;
+  o->beta = 0.0;
+  o->mixed_kappa = 20.0;
+}
+
+int ps_create(ps_handle* h, void* stream) {
+  if (!h) return -1;
+  ps_handle_s* p = new ps_handle_s();
+  p->stream = (hipStream_t)stream;
+  if (hipGetDevice(&p->device) != hipSuccess ||
+      hipHostMalloc((void**)&p->pinned, kPinned * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess) {
+    delete p;
+    return PS_HIP_ERROR;
+  }
+  for (auto& e : p->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete p;
+      return PS_HIP_ERROR;
+    }
+  p->events = true;
+  *h = p;
+  return PS_OK;
+}
+
+int ps_destroy(ps_handle h) {
+  if (!h) return -1;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  if (h->own_ws) (void)hipFree(h->own_ws);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->events)
+    for (auto& e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+  return PS_OK;
+}
+
+int ps_set_stream(ps_handle h, void* stream) {
+  if (!h) return -1;
+  h->stream = (hipStream_t)stream;
+  return PS_OK;
+}
+
+size_t ps_workspace_size(int m, const ps_opts* o, int what) {
+  ps_opts d;
+  ps_opts_default(&d);
+  if (m < 1) return 0;
+  return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : (what > 2 ? 2 : what));
+}
+
+int ps_set_workspace(ps_handle h, void* dptr, size_t bytes) {
+  if (!h) return -1;
+  if (dptr && ((uintptr_t)dptr % kAlign)) return -2;
+  h->user_ws = dptr;
+  h->user_bytes = dptr ? bytes : 0;
+  return PS_OK;
+}
+
+int ps_zolotarev_coeffs(double ell, int r, double* c, double* a, double* chat, double* ell_next) {
+  ZoloHost z;
+  if (zolotarev_host(ell, r, &z)) return -1;
+  if (c)
+    for (int i = 0; i < 2 * r; ++i) c[i] = z.c[i];
+  if (a)
+    for (int j = 0; j < r; ++j) a[j] = z.a[j];
+  if (chat) *chat = z.chat;
+  if (ell_next) *ell_next = z.ell_next;
+  return 0;
+}
+
+int pseudosym_sign(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                   double* SA, double* SB, int lds, const ps_opts* opts, ps_info* info) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (!SA) return -7;
+  if (!SB) return -8;
+  if (lds < m) return -9;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  return guarded(h, [&] { return run(h, m, A, lda, B, ldb, SA, lds, SB, lds, o, info, 0); });
+}
+
+int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                     double* Qp, int ldq, double* Hp, int ldh, const ps_opts* opts,
+                     ps_info* info) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (!Qp) return -7;
+  if (ldq < 2 * m) return -8;
+  if (!Hp) return -9;
+  if (ldh < m) return -10;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  return guarded(h, [&] { return run(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, info, 1); });
+}
+
+const char* ps_status_string(int st) {
+  switch (st) {
+    case PS_OK: return "ok";
+    case PS_NOT_DEFINITE: return "not definite: A+B or A-B is not positive definite";
+    case PS_SHIFT_BREAKDOWN: return "Cholesky of a shifted Gram matrix failed";
+    case PS_NOT_CONVERGED: return "stopping test failed after the allowed restarts";
+    case PS_HIP_ERROR: return "HIP runtime error";
+    case PS_NO_WORKSPACE: return "workspace too small";
+    case PS_BASIS_BREAKDOWN: return "Cholesky of the leading block of P_+ failed";
+    default: return st < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal declarations of the pseudosym HIP library (not part of the C-ABI).
+//
+// Storage convention inside the library: every m x m operand is held in a padded
+// column-major buffer of size mp x mp (mp = m rounded up to a multiple of 64,
+// leading dimension mp).  Padding rows/columns are kept block-diagonal with the
+// real part (zeros off the diagonal block, and a positive constant on the padded
+// diagonal of matrices that get factorized), so that no kernel needs bounds checks
+// and the padded block never mixes into the real block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "zolo_host.h"
+
+namespace ps {
+
+constexpr int kTile = 64;   // padding granule and GEMM tile edge
+constexpr int kNb = 64;     // Cholesky diagonal block size
+constexpr int kMaxSeg = 16; // K segments with separate scale (shift terms of one step)
+constexpr int kMaxGroup = 4;
+
+inline int pad_to(int m, int g = kTile) { return (m + g - 1) / g * g; }
+
+struct HipError {
+  hipError_t code;
+  const char* where;
+};
+
+#define PS_HIP(call)                                                  \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) throw ::ps::HipError{e_, #call};            \
+  } while (0)
+
+// ----------------------------------------------------------------- FP64 GEMM
+// D = alpha * op(A) op(B) + beta * C  for a grouped, two-level batched set of
+// problems.  op(X) = X (t = 0) or X^T (t = 1); all matrices column-major.
+enum GemmFlags : int {
+  kOutUpper = 1,   // compute tiles I <= J only, store entries i <= j only
+  kOutLower = 2,   // compute tiles I >= J only, store entries i >= j only
+  kMirror = 4,     // also store D(j,i) = D(i,j) for the stored off-diagonal entries
+  kAUpper = 8,     // op(A)(i,k) = 0 for k < i  (within each K segment)
+  kALower = 16,    // op(A)(i,k) = 0 for k > i
+  kBUpper = 32,    // op(B)(k,j) = 0 for k > j
+  kBLower = 64,    // op(B)(k,j) = 0 for k < j
+};
+
+struct GemmProblem {
+  const double* A;
+  const double* B;
+  const double* C;
+  double* D;
+  long long sA[2], sB[2], sC[2], sD[2];  // strides of the two batch indices
+  int M, N, K;
+  int lda, ldb, ldc, ldd;
+  int tA, tB, flags;
+  int nb1, nb2;     // batch extents (batch index z = z1 + nb1 * z2)
+  int kseg, nseg;   // K = nseg * kseg; segment s scales op(A) by kscale[s]
+  double alpha, beta;
+  double kscale[kMaxSeg];
+  // filled by the launcher
+  int tm, tn, tiles_per_batch, tile_begin;
+};
+
+GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
+                         const double* B, int ldb, int tB, double* D, int ldd,
+                         double alpha = 1.0, double beta = 0.0, const double* C = nullptr,
+                         int ldc = 0, int flags = 0);
+
+// Launch up to kMaxGroup independent problems in one kernel.
+void gemm_f64(hipStream_t s, const GemmProblem* probs, int count);
+inline void gemm_f64(hipStream_t s, const GemmProblem& p) { gemm_f64(s, &p, 1); }
+
+// ----------------------------------------------------------------- Cholesky
+// In-place upper Cholesky Z = R^T R of `batch` SPD matrices (mp x mp, ld = mp,
+// matrix stride sz) with the strictly lower part zero on entry, producing the
+// inverse factor W = R^{-1} (upper) in `w` (stride sw).  `tmp` holds
+// batch * mp * kNb doubles.  A non-positive pivot in matrix b sets bit min(b, 30) of
+// the device int *info.
+void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
+                   double* tmp, int mp, int batch, int* info);
+
+// ----------------------------------------------------------------- elementwise
+void pack_casida(hipStream_t s, int m, int mp, const double* A, int lda, const double* B,
+                 int ldb, double* mk);  // mk[0] = upper(A+B), mk[1] = upper(A-B), pad diag 1
+void mask_pad(hipStream_t s, double* x, int m, int mp, long long stride, int batch);
+void fill_zero(hipStream_t s, double* x, size_t n);
+void transpose(hipStream_t s, const double* x, double* y, int mp, long long stride, int batch);
+void form_shifts(hipStream_t s, const double* g, double* z, int mp, const double* shifts,
+                 int r);   // z[j] = upper(G) + shifts[j] I, strictly lower zero
+void scale_copy(hipStream_t s, const double* x, double* y, double a, size_t n);
+void sign_blocks(hipStream_t s, const double* s12, const double* s21, double* as,
+                 double* bs, int mp);   // A_s = sym(S21+S12)/2, B_s = sym(S21-S12)/2
+void half_shift_upper(hipStream_t s, const double* as, double* p11, int mp);  // (I+A_s)/2
+void basis_mix(hipStream_t s, const double* c, const double* qbot, double* top_out,
+               double* ab, int mp);     // Q_top = C^T, a=(Q_top+Q_bot)/sqrt2, b=(..-..)/sqrt2
+void copy_out(hipStream_t s, const double* x, int ldx, double* y, int ldy, int rows,
+              int cols);
+void diff_norms(hipStream_t s, const double* x1, const double* x2, size_t n, double* out2);
+
+// Golub-Kahan bidiagonalization (batch of two matrices M_b with transposes Mt_b).
+void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned seed);
+void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
+             long long xstride, double* y, long long ystride, int mp, int batch);
+void gk_update(hipStream_t s, const double* p, long long pstride, double* w,
+               long long wstride, const double* wprev, long long wpstride,
+               double* hist, int hist_prev, int hist_out, int hist_ld, int m, int batch);
+
+}  // namespace ps

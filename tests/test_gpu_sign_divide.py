@@ -1,0 +1,203 @@
+"""GPU parity of pseudosym_sign / pseudosym_divide (FP64 mode) against the oracle.
+
+Every case runs the HIP library through its C-ABI (ctypes binding) and the
+oracle on the same seeded inputs.  With the same alpha and beta both sides run the
+same rational iteration (Alg. 8), the GPU on the half-size SPD core and the oracle
+with LDL^T solves on the full H, so the iterates, sign(H), the Alg. 6 basis
+(unique: its top block is lower triangular with positive diagonal) and H_+ are
+compared element by element.  FP64 tolerances: 1e-12 relative (Frobenius) for
+sign(H) and its iterate, 1e-11 for Q_+ and H_+ (the basis passes through one more
+Cholesky factorization), 1e-10 relative eigenvalue error.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bases as bs
+from oracle import divide as dv
+from oracle import eig as eg
+from oracle import sign as sg
+from paper_2203_08900_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(x, y):
+    ny = np.linalg.norm(y)
+    return np.linalg.norm(x - y) / (ny if ny > 0 else 1.0)
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def bounds(a, b):
+    m = a.shape[0]
+    amax, amin = sg.abs_eig_bounds(sg.casida_matrix(a, b), sg.casida_sigma(m))
+    return 1.01 * amax, 0.99 * amin
+
+
+CASES = [(1, 2, "dense"), (17, 5, "dense"), (64, 0, "dense"), (100, 1, "dense"),
+         (130, 7, "casida"), (200, 3, "dense")]
+
+
+def make(m, seed, kind):
+    return inputs.small_dense(m, seed) if kind == "dense" else inputs.casida_like(m, seed, rank=16)
+
+
+@pytest.mark.parametrize("m,seed,kind", CASES)
+def test_sign_parity(m, seed, kind):
+    print(f"[sign parity] m={m} seed={seed} kind={kind}", flush=True)
+    a, b = make(m, seed, kind)
+    al, be = bounds(a, b)
+    ref = dv.divide_casida(a, b, alpha=al, beta=be)
+    SA, SB, info = api.sign(dev(a), dev(b), alpha=al, beta=be)
+    s = ref["S"]
+    assert info["status"] == 0 and info["steps"] == 2 and info["restarts"] == 0
+    assert rel(SA.cpu().numpy(), s[:m, :m]) < 1e-12
+    assert np.abs(SB.cpu().numpy() - s[:m, m:]).max() < 1e-12 * np.abs(s).max()
+
+
+@pytest.mark.parametrize("m,seed,kind", CASES[1:4])
+def test_first_iterate_parity(m, seed, kind):
+    """X_1 = hat Z(H / alpha; l) of Alg. 8, returned in H-form with max_steps = 1."""
+    print(f"[iterate parity] m={m} seed={seed}", flush=True)
+    a, b = make(m, seed, kind)
+    al, be = bounds(a, b)
+    h = sg.casida_matrix(a, b)
+    _, rec = sg.zolo_pd(h, sg.casida_sigma(m), r=8, alpha=al, beta=be, keep_iterates=True)
+    x1 = rec.iterates[0]
+    SA, SB, info = api.sign(dev(a), dev(b), alpha=al, beta=be, max_steps=1)
+    assert info["steps"] == 1
+    assert rel(SA.cpu().numpy(), x1[:m, :m]) < 1e-12
+    assert np.abs(SB.cpu().numpy() - x1[:m, m:]).max() < 1e-12 * np.abs(x1).max()
+
+
+@pytest.mark.parametrize("m,seed,kind", CASES)
+def test_divide_parity(m, seed, kind):
+    print(f"[divide parity] m={m} seed={seed} kind={kind}", flush=True)
+    a, b = make(m, seed, kind)
+    al, be = bounds(a, b)
+    ref = dv.divide_casida(a, b, alpha=al, beta=be)
+    Qp, Hp, info = api.divide(dev(a), dev(b), alpha=al, beta=be)
+    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+    assert info["status"] == 0
+    assert rel(Qp, ref["Q_plus"]) < 1e-11
+    assert rel(Hp, ref["H_plus"]) < 1e-11
+    # invariants that hold for any valid result
+    sigma = sg.casida_sigma(m)
+    assert np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max() < 1e-12
+    assert np.abs(np.triu(Qp[:m], 1)).max() == 0.0 and np.all(np.diag(Qp[:m]) > 0)
+    lam, _ = eg.eig_casida(a, b)
+    w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
+    assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-12
+    pi = np.block([[np.zeros((m, m)), np.eye(m)], [np.eye(m), np.zeros((m, m))]])
+    _, _, bwd = dv.decouple(ref["H"], sigma, Qp, pi @ Qp)
+    assert bwd < 1e-13                      # the paper's backward error
+
+
+@pytest.mark.parametrize("m,seed", [(64, 0), (200, 3)])
+def test_estimator_bounds(m, seed):
+    """Golub-Kahan estimates bracket the spectrum (Alg. 8 needs alpha >~ max|lambda|,
+    beta <~ min|lambda|) and the result matches the definition of sign(H)."""
+    a, b = inputs.small_dense(m, seed)
+    h = sg.casida_matrix(a, b)
+    sigma = sg.casida_sigma(m)
+    amax, amin = sg.abs_eig_bounds(h, sigma)
+    SA, SB, info = api.sign(dev(a), dev(b))
+    assert amax <= info["alpha"] <= 1.05 * amax
+    assert 0.9 * amin <= info["beta"] <= amin
+    s = sg.sign_definition(h, sigma)
+    assert rel(SA.cpu().numpy(), s[:m, :m]) < 1e-12
+
+
+def test_auto_r():
+    a, b = inputs.small_dense(64, 0)
+    al, be = bounds(a, b)
+    SA, SB, info = api.sign(dev(a), dev(b), alpha=al, beta=be, r=0)
+    assert 1 <= info["r"] < 8
+    s = sg.sign_definition(sg.casida_matrix(a, b), sg.casida_sigma(64))
+    assert rel(SA.cpu().numpy(), s[:64, :64]) < 1e-12
+
+
+def test_commuting_blocks_closed_form():
+    m = 70
+    rng = np.random.default_rng(4)
+    q = inputs.haar(rng, m)
+    alv = rng.uniform(1.0, 4.0, m)
+    bev = alv * rng.uniform(-0.9, 0.9, m)
+    a = (q * alv) @ q.T
+    b = (q * bev) @ q.T
+    a, b = 0.5 * (a + a.T), 0.5 * (b + b.T)
+    lam = np.sqrt(alv ** 2 - bev ** 2)
+    SA, SB, info = api.sign(dev(a), dev(b))
+    assert rel(SA.cpu().numpy(), (q * (alv / lam)) @ q.T) < 1e-12
+    assert rel(SB.cpu().numpy(), (q * (bev / lam)) @ q.T) < 1e-12
+
+
+def test_b_zero():
+    a, _ = inputs.small_dense(40, 9)
+    b = np.zeros_like(a)
+    SA, SB, _ = api.sign(dev(a), dev(b))
+    assert np.abs(SA.cpu().numpy() - np.eye(40)).max() < 1e-13
+    assert np.abs(SB.cpu().numpy()).max() < 1e-13
+    Qp, Hp, _ = api.divide(dev(a), dev(b))
+    Qp = Qp.cpu().numpy()
+    assert np.abs(Qp[:40] - np.eye(40)).max() < 1e-13 and np.abs(Qp[40:]).max() < 1e-13
+    assert rel(Hp.cpu().numpy(), a) < 1e-13
+
+
+def test_not_definite_is_reported():
+    a, _ = inputs.small_dense(32, 2)
+    b = 1.5 * a                   # A - B = -A/2 is negative definite
+    with pytest.raises(np.linalg.LinAlgError):
+        sg.abs_eig_bounds(sg.casida_matrix(a, b), sg.casida_sigma(32))   # oracle agrees
+    SA, SB, info = api.sign(dev(a), dev(b), raise_on_error=False)
+    assert info["rc"] == 1 and info["failed_step"] == 0 and info["failed_mask"] == 2
+
+
+def test_restart_path():
+    """An overestimated beta leaves small singular values outside [l, 1]; the stopping
+    test of Alg. 8 restarts from X2 and still reaches sign(H)."""
+    a, b = inputs.small_dense(48, 5)
+    h = sg.casida_matrix(a, b)
+    sigma = sg.casida_sigma(48)
+    amax, amin = sg.abs_eig_bounds(h, sigma)
+    SA, SB, info = api.sign(dev(a), dev(b), alpha=amax, beta=0.9 * amax, r=2)
+    assert info["restarts"] >= 1 and info["status"] == 0
+    s = sg.sign_definition(h, sigma)
+    assert rel(SA.cpu().numpy(), s[:48, :48]) < 1e-11
+
+
+def test_bad_arguments():
+    a, b = inputs.small_dense(8, 1)
+    with pytest.raises(api.PseudosymError):
+        api.sign(dev(a), dev(b), r=9)
+
+
+@pytest.mark.timeout(400)
+def test_full_size_casida_n4096():
+    """m = 2048 (n = 4096), the benchmark workload, estimated alpha/beta: eigenvalues
+    of H_+ against the definition (simultaneous diagonalization of Sigma H and
+    Sigma), Sigma-orthonormality of Q_+, and sampled columns of Q_+ against the
+    projector P_+ = (I + S)/2 built from the GPU's own sign(H)."""
+    m = 2048
+    a, b = inputs.casida_like(m, 1)
+    print("[full size] m=2048 divide", flush=True)
+    Qp, Hp, info = api.divide(dev(a), dev(b))
+    assert info["status"] == 0 and info["restarts"] == 0
+    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+    sigma = sg.casida_sigma(m)
+    assert np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max() < 1e-11
+    w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
+    lam, _ = eg.eig_casida(a, b)
+    assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-10
+    SA, SB, _ = api.sign(dev(a), dev(b))
+    SA, SB = SA.cpu().numpy(), SB.cpu().numpy()
+    s = np.block([[SA, SB], [-SB, -SA]])
+    cols = np.random.default_rng(0).choice(m, 16, replace=False)
+    pq = 0.5 * (Qp[:, cols] + s @ Qp[:, cols])
+    assert np.abs(pq - Qp[:, cols]).max() < 1e-10
+    e = np.eye(2 * m)[:, cols]
+    assert np.abs(s @ (s @ e) - e).max() < 1e-10
