@@ -1,18 +1,23 @@
 // FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
 //
-// One workgroup of 4 waves computes a 64 x 64 tile of D = alpha op(A) op(B) + beta C;
-// each wave owns a 32 x 32 quadrant as 2 x 2 MFMA 16x16 fragments.  K advances in
-// steps of 16 through two LDS buffers (one barrier per step): the next step's
-// global loads are issued into registers before the MFMAs of the current step.
+// A workgroup of 4 waves computes a BM x BN tile of D = alpha op(A) op(B) + beta C;
+// each wave owns a (BM/2) x (BN/2) quadrant as MFMA 16x16 fragments.  Two tile shapes:
+// 128 x 128 (16 fragments per wave, 16 flops per byte loaded) for large problems and
+// 64 x 64 for small ones.  K advances in steps of 16 through two LDS buffers (one
+// barrier per step); the next step's global loads are issued before the MFMAs of
+// the current step.
 //
-// LDS layouts are chosen per operand so that global loads are coalesced along the
-// contiguous dimension and the fragment reads hit distinct banks:
-//   op(A) = A   : [k][i], stride 64+16 doubles   (A read down columns)
-//   op(A) = A^T : [i][k], stride 16+1  doubles   (A read along columns = op rows)
-//   op(B) = B   : [j][k], stride 16+1
-//   op(B) = B^T : [k][j], stride 64+16
-// Structure flags restrict the K loop of each tile to the non-zero band of
-// triangular operands and restrict/mirror the stored output for symmetric results.
+// LDS layouts per operand keep global loads coalesced along the contiguous
+// dimension and fragment reads on distinct banks:
+//   op(A) = A   : [k][i], stride BM+16       op(A) = A^T : [i][k], stride 16+1
+//   op(B) = B   : [j][k], stride 16+1        op(B) = B^T : [k][j], stride BN+16
+// Structure flags restrict each tile's K loop to the non-zero band of triangular
+// operands and restrict / mirror the stored output of symmetric results.  Split-K
+// writes per-split partial tiles that a second kernel sums in a fixed order.
+//
+// MFMA f64 16x16x4 register layout (checked on the device): A operand lane l holds
+// A(l%16, l/16), B operand lane l holds B(l/16, l%16), accumulator element v of
+// lane l is D(4v + l/16, l%16).
 #include "ps_internal.h"
 
 namespace ps {
@@ -21,20 +26,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct GemmGroup {
   int count;
+  int remap;   // nonzero: spread consecutive tiles over one XCD (8 XCDs, round-robin dispatch)
+  int total;
   GemmProblem p[kMaxGroup];
 };
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, WM = 2, WN = 2;
-constexpr int NT = WM * WN * 64;
-constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
-constexpr int LDKM = BM + 16;   // [k][i] stride
-constexpr int LDIK = BK + 1;    // [i][k] stride
-constexpr int ASZ = (BK * LDKM > BM * LDIK) ? BK * LDKM : BM * LDIK;
-constexpr int BSZ = (BK * (BN + 16) > BN * LDIK) ? BK * (BN + 16) : BN * LDIK;
-constexpr int APT = BM * BK / NT;
-constexpr int BPT = BN * BK / NT;
+constexpr int BK = 16;
+constexpr int NT = 256;
+constexpr int LDIK = BK + 1;
 
 __device__ inline void tri_index(int t, int& hi, int& lo) {
   // t enumerates pairs (lo <= hi) row by row of hi: t = hi*(hi+1)/2 + lo
@@ -47,18 +48,35 @@ __device__ inline void tri_index(int t, int& hi, int& lo) {
 
 }  // namespace
 
+template <int BM, int BN>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
+  constexpr int WM = 2, WN = 2;
+  constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
+  constexpr int LDKM = BM + 16;
+  constexpr int LDKN = BN + 16;
+  constexpr int ASZ = (BK * LDKM > BM * LDIK) ? BK * LDKM : BM * LDIK;
+  constexpr int BSZ = (BK * LDKN > BN * LDIK) ? BK * LDKN : BN * LDIK;
+  constexpr int APT = BM * BK / NT;
+  constexpr int BPT = BN * BK / NT;
   __shared__ double As[2][ASZ];
   __shared__ double Bs[2][BSZ];
 
-  const int bid = blockIdx.x;
+  int bid = blockIdx.x;
+  if (g.remap) {
+    // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
+    // contiguous range of logical tiles [x * total/8, (x+1) * total/8).
+    const int per = g.total >> 3;
+    bid = (bid & 7) * per + (bid >> 3);
+  }
   int pi = 0;
   while (pi + 1 < g.count && bid >= g.p[pi + 1].tile_begin) ++pi;
   const GemmProblem& P = g.p[pi];
 
   const int local = bid - P.tile_begin;
   const int z = local / P.tiles_per_batch;
-  const int t = local - z * P.tiles_per_batch;
+  const int tz = local - z * P.tiles_per_batch;
+  const int ks = tz / P.tiles;          // split index
+  const int t = tz - ks * P.tiles;
   int I, J;
   if (P.flags & kOutUpper) {
     tri_index(t, J, I);
@@ -86,7 +104,9 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
   kb = kb / BK * BK;
   ke = min(segK, (ke + BK - 1) / BK * BK);
   const int per = ke > kb ? (ke - kb) / BK : 0;
-  const int nkt = per * nseg;
+  const int nkt_all = per * nseg;
+  const int kt_begin = (int)((long long)nkt_all * ks / P.ksplit);
+  const int kt_end = (int)((long long)nkt_all * (ks + 1) / P.ksplit);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -150,18 +170,18 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
         Bs[buf][j * LDIK + k] = rb[p];
       } else {
         const int j = idx % BN, k = idx / BN;
-        Bs[buf][k * (BN + 16) + j] = rb[p];
+        Bs[buf][k * LDKN + j] = rb[p];
       }
     }
   };
 
-  if (nkt > 0) {
-    load(0);
+  if (kt_end > kt_begin) {
+    load(kt_begin);
     store(0);
     __syncthreads();
-    for (int kt = 0; kt < nkt; ++kt) {
-      const int buf = kt & 1;
-      if (kt + 1 < nkt) load(kt + 1);
+    for (int kt = kt_begin; kt < kt_end; ++kt) {
+      const int buf = (kt - kt_begin) & 1;
+      if (kt + 1 < kt_end) load(kt + 1);
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
         const int k = kk * 4 + lk;
@@ -174,7 +194,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
           const int j = wn * FN * 16 + b * 16 + li;
-          bv[b] = !tB ? Bs[buf][j * LDIK + k] : Bs[buf][k * (BN + 16) + j];
+          bv[b] = !tB ? Bs[buf][j * LDIK + k] : Bs[buf][k * LDKN + j];
         }
 #pragma unroll
         for (int a = 0; a < FM; ++a)
@@ -182,12 +202,28 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
           for (int b = 0; b < FN; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
-      if (kt + 1 < nkt) store(buf ^ 1);
+      if (kt + 1 < kt_end) store(buf ^ 1);
       __syncthreads();
     }
   }
 
   const double alpha = P.alpha, beta = P.beta;
+  if (P.ksplit > 1) {
+    // partial tile of split ks (batch extent is 1 for split problems)
+    double* W = P.ws + (long long)ks * P.M * P.N;
+    const long long M = P.M;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + wm * FM * 16 + a * 16 + lk + 4 * v;
+          const int j = j0 + wn * FN * 16 + b * 16 + li;
+          W[i + j * M] = alpha * acc[a][b][v];
+        }
+    return;
+  }
   const long long ldc = P.ldc, ldd = P.ldd;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
@@ -204,6 +240,24 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
         D[i + j * ldd] = val;
         if ((flags & kMirror) && i != j) D[j + i * ldd] = val;
       }
+}
+
+// D = sum_s partial_s + beta C with the triangle / mirror conventions of the GEMM
+__global__ void gemm_split_reduce_kernel(GemmProblem P) {
+  const long long M = P.M, N = P.N;
+  const long long n = M * N;
+  const long long MN = M * N;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % M), j = (int)(e / M);
+    if ((P.flags & kOutUpper) && i > j) continue;
+    if ((P.flags & kOutLower) && i < j) continue;
+    double val = 0.0;
+    for (int s = 0; s < P.ksplit; ++s) val += P.ws[s * MN + e];
+    if (P.beta != 0.0) val += P.beta * P.C[i + (long long)j * P.ldc];
+    P.D[i + (long long)j * P.ldd] = val;
+    if ((P.flags & kMirror) && i != j) P.D[j + (long long)i * P.ldd] = val;
+  }
 }
 
 GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
@@ -228,33 +282,72 @@ GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
   p.nb2 = 1;
   p.kseg = 0;
   p.nseg = 1;
+  p.ksplit = 1;
   p.alpha = alpha;
   p.beta = beta;
+  p.ws = nullptr;
   return p;
 }
 
-void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) {
+namespace {
+template <int BM, int BN>
+void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
   GemmGroup g{};
   int total = 0;
   for (int q = 0; q < count; ++q) {
     GemmProblem p = probs[q];
     if (p.M <= 0 || p.N <= 0 || p.nb1 <= 0 || p.nb2 <= 0) continue;
-    if (p.M % BM || p.N % BN || p.K % BK || (p.kseg > 0 && p.kseg % BK))
-      throw HipError{hipErrorInvalidValue, "gemm_f64: dimensions must be multiples of the tile"};
-    if ((p.flags & (kOutUpper | kOutLower)) && p.M != p.N)
-      throw HipError{hipErrorInvalidValue, "gemm_f64: triangular output needs M == N"};
-    if (p.kseg > 0 && (p.nseg < 1 || p.nseg > kMaxSeg || p.kseg * p.nseg != p.K))
-      throw HipError{hipErrorInvalidValue, "gemm_f64: bad K segmentation"};
     p.tm = p.M / BM;
     p.tn = p.N / BN;
-    p.tiles_per_batch = (p.flags & (kOutUpper | kOutLower)) ? p.tm * (p.tm + 1) / 2 : p.tm * p.tn;
+    p.tiles = (p.flags & (kOutUpper | kOutLower)) ? p.tm * (p.tm + 1) / 2 : p.tm * p.tn;
+    p.tiles_per_batch = p.tiles * p.ksplit;
     p.tile_begin = total;
     total += p.tiles_per_batch * p.nb1 * p.nb2;
     g.p[g.count++] = p;
   }
   if (total == 0) return;
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3(total), dim3(NT), 0, s, g);
+  g.total = total;
+  g.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), dim3(total), dim3(NT), 0, s, g);
   PS_HIP(hipGetLastError());
+  for (int q = 0; q < g.count; ++q) {
+    const GemmProblem& p = g.p[q];
+    if (p.ksplit > 1) {
+      const long long n = (long long)p.M * p.N;
+      const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 8192);
+      hipLaunchKernelGGL(gemm_split_reduce_kernel, dim3(nb), dim3(256), 0, s, p);
+      PS_HIP(hipGetLastError());
+    }
+  }
+}
+}  // namespace
+
+void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) {
+  bool big = true;
+  long long tiles128 = 0;
+  int live = 0;
+  for (int q = 0; q < count; ++q) {
+    const GemmProblem& p = probs[q];
+    if (p.M <= 0 || p.N <= 0 || p.nb1 <= 0 || p.nb2 <= 0) continue;
+    ++live;
+    if (p.M % 64 || p.N % 64 || p.K % BK || (p.kseg > 0 && p.kseg % BK))
+      throw HipError{hipErrorInvalidValue, "gemm_f64: dimensions must be multiples of the tile"};
+    if ((p.flags & (kOutUpper | kOutLower)) && p.M != p.N)
+      throw HipError{hipErrorInvalidValue, "gemm_f64: triangular output needs M == N"};
+    if (p.kseg > 0 && (p.nseg < 1 || p.nseg > kMaxSeg || p.kseg * p.nseg != p.K))
+      throw HipError{hipErrorInvalidValue, "gemm_f64: bad K segmentation"};
+    if (p.ksplit < 1 || (p.ksplit > 1 && (p.nb1 * p.nb2 != 1 || !p.ws)))
+      throw HipError{hipErrorInvalidValue, "gemm_f64: bad split-K setup"};
+    if (p.M % 128 || p.N % 128 || std::min(p.M, p.N) < 512) big = false;
+    const long long tm = p.M / 128, tn = p.N / 128;
+    tiles128 += ((p.flags & (kOutUpper | kOutLower)) ? tm * (tm + 1) / 2 : tm * tn) *
+                p.ksplit * p.nb1 * p.nb2;
+  }
+  if (!live) return;
+  if (big && tiles128 >= 128)
+    launch_group<128, 128>(s, probs, count);
+  else
+    launch_group<64, 64>(s, probs, count);
 }
 
 }  // namespace ps

@@ -88,6 +88,42 @@ void fill_zero(hipStream_t s, double* x, size_t n) {
   PS_HIP(hipGetLastError());
 }
 
+__global__ void zero_lower_kernel(double* x, int mp, long long stride) {
+  double* X = x + blockIdx.y * stride;
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    if (i > j) X[e] = 0.0;
+  }
+}
+
+void zero_lower(hipStream_t s, double* x, int mp, long long stride, int batch) {
+  hipLaunchKernelGGL(zero_lower_kernel, dim3(blocks_for((size_t)mp * mp), batch), dim3(NT), 0, s,
+                     x, mp, stride);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void zero_block_kernel(double* x, int rows, int cols, int ld, int nb1, long long s1,
+                                  long long s2) {
+  const int b = blockIdx.y;
+  double* X = x + (b % nb1) * s1 + (b / nb1) * s2;
+  const size_t n = (size_t)rows * cols;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    X[i + (size_t)j * ld] = 0.0;
+  }
+}
+
+void zero_block(hipStream_t s, double* x, int rows, int cols, int ld, int nb1, long long s1,
+                int nb2, long long s2) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(zero_block_kernel, dim3(blocks_for((size_t)rows * cols), nb1 * nb2), dim3(NT),
+                     0, s, x, rows, cols, ld, nb1, s1, s2);
+  PS_HIP(hipGetLastError());
+}
+
 // 64 x 64 tiles through LDS
 __global__ void transpose_kernel(const double* x, double* y, int mp, long long stride) {
   __shared__ double t[64][65];

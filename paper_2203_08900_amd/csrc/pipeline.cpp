@@ -66,8 +66,28 @@ struct Buffers {
   double *mk, *wmk, *tmp, *y, *yt, *x0, *x1, *x2, *g, *z, *w, *nmat;
   double *t1, *t2, *s12, *s21, *as, *bs, *p11, *wc, *qbot, *top, *ab, *F, *hp;
   double *vv, *uu, *pp, *hist, *norms;
+  double* splitws;   // kMaxSplit partial products of split-K GEMMs
   int* dinfo;
 };
+
+constexpr int kMaxSplit = 8;
+
+// Choose a split-K factor so that a launch has at least ~2 workgroups per CU.
+void auto_split(GemmProblem& p, double* ws, int maxsplit = kMaxSplit) {
+  const bool big = p.M % 128 == 0 && p.N % 128 == 0 && std::min(p.M, p.N) >= 512;
+  const int T = big ? 128 : 64;
+  long long tiles = (p.flags & (kOutUpper | kOutLower)) ? (long long)(p.M / T) * (p.M / T + 1) / 2
+                                                        : (long long)(p.M / T) * (p.N / T);
+  tiles *= (long long)p.nb1 * p.nb2;
+  if (p.nb1 * p.nb2 != 1 || tiles >= 512) return;
+  int want = (int)((512 + tiles - 1) / tiles);
+  want = std::min(want, maxsplit);
+  while (want > 1 && p.K / 16 / want < 8) --want;
+  if (want > 1) {
+    p.ksplit = want;
+    p.ws = ws;
+  }
+}
 
 void carve(Arena& a, Buffers& b, int m, int r, int what) {
   b.m = m;
@@ -110,6 +130,7 @@ void carve(Arena& a, Buffers& b, int m, int r, int what) {
   b.pp = a.take<double>(2 * (size_t)b.mp);
   b.hist = a.take<double>(2 * 256);
   b.norms = a.take<double>(2 + 2 * 1024 + 16);
+  b.splitws = a.take<double>((size_t)kMaxSplit * S);
   b.dinfo = a.take<int>(16);
 }
 
@@ -192,8 +213,12 @@ void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const
                    int* dinfo_slot) {
   const int mp = b.mp, r = co.r;
   const long long S = (long long)b.S;
-  gemm_f64(s, gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
-                           kOutUpper));
+  {
+    GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
+                                  kOutUpper);
+    auto_split(pg, b.splitws);
+    gemm_f64(s, pg);
+  }
   double shifts[8];
   for (int j = 0; j < r; ++j) shifts[j] = co.c[2 * j];
   form_shifts_v(s, b.g, b.z, mp, shifts, r);
@@ -203,9 +228,15 @@ void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const
   pn.kseg = mp;
   pn.nseg = r;
   for (int j = 0; j < r; ++j) pn.kscale[j] = co.a[j];
+  if (r > 1 && r <= kMaxSplit) {   // one partial per shift term, summed by the reduction
+    pn.ksplit = r;
+    pn.ws = b.splitws;
+  }
   gemm_f64(s, pn);
-  gemm_f64(s, gemm_problem(mp, mp, mp, x, mp, 0, b.nmat, mp, 0, xn, mp, co.chat, co.chat, x, mp,
-                           0));
+  GemmProblem px = gemm_problem(mp, mp, mp, x, mp, 0, b.nmat, mp, 0, xn, mp, co.chat, co.chat, x,
+                                mp, 0);
+  auto_split(px, b.splitws);
+  gemm_f64(s, px);
 }
 
 // alpha, beta for the core matrix: sigma_max(Y) and 1/sigma_max(Y^{-1}) by Golub-Kahan.
@@ -344,8 +375,10 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     // restart from X2: new bounds from Golub-Kahan on X2 and on chol(X2^T X2)^{-1}
     inf.restarts += 1;
     {
-      gemm_f64(s, gemm_problem(mp, mp, mp, b.x2, mp, 1, b.x2, mp, 0, b.g, mp, 1.0, 0.0, nullptr,
-                               0, kOutUpper));
+      GemmProblem pg = gemm_problem(mp, mp, mp, b.x2, mp, 1, b.x2, mp, 0, b.g, mp, 1.0, 0.0,
+                                    nullptr, 0, kOutUpper);
+      auto_split(pg, b.splitws);
+      gemm_f64(s, pg);
       double one = 0.0;
       form_shifts_v(s, b.g, b.z, mp, &one, 1);
       potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, 1, b.dinfo + 3);
@@ -393,8 +426,12 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     // ---- Alg. 6: C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
     half_shift_upper(s, b.as, b.p11, mp);
     potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4);
-    gemm_f64(s, gemm_problem(mp, mp, mp, b.bs, mp, 0, b.wc, mp, 0, b.qbot, mp, -0.5, 0.0, nullptr,
-                             0, kBUpper));
+    {
+      GemmProblem pq = gemm_problem(mp, mp, mp, b.bs, mp, 0, b.wc, mp, 0, b.qbot, mp, -0.5, 0.0,
+                                    nullptr, 0, kBUpper);
+      auto_split(pq, b.splitws);
+      gemm_f64(s, pq);
+    }
     mask_pad(s, b.qbot, m, mp, S, 1);
     basis_mix(s, b.p11, b.qbot, b.top, b.ab, mp);
     mask_pad(s, b.ab, m, mp, S, 2);
@@ -409,8 +446,10 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
       pf.sC[0] = mp;
       pf.sD[0] = mp;
       gemm_f64(s, pf);
-      gemm_f64(s, gemm_problem(mp, mp, 2 * mp, b.F, 2 * mp, 1, b.F, 2 * mp, 0, b.hp, mp, 1.0, 0.0,
-                               nullptr, 0, kOutUpper | kMirror));
+      GemmProblem ph = gemm_problem(mp, mp, 2 * mp, b.F, 2 * mp, 1, b.F, 2 * mp, 0, b.hp, mp, 1.0,
+                                    0.0, nullptr, 0, kOutUpper | kMirror);
+      auto_split(ph, b.splitws);
+      gemm_f64(s, ph);
     }
     tm.mark(7);
     copy_out(s, b.top, mp, out1, ld1, m, m);

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -60,10 +61,12 @@ struct GemmProblem {
   int tA, tB, flags;
   int nb1, nb2;     // batch extents (batch index z = z1 + nb1 * z2)
   int kseg, nseg;   // K = nseg * kseg; segment s scales op(A) by kscale[s]
+  int ksplit;       // > 1: split the K loop; partial products go to ws, then a reduction
   double alpha, beta;
   double kscale[kMaxSeg];
+  double* ws;       // ksplit * M * N doubles per batch entry (only when ksplit > 1)
   // filled by the launcher
-  int tm, tn, tiles_per_batch, tile_begin;
+  int tm, tn, tiles, tiles_per_batch, tile_begin;
 };
 
 GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
@@ -71,7 +74,9 @@ GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
                          double alpha = 1.0, double beta = 0.0, const double* C = nullptr,
                          int ldc = 0, int flags = 0);
 
-// Launch up to kMaxGroup independent problems in one kernel.
+// Launch up to kMaxGroup independent problems in one kernel.  Problems with
+// ksplit > 1 are followed by a reduction launch (sum of partials, beta C, triangle
+// and mirror handling); their batch extent must be 1.
 void gemm_f64(hipStream_t s, const GemmProblem* probs, int count);
 inline void gemm_f64(hipStream_t s, const GemmProblem& p) { gemm_f64(s, &p, 1); }
 
@@ -89,6 +94,10 @@ void pack_casida(hipStream_t s, int m, int mp, const double* A, int lda, const d
                  int ldb, double* mk);  // mk[0] = upper(A+B), mk[1] = upper(A-B), pad diag 1
 void mask_pad(hipStream_t s, double* x, int m, int mp, long long stride, int batch);
 void fill_zero(hipStream_t s, double* x, size_t n);
+void zero_lower(hipStream_t s, double* x, int mp, long long stride, int batch);
+// zero `rows x cols` blocks (leading dimension ld) at x + b1*s1 + b2*s2
+void zero_block(hipStream_t s, double* x, int rows, int cols, int ld, int nb1, long long s1,
+                int nb2, long long s2);
 void transpose(hipStream_t s, const double* x, double* y, int mp, long long stride, int batch);
 void form_shifts(hipStream_t s, const double* g, double* z, int mp, const double* shifts,
                  int r);   // z[j] = upper(G) + shifts[j] I, strictly lower zero

@@ -39,7 +39,7 @@ def bounds(a, b):
 
 
 CASES = [(1, 2, "dense"), (17, 5, "dense"), (64, 0, "dense"), (100, 1, "dense"),
-         (130, 7, "casida"), (200, 3, "dense")]
+         (130, 7, "casida"), (200, 3, "dense"), (300, 11, "dense"), (420, 12, "casida")]
 
 
 def make(m, seed, kind):
