@@ -70,11 +70,19 @@ typedef struct {
                        /* and return that iterate in place of sign(H) (the blocks */
                        /* of X_1 = hat Z(H/alpha)); only honoured by pseudosym_sign */
   int lanczos_steps;   /* Golub-Kahan steps of the alpha/beta estimator (>= 4)   */
-  int timing;          /* nonzero: fill info->phase_ms with per-phase GPU times  */
+  int timing;          /* 1: fill info->phase_ms with per-phase GPU times;        */
+                       /* 2: also time every launch of the large-tile FP64 GEMM  */
+                       /*    kernel (info->gemm_*)                               */
   double alpha;        /* > 0: caller's upper bound of max|lambda(H)| (skips the  */
   double beta;         /* estimator); > 0: caller's lower bound of min|lambda(H)| */
   double mixed_kappa;  /* mixed precision: shifts whose condition number          */
                        /* (1 + c)/(l^2 + c) exceeds this run in FP64               */
+  int step2_series;    /* nonzero: when step 1 has left every singular value of the */
+                       /* iterate within [l_1, 1] with (1 - l_1^2)^P < 1e-17 for    */
+                       /* P <= 4, evaluate the second step's sum                    */
+                       /* sum_j a_j (X^T X + c_{2j-1} I)^{-1} as the convergent     */
+                       /* series in Delta = X^T X - I instead of r factorizations   */
+                       /* (the same rational function to below 1e-17)               */
 } ps_opts;
 
 typedef struct {
@@ -91,10 +99,15 @@ typedef struct {
   double sigma_est[2];     /* estimator output: sigma_max(Y0), 1/sigma_max(Y0^{-1}) */
   double phase_ms[8];      /* setup, estimate, step1, step2, refine, assemble,      */
                            /* bases, decouple (when opts->timing)                    */
+  int step2_terms;         /* 0: second step by factorizations; P > 0: series terms */
+  int gemm_launches;       /* timing == 2: launches of the large-tile FP64 GEMM kernel */
+  double gemm_ms;          /*   their summed GPU time                                 */
+  double gemm_flops;       /*   their algorithmic flops (zero blocks of triangular    */
+                           /*   operands and the unstored triangle not counted)      */
 } ps_info;
 
 /* Fill *o with the defaults: FP64, r = 8, 2 restarts, full method, 20 Lanczos
- * steps, no timing, estimated alpha/beta, mixed_kappa = 20. */
+ * steps, no timing, estimated alpha/beta, mixed_kappa = 20, step2_series = 1. */
 void ps_opts_default(ps_opts* o);
 
 /* Create a handle bound to `stream` (a hipStream_t, NULL = default stream) on

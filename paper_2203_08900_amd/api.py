@@ -39,6 +39,7 @@ class PsOpts(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("beta", ctypes.c_double),
         ("mixed_kappa", ctypes.c_double),
+        ("step2_series", ctypes.c_int),
     ]
 
 
@@ -57,6 +58,10 @@ class PsInfo(ctypes.Structure):
         ("step_change", ctypes.c_double),
         ("sigma_est", ctypes.c_double * 2),
         ("phase_ms", ctypes.c_double * 8),
+        ("step2_terms", ctypes.c_int),
+        ("gemm_launches", ctypes.c_int),
+        ("gemm_ms", ctypes.c_double),
+        ("gemm_flops", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -66,7 +71,9 @@ class PsInfo(ctypes.Structure):
             "failed_step": self.failed_step, "failed_mask": self.failed_mask,
             "alpha": self.alpha, "beta": self.beta, "ell": list(self.ell),
             "step_change": self.step_change, "sigma_est": list(self.sigma_est),
-            "phase_ms": list(self.phase_ms),
+            "phase_ms": list(self.phase_ms), "step2_terms": self.step2_terms,
+            "gemm_launches": self.gemm_launches, "gemm_ms": self.gemm_ms,
+            "gemm_flops": self.gemm_flops,
         }
 
 
@@ -136,7 +143,8 @@ def zolotarev_coeffs(ell: float, r: int):
 
 
 def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=20,
-              timing=False, alpha=0.0, beta=0.0, mixed_kappa=20.0) -> PsOpts:
+              timing=False, alpha=0.0, beta=0.0, mixed_kappa=20.0,
+              step2_series=True) -> PsOpts:
     lib = load()
     o = PsOpts()
     lib.ps_opts_default(ctypes.byref(o))
@@ -146,10 +154,11 @@ def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=
     o.max_restarts = int(max_restarts)
     o.max_steps = int(max_steps)
     o.lanczos_steps = int(lanczos_steps)
-    o.timing = 1 if timing else 0
+    o.timing = int(timing) if not isinstance(timing, bool) else (1 if timing else 0)
     o.alpha = float(alpha or 0.0)
     o.beta = float(beta or 0.0)
     o.mixed_kappa = float(mixed_kappa)
+    o.step2_series = 1 if step2_series else 0
     return o
 
 

@@ -18,24 +18,78 @@ constexpr int NTD = 256;
 }
 
 // Factor and invert one 64 x 64 diagonal block per workgroup.  Thread (bi, bj) of a
-// 16 x 16 grid owns the 4 x 4 register block rows 4bi.., columns 4bj.. (only blocks
-// with bi <= bj carry data).  Elimination is right-looking and unscaled: at pivot k
-// the owners of row k publish u(k, :) to LDS (double-buffered), one barrier, then
-// every thread applies u(i, j) -= u(k, i) u(k, j) / u(k, k) to its rows i > k.
-// R(i, j) = u(i, j) / sqrt(u(i, i)).  The inverse W = R^{-1} runs the same rank-1
-// pattern from the bottom row up: W(l, :) /= R(l, l), then W(i, :) -= R(i, l) W(l, :)
-// for i < l, with column l of R and row l of W read from LDS.
+// 16 x 16 grid owns the 4 x 4 register block rows 4bi.., columns 4bj.. (blocks with
+// bi <= bj carry data).  Factorization, blocked by 4 pivots (kb = 0..15):
+//   1. thread (kb, kb) factors its block D = R_d^T R_d and inverts R_d, in registers;
+//   2. threads (kb, bj > kb) form the panel R(kb, bj) = R_d^{-T} U(kb, bj);
+//   3. every thread with kb < bi <= bj applies U(bi, bj) -= R(kb, bi)^T R(kb, bj).
+// The inverse W = R^{-1} is built bottom-up by block rows: W(lb, :) = R_d(lb)^{-1} B(lb, :)
+// followed by B(bi, :) -= R(bi, lb) W(lb, :) for bi < lb, with B initialized to I.
+// Two barriers per 4 pivots in the factorization, one per 4 rows in the inverse.
+namespace {
+// 1/sqrt(x) and 1/x from the hardware approximations, each refined by two Newton
+// steps (y <- y (3 - x y^2)/2 and y <- y (2 - x y)), which brings the approximations
+// to full double precision; x > 0 is checked by the caller.
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+__device__ inline void chol4(double d[4][4], double w[4][4], bool& bad) {
+  // upper Cholesky of the 4 x 4 block d (upper triangle used) and w = R_d^{-1}
+  double rinv[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const double piv = d[p][p];
+    if (!(piv > 0.0)) bad = true;
+    const double ri = piv > 0.0 ? rsqrt_nr(piv) : 0.0;
+    rinv[p] = ri;
+    d[p][p] = piv * ri;
+#pragma unroll
+    for (int y = p + 1; y < 4; ++y) d[p][y] *= ri;
+#pragma unroll
+    for (int x = p + 1; x < 4; ++x)
+#pragma unroll
+      for (int y = x; y < 4; ++y) d[x][y] -= d[p][x] * d[p][y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < x; ++y) d[x][y] = 0.0;
+  // w = R_d^{-1}: columns by back substitution with the reciprocal diagonal
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+#pragma unroll
+    for (int x = 3; x >= 0; --x) {
+      double acc = (x == y) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = x + 1; q < 4; ++q) acc -= d[x][q] * w[q][y];
+      w[x][y] = (x <= y) ? acc * rinv[x] : 0.0;
+    }
+  }
+}
+}  // namespace
+
 __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz, double* w,
                                                          long long sw, int ld, int k0,
                                                          int* info) {
-  __shared__ double prow[2][NB];
-  __shared__ double rfull[NB][NB + 1];   // R, filled after the factorization
-  __shared__ double dgs[NB];
+  __shared__ double panel[4][NB];        // R(kb, :) of the current block row
+  __shared__ double wd[NB / 4][4][4];    // R_d^{-1} of every diagonal block
+  __shared__ double rfull[NB][NB + 1];   // R after the factorization
+  __shared__ double wrow[2][4][NB];      // published block row of W
   const int b = blockIdx.x;
   double* Z = z + b * sz + k0 + (long long)k0 * ld;
   double* W = w + b * sw + k0 + (long long)k0 * ld;
   const int tid = threadIdx.x;
-  const int bi = tid & 15, bj = tid >> 4;          // block row, block column
+  const int bi = tid & 15, bj = tid >> 4;
   const int r0 = 4 * bi, c0 = 4 * bj;
   const bool active = bi <= bj;
   double v[4][4];
@@ -46,99 +100,128 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
       const int i = r0 + x, j = c0 + y;
       v[x][y] = (active && i <= j) ? Z[i + (long long)j * ld] : 0.0;
     }
-  // publish row 0
-  if (bi == 0)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) prow[0][c0 + y] = v[0][y];
-  __syncthreads();
   bool bad = false;
-  for (int k = 0; k < NB; ++k) {
-    const int cur = k & 1;
-    const double piv = prow[cur][k];
-    if (!(piv > 0.0)) bad = true;
-    const double inv = (piv > 0.0) ? 1.0 / piv : 0.0;
-    if (active && r0 + 3 > k) {
-      double ui[4], uj[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) ui[x] = prow[cur][r0 + x] * inv;
-#pragma unroll
-      for (int y = 0; y < 4; ++y) uj[y] = prow[cur][c0 + y];
+  for (int kb = 0; kb < NB / 4; ++kb) {
+    // 1. diagonal block
+    if (bi == kb && bj == kb) {
+      double wl[4][4];
+      chol4(v, wl, bad);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
-          if (r0 + x > k && r0 + x <= c0 + y) v[x][y] -= ui[x] * uj[y];
-    }
-    // owners of row k+1 publish it (already updated by this step)
-    if (k + 1 < NB && active && (k + 1) / 4 == bi) {
-      const int x = (k + 1) & 3;
-#pragma unroll
-      for (int xx = 0; xx < 4; ++xx)
-        if (xx == x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) prow[cur ^ 1][c0 + y] = v[xx][y];
+        for (int y = 0; y < 4; ++y) wd[kb][x][y] = wl[x][y];
     }
     __syncthreads();
-  }
-  if (bad && tid == 0) atomicOr(info, 1 << (b < 30 ? b : 30));
-
-  // diagonal: u(i, i) sits in the diagonal blocks
-  if (bi == bj)
+    // 2. panel blocks of block row kb (the panel buffer is free: every reader of the
+    // previous one has passed the barrier above)
+    if (bi == kb && bj == kb) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) dgs[r0 + x] = sqrt(fmax(v[x][x], 0.0));
-  __syncthreads();
-  // R = u / sqrt(u_ii), stored to LDS (full, zero below the diagonal)
+      for (int x = 0; x < 4; ++x)
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const double d = dgs[r0 + x];
-    const double sc = d > 0.0 ? 1.0 / d : 0.0;
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = r0 + x, j = c0 + y;
-      const double rv = (active && i <= j) ? v[x][y] * sc : 0.0;
-      v[x][y] = rv;
-      rfull[i][j] = rv;
+        for (int y = 0; y < 4; ++y) panel[x][c0 + y] = v[x][y];
     }
+    if (bi == kb && bj > kb) {
+      double r[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          double acc = 0.0;
+#pragma unroll
+          for (int p = 0; p <= x; ++p) acc += wd[kb][p][x] * v[p][y];
+          r[x][y] = acc;
+        }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          v[x][y] = r[x][y];
+          panel[x][c0 + y] = r[x][y];
+        }
+    }
+    __syncthreads();
+    // 3. trailing update
+    if (active && bi > kb) {
+      double ra[4][4], rb[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          ra[p][y] = panel[p][r0 + y];
+          rb[p][y] = panel[p][c0 + y];
+        }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          double acc = v[x][y];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) acc -= ra[p][x] * rb[p][y];
+          v[x][y] = acc;
+        }
+    }
+    // the next step's diagonal thread works in its own registers and on wd[kb + 1];
+    // the panel buffer is rewritten only after the next step's first barrier
   }
-  // write R
+  if (bad) atomicOr(info, 1 << (b < 30 ? b : 30));
+  // R out (zero below the diagonal) and into LDS
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) Z[(r0 + x) + (long long)(c0 + y) * ld] = v[x][y];
-  // W = I, then rank-1 updates from the bottom row up
+    for (int y = 0; y < 4; ++y) {
+      const int i = r0 + x, j = c0 + y;
+      const double rv = (active && i <= j) ? v[x][y] : 0.0;
+      v[x][y] = rv;
+      rfull[i][j] = rv;
+      Z[i + (long long)j * ld] = rv;
+    }
+  // W: B = I, bottom-up block rows
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) v[x][y] = (r0 + x == c0 + y) ? 1.0 : 0.0;
   __syncthreads();
-  for (int l = NB - 1; l >= 0; --l) {
-    const int cur = l & 1;
-    const double rll = rfull[l][l];
-    const double rinv = rll != 0.0 ? 1.0 / rll : 0.0;
-    // owners of row l scale it (its updates from rows > l are complete) and publish
-    if (l / 4 == bi) {
-      const int x = l & 3;
-#pragma unroll
-      for (int xx = 0; xx < 4; ++xx)
-        if (xx == x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            v[xx][y] *= rinv;
-            prow[cur][c0 + y] = v[xx][y];
-          }
-    }
-    __syncthreads();
-    if (r0 < l) {
-      double rc[4], wl[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) rc[x] = rfull[r0 + x][l];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) wl[y] = prow[cur][c0 + y];
+  for (int lb = NB / 4 - 1; lb >= 0; --lb) {
+    const int buf = lb & 1;
+    if (bi == lb && bj >= lb) {
+      double t[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
-        if (r0 + x < l)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) v[x][y] -= rc[x] * wl[y];
+        for (int y = 0; y < 4; ++y) {
+          double acc = 0.0;
+#pragma unroll
+          for (int p = x; p < 4; ++p) acc += wd[lb][x][p] * v[p][y];
+          t[x][y] = acc;
+        }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          v[x][y] = t[x][y];
+          wrow[buf][x][c0 + y] = t[x][y];
+        }
+    }
+    __syncthreads();
+    if (bi < lb && bj >= lb) {
+      double rc[4][4], wr[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) rc[x][p] = rfull[r0 + x][4 * lb + p];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) wr[p][y] = wrow[buf][p][c0 + y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          double acc = v[x][y];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) acc -= rc[x][p] * wr[p][y];
+          v[x][y] = acc;
+        }
     }
   }
 #pragma unroll
@@ -146,7 +229,7 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int i = r0 + x, j = c0 + y;
-      W[i + (long long)j * ld] = (i <= j) ? v[x][y] : 0.0;
+      W[i + (long long)j * ld] = (active && i <= j) ? v[x][y] : 0.0;
     }
 }
 

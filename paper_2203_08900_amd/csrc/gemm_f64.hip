@@ -1,9 +1,10 @@
 // FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
 //
-// A workgroup of 4 waves computes a BM x BN tile of D = alpha op(A) op(B) + beta C;
-// each wave owns a (BM/2) x (BN/2) quadrant as MFMA 16x16 fragments.  Two tile shapes:
-// 128 x 128 (16 fragments per wave, 16 flops per byte loaded) for large problems and
-// 64 x 64 for small ones.  K advances in steps of 16 through two LDS buffers (one
+// A workgroup computes a BM x BN tile of D = alpha op(A) op(B) + beta C; its waves
+// own (BM/WM) x (BN/WN) sub-tiles as MFMA 16x16 fragments.  Two shapes: 128 x 128 with
+// 8 waves of 64 x 32 (16 flops per byte loaded, two waves per SIMD) for large problems
+// and 64 x 64 with 4 waves of 32 x 32 for small ones.  Operand transposes are
+// template parameters; a group of problems is launched once per transpose pair.  K advances in steps of 16 through two LDS buffers (one
 // barrier per step); the next step's global loads are issued before the MFMAs of
 // the current step.
 //
@@ -34,7 +35,6 @@ struct GemmGroup {
 namespace {
 
 constexpr int BK = 16;
-constexpr int NT = 256;
 constexpr int LDIK = BK + 1;
 
 __device__ inline void tri_index(int t, int& hi, int& lo) {
@@ -48,9 +48,9 @@ __device__ inline void tri_index(int t, int& hi, int& lo) {
 
 }  // namespace
 
-template <int BM, int BN>
-__global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
-  constexpr int WM = 2, WN = 2;
+template <int BM, int BN, int WM, int WN, int TA, int TB>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_f64_kernel(GemmGroup g) {
+  constexpr int NT = WM * WN * 64;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
   constexpr int LDKM = BM + 16;
   constexpr int LDKN = BN + 16;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmGroup g) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
-  const int tA = P.tA, tB = P.tB;
+  constexpr int tA = TA, tB = TB;
   const long long lda = P.lda, ldb = P.ldb;
 
   d4 acc[FM][FN];
@@ -290,13 +290,16 @@ GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
 }
 
 namespace {
-template <int BM, int BN>
-void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
+GemmRecorder* g_rec = nullptr;
+
+template <int BM, int BN, int WM, int WN, int TA, int TB>
+void launch_one(hipStream_t s, const GemmProblem* probs, int count) {
   GemmGroup g{};
   int total = 0;
   for (int q = 0; q < count; ++q) {
     GemmProblem p = probs[q];
     if (p.M <= 0 || p.N <= 0 || p.nb1 <= 0 || p.nb2 <= 0) continue;
+    if (p.tA != TA || p.tB != TB) continue;
     p.tm = p.M / BM;
     p.tn = p.N / BN;
     p.tiles = (p.flags & (kOutUpper | kOutLower)) ? p.tm * (p.tm + 1) / 2 : p.tm * p.tn;
@@ -308,8 +311,18 @@ void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
   if (total == 0) return;
   g.total = total;
   g.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), dim3(total), dim3(NT), 0, s, g);
+  const bool rec = BM == 128 && g_rec && g_rec->n < g_rec->cap;
+  if (rec) PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n], s));
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB>), dim3(total), dim3(WM * WN * 64),
+                     0, s, g);
   PS_HIP(hipGetLastError());
+  if (rec) {
+    PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n + 1], s));
+    double f = 0.0;
+    for (int q = 0; q < g.count; ++q) f += gemm_algorithmic_flops(g.p[q]);
+    g_rec->flops[g_rec->n] = f;
+    g_rec->n += 1;
+  }
   for (int q = 0; q < g.count; ++q) {
     const GemmProblem& p = g.p[q];
     if (p.ksplit > 1) {
@@ -320,7 +333,71 @@ void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
     }
   }
 }
+
+template <int BM, int BN, int WM, int WN>
+void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
+  launch_one<BM, BN, WM, WN, 0, 0>(s, probs, count);
+  launch_one<BM, BN, WM, WN, 0, 1>(s, probs, count);
+  launch_one<BM, BN, WM, WN, 1, 0>(s, probs, count);
+  launch_one<BM, BN, WM, WN, 1, 1>(s, probs, count);
+}
 }  // namespace
+
+void gemm_set_recorder(GemmRecorder* r) { g_rec = r; }
+
+// 2 x (number of structurally non-zero products) over the stored output entries.  For
+// each output (i, j) the K range is the intersection of the non-zero bands of op(A) row
+// i and op(B) column j within every segment; the unstored triangle is not counted.
+double gemm_algorithmic_flops(const GemmProblem& p) {
+  const long long M = p.M, N = p.N;
+  const long long segK = p.kseg > 0 ? p.kseg : p.K;
+  const long long nseg = p.kseg > 0 ? p.nseg : 1;
+  auto kb_a = [&](long long i) { return (p.flags & kAUpper) ? i : 0LL; };
+  auto ke_a = [&](long long i) { return (p.flags & kALower) ? std::min(segK, i + 1) : segK; };
+  auto kb_b = [&](long long j) { return (p.flags & kBLower) ? j : 0LL; };
+  auto ke_b = [&](long long j) { return (p.flags & kBUpper) ? std::min(segK, j + 1) : segK; };
+  const bool a_dep = p.flags & (kAUpper | kALower);
+  const bool b_dep = p.flags & (kBUpper | kBLower);
+  const bool tri = p.flags & (kOutUpper | kOutLower);
+  double total = 0.0;
+  if (!a_dep && !b_dep && !tri) {
+    total = (double)M * N * segK;
+  } else {
+    // sum over i of sum over the stored j of max(0, ke - kb); O(M * N) only when both
+    // operands or the output triangle couple i and j, done in closed form per row
+    for (long long i = 0; i < M; ++i) {
+      long long jlo = 0, jhi = N;   // stored columns [jlo, jhi)
+      if (p.flags & kOutUpper) jlo = i;
+      if (p.flags & kOutLower) jhi = std::min(N, i + 1);
+      if (!b_dep) {
+        const long long len = std::max(0LL, ke_a(i) - kb_a(i));
+        total += (double)len * std::max(0LL, jhi - jlo);
+      } else {
+        // B's band depends on j: lower (k >= j) or upper (k <= j); sum the piecewise
+        // linear length over j in [jlo, jhi) in closed form
+        const long long a0 = kb_a(i), a1 = ke_a(i);
+        auto sum_range = [](long long lo, long long hi, long long c0, long long c1) {
+          // sum over j in [lo, hi) of (c0 + c1 * j)
+          if (hi <= lo) return 0.0;
+          const double n = (double)(hi - lo);
+          return n * c0 + c1 * (double)(lo + hi - 1) * n / 2.0;
+        };
+        if (p.flags & kBLower) {
+          // len = a1 - max(a0, j) for j < a1
+          const long long hi = std::min(jhi, a1);
+          total += sum_range(jlo, std::min(hi, a0), a1 - a0, 0);
+          total += sum_range(std::max(jlo, a0), hi, a1, -1);
+        } else {
+          // kBUpper: len = min(a1, j + 1) - a0 for j + 1 > a0
+          const long long lo = std::max(jlo, a0);
+          total += sum_range(lo, std::min(jhi, a1), 1 - a0, 1);
+          total += sum_range(std::max(lo, a1), jhi, a1 - a0, 0);
+        }
+      }
+    }
+  }
+  return 2.0 * total * nseg * p.nb1 * p.nb2;
+}
 
 void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) {
   bool big = true;
@@ -345,9 +422,9 @@ void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) {
   }
   if (!live) return;
   if (big && tiles128 >= 128)
-    launch_group<128, 128>(s, probs, count);
+    launch_group<128, 128, 2, 4>(s, probs, count);
   else
-    launch_group<64, 64>(s, probs, count);
+    launch_group<64, 64, 2, 2>(s, probs, count);
 }
 
 }  // namespace ps

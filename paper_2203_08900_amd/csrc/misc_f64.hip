@@ -196,6 +196,22 @@ void fill_int_zero(hipStream_t s, int* x, int n) {
   PS_HIP(hipGetLastError());
 }
 
+// y = a x + b I (x, y may alias)
+__global__ void axpb_identity_kernel(const double* x, double* y, double a, double b, int mp) {
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    y[e] = a * x[e] + (i == j ? b : 0.0);
+  }
+}
+
+void axpb_identity(hipStream_t s, const double* x, double* y, double a, double b, int mp) {
+  hipLaunchKernelGGL(axpb_identity_kernel, dim3(blocks_for((size_t)mp * mp)), dim3(NT), 0, s, x,
+                     y, a, b, mp);
+  PS_HIP(hipGetLastError());
+}
+
 __global__ void scale_copy_kernel(const double* x, double* y, double a, size_t n) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x)

@@ -39,6 +39,8 @@ struct ps_handle_s {
   double* pinned = nullptr;  // host staging for scalars
   hipEvent_t ev[10] = {};
   bool events = false;
+  std::vector<hipEvent_t> kev;  // per-launch GEMM timing (opts.timing == 2)
+  std::vector<double> kflops;
 };
 
 namespace ps {
@@ -239,6 +241,65 @@ void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const
   gemm_f64(s, px);
 }
 
+// Number of series terms for the second step, or 0 when the factorization form is
+// needed.  After the first step the singular values of X lie in [l1, 1], so
+// Delta = X^T X - I has ||Delta|| <= 1 - l1^2 and, with (G + c I)^{-1} =
+// (1 + c)^{-1} sum_p (-Delta / (1 + c))^p, the p-th term of sum_j a_j (G + c_j I)^{-1} is
+// bounded by gamma_p ||Delta||^p, gamma_p = sum_j a_j / (1 + c_j)^{p+1}.  P terms are
+// used when the first omitted one is below 1e-17 relative to gamma_0.
+int series_terms(const ZoloHost& co, double ell_in, double gam[4]) {
+  const long double d = 1.0L - (long double)ell_in * ell_in;
+  long double g[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < co.r; ++j) {
+    long double f = 1.0L / (1.0L + co.c[2 * j]);
+    long double t = co.a[j] * f;
+    for (int p = 0; p < 6; ++p) {
+      g[p] += t;
+      t *= f;
+    }
+  }
+  for (int P = 1; P <= 4; ++P) {
+    long double bound = g[P];
+    for (int q = 0; q < P; ++q) bound *= d;
+    if (bound <= 1e-17L * g[0]) {
+      for (int p = 0; p < 4; ++p) gam[p] = (double)((p & 1) ? -g[p] : g[p]);
+      return P;
+    }
+  }
+  return 0;
+}
+
+// Second Zolotarev step by the series: xn = hat C x (I + sum_{p<P} gam_p Delta^p),
+// Delta = x^T x - I, evaluated by Horner's rule on the right.
+void zolo_step_series(hipStream_t s, Buffers& b, const double* x, double* xn, const ZoloHost& co,
+                      int P, const double gam[4]) {
+  const int mp = b.mp;
+  GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
+                                kOutUpper | kMirror);
+  auto_split(pg, b.splitws);
+  gemm_f64(s, pg);
+  axpb_identity(s, b.g, b.g, 1.0, -1.0, mp);                 // Delta
+  // T = (1 + gam_0) I + gam_1 Delta + ... + gam_{P-1} Delta^{P-1}
+  double* T = b.nmat;
+  double* T2 = b.t1;
+  if (P == 1) {
+    axpb_identity(s, b.g, T, 0.0, 1.0 + gam[0], mp);
+  } else {
+    axpb_identity(s, b.g, T, gam[P - 1], (P - 2 == 0 ? 1.0 + gam[0] : gam[P - 2]), mp);
+    for (int q = P - 3; q >= 0; --q) {
+      GemmProblem ph = gemm_problem(mp, mp, mp, b.g, mp, 0, T, mp, 0, T2, mp, 1.0, 0.0, nullptr,
+                                    0, 0);
+      auto_split(ph, b.splitws);
+      gemm_f64(s, ph);
+      axpb_identity(s, T2, T, 1.0, q == 0 ? 1.0 + gam[0] : gam[q], mp);
+    }
+  }
+  GemmProblem px = gemm_problem(mp, mp, mp, x, mp, 0, T, mp, 0, xn, mp, co.chat, 0.0, nullptr, 0,
+                                0);
+  auto_split(px, b.splitws);
+  gemm_f64(s, px);
+}
+
 // alpha, beta for the core matrix: sigma_max(Y) and 1/sigma_max(Y^{-1}) by Golub-Kahan.
 void estimate_bounds(hipStream_t s, Buffers& b, const double* ymats, int steps, double* pinned,
                      double* alpha, double* beta, double est[2]) {
@@ -286,6 +347,25 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   inf.r = r;
   Timer tm{h, o.timing != 0};
   tm.mark(-1);
+  GemmRecorder grec;
+  struct RecGuard {
+    ~RecGuard() { gemm_set_recorder(nullptr); }
+  } rec_guard;
+  if (o.timing >= 2) {
+    const int cap = 256;
+    if ((int)h->kev.size() < 2 * cap) {
+      while ((int)h->kev.size() < 2 * cap) {
+        hipEvent_t e;
+        PS_HIP(hipEventCreate(&e));
+        h->kev.push_back(e);
+      }
+    }
+    h->kflops.assign(cap, 0.0);
+    grec.ev = h->kev.data();
+    grec.flops = h->kflops.data();
+    grec.cap = cap;
+    gemm_set_recorder(&grec);
+  }
 
   fill_int_zero(s, b.dinfo, 16);
   // ---- setup: M = A + B = R_M^T R_M, K = A - B = R_K^T R_K, Y0 = R_M R_K^T, Y0^{-1} = W_K^T W_M
@@ -351,7 +431,13 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
       std::swap(b.x1, b.x2);  // the sign assembly reads x2
       break;
     }
-    zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
+    double gam[4];
+    const int P = o.step2_series ? series_terms(c2, ell1, gam) : 0;
+    inf.step2_terms = P;
+    if (P > 0)
+      zolo_step_series(s, b, b.x1, b.x2, c2, P, gam);
+    else
+      zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
     tm.mark(3);
     inf.steps += 2;
     diff_norms(s, b.x1, b.x2, b.S, b.norms);
@@ -467,6 +553,13 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     return PS_BASIS_BREAKDOWN;
   }
   tm.finish(inf.phase_ms);
+  for (int q = 0; q < grec.n; ++q) {
+    float t = 0.f;
+    PS_HIP(hipEventElapsedTime(&t, grec.ev[2 * q], grec.ev[2 * q + 1]));
+    inf.gemm_ms += t;
+    inf.gemm_flops += grec.flops[q];
+  }
+  inf.gemm_launches = grec.n;
   inf.status = PS_OK;
   if (info) *info = inf;
   return PS_OK;
@@ -519,6 +612,7 @@ void ps_opts_default(ps_opts* o) {
   o->alpha = 0.0;
   o->beta = 0.0;
   o->mixed_kappa = 20.0;
+  o->step2_series = 1;
 }
 
 int ps_create(ps_handle* h, void* stream) {
@@ -549,6 +643,7 @@ int ps_destroy(ps_handle h) {
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->events)
     for (auto& e : h->ev) (void)hipEventDestroy(e);
+  for (auto& e : h->kev) (void)hipEventDestroy(e);
   delete h;
   return PS_OK;
 }

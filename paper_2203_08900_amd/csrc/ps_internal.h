@@ -74,6 +74,17 @@ GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
                          double alpha = 1.0, double beta = 0.0, const double* C = nullptr,
                          int ldc = 0, int flags = 0);
 
+// Optional per-launch timing of the large-tile GEMM kernel: when set, gemm_f64 brackets
+// each such launch with events from this recorder and adds the algorithmic flops.
+struct GemmRecorder {
+  hipEvent_t* ev = nullptr;   // pairs (start, stop)
+  double* flops = nullptr;    // per recorded launch
+  int cap = 0;                // number of pairs available
+  int n = 0;                  // pairs used
+};
+void gemm_set_recorder(GemmRecorder* r);
+double gemm_algorithmic_flops(const GemmProblem& p);
+
 // Launch up to kMaxGroup independent problems in one kernel.  Problems with
 // ksplit > 1 are followed by a reduction launch (sum of partials, beta C, triangle
 // and mirror handling); their batch extent must be 1.
@@ -102,6 +113,7 @@ void transpose(hipStream_t s, const double* x, double* y, int mp, long long stri
 void form_shifts(hipStream_t s, const double* g, double* z, int mp, const double* shifts,
                  int r);   // z[j] = upper(G) + shifts[j] I, strictly lower zero
 void scale_copy(hipStream_t s, const double* x, double* y, double a, size_t n);
+void axpb_identity(hipStream_t s, const double* x, double* y, double a, double b, int mp);
 void sign_blocks(hipStream_t s, const double* s12, const double* s21, double* as,
                  double* bs, int mp);   // A_s = sym(S21+S12)/2, B_s = sym(S21-S12)/2
 void half_shift_upper(hipStream_t s, const double* as, double* p11, int mp);  // (I+A_s)/2

@@ -59,6 +59,21 @@ def test_sign_parity(m, seed, kind):
     assert np.abs(SB.cpu().numpy() - s[:m, m:]).max() < 1e-12 * np.abs(s).max()
 
 
+@pytest.mark.parametrize("m,seed,kind", [CASES[2], CASES[5], CASES[7]])
+def test_step2_forms_agree(m, seed, kind):
+    """The second step by r factorizations (Eq:LDLZolo form on the core) and by the
+    series in Delta = X^T X - I evaluate the same rational function."""
+    a, b = make(m, seed, kind)
+    al, be = bounds(a, b)
+    ref = dv.divide_casida(a, b, alpha=al, beta=be)["S"]
+    SA1, SB1, i1 = api.sign(dev(a), dev(b), alpha=al, beta=be, step2_series=False)
+    SA2, SB2, i2 = api.sign(dev(a), dev(b), alpha=al, beta=be, step2_series=True)
+    assert i1["step2_terms"] == 0 and 1 <= i2["step2_terms"] <= 4
+    for SA in (SA1, SA2):
+        assert rel(SA.cpu().numpy(), ref[:m, :m]) < 1e-12
+    assert np.abs(SA1.cpu().numpy() - SA2.cpu().numpy()).max() < 1e-13
+
+
 @pytest.mark.parametrize("m,seed,kind", CASES[1:4])
 def test_first_iterate_parity(m, seed, kind):
     """X_1 = hat Z(H / alpha; l) of Alg. 8, returned in H-form with max_steps = 1."""
