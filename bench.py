@@ -91,6 +91,35 @@ def gpu_leg(args, a, b):
     return out
 
 
+def copy_probe(nbytes: int = 512 << 20):
+    """A plain streaming kernel of known size: y = -x over nbytes of FP64 (reads and
+    writes nbytes each)."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+
+
+def traffic_from_profile(kernel_src: str):
+    """HBM bytes per launch of the large-tile GEMM from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_f64_128x128_traffic_casida_n4096.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if kv.get("kernel_source_sha256_16") != h:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def cpu_leg(args, a, b):
     """The oracle: one shifted LDL^T solve of Eq:LDLZolo at full size (the unit that
     dominates the paper-literal divide), and the reference eigenvalues."""
@@ -140,6 +169,9 @@ def main():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--modes", default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain device copy of 512 MiB three times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     args = ap.parse_args()
     args.modes = [s for s in args.modes.split(",") if s]
     if args.gpus != 1:
@@ -150,6 +182,8 @@ def main():
 
     from paper_2203_08900_amd import inputs
 
+    if args.copy_probe:
+        copy_probe()
     a, b = inputs.casida_like(args.m, args.seed)
     g = gpu_leg(args, a, b)
     primary = "mixed" if "mixed" in g else args.modes[0]
@@ -176,7 +210,9 @@ def main():
     if gm["launches"] > 0 and gm["ms"] > 0:
         achieved = gm["flops"] / (gm["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK["f64"], "traffic": None,
+                "frac": achieved / PEAK["f64"],
+                "traffic": traffic_from_profile(os.path.join(
+                    ROOT, "paper_2203_08900_amd", "csrc", "gemm_f64.hip")),
                 "kernel": "gemm_f64_kernel<128,128> (all transposes)",
                 "launches_per_step": gm["launches"] / args.steps,
                 "avg_launch_ms": gm["ms"] / gm["launches"],
