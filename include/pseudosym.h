@@ -104,6 +104,11 @@ typedef struct {
   double gemm_ms;          /*   their summed GPU time                                 */
   double gemm_flops;       /*   their algorithmic flops (zero blocks of triangular    */
                            /*   operands and the unstored triangle not counted)      */
+  int eig_splits;          /* pseudosym_eig: splits of the symmetric recursion        */
+  int eig_leaves;          /*   leaves solved by the Jacobi kernel                    */
+  int eig_sweeps;          /*   largest number of Jacobi sweeps of a leaf             */
+  int eig_steps;           /*   Zolotarev steps summed over the splits                */
+  int eig_restarts;        /*   restarts summed over the splits                       */
 } ps_info;
 
 /* Fill *o with the defaults: FP64, r = 8, 2 restarts, full method, 20 Lanczos
@@ -153,6 +158,24 @@ int pseudosym_sign(ps_handle h, int m, const double* A, int lda, const double* B
 int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                      double* Qp, int ldq, double* Hp, int ldh, const ps_opts* opts,
                      ps_info* info);
+
+/* All eigenpairs of H (Alg. 3 once, then Alg. 2 on the decoupled block; Thm. DefDivConq
+ * reduces the rest to the symmetric positive definite H_+).  H_+ = Q_+^T Sigma H Q_+
+ * comes from pseudosym_divide; the symmetric spectral divide-and-conquer splits it
+ * recursively: shift sigma = median of the diagonal of the current block, sign of the
+ * shifted block by the same Zolotarev iteration (r chosen by the two-step rule), bases
+ * of both projectors by Alg. 4 (Cholesky of a leading block; the leading indices are
+ * those with the largest projector diagonal), until blocks of at most 64 remain, which
+ * a Jacobi kernel diagonalizes.
+ * Outputs (device): lambda[0..2m-1]: lambda[i], i < m, the positive eigenvalues in
+ * ascending order, lambda[m+i] = -lambda[i].  V (2m x 2m, leading dimension
+ * ldv >= 2m, may be NULL): column j is the eigenvector of lambda[j] with
+ * V^T Sigma V = diag(I_m, -I_m), V(:, m+i) = Pi V(:, i), and each column's entry of
+ * largest modulus (lowest index on ties) positive.  opts->r applies to the first
+ * division step.  Status PS_NOT_CONVERGED with info->failed_step = 5 when no shift
+ * splits a block of the recursion. */
+int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                  double* lambda, double* V, int ldv, const ps_opts* opts, ps_info* info);
 
 /* Human-readable name of a status code. */
 const char* ps_status_string(int status);

@@ -62,6 +62,11 @@ class PsInfo(ctypes.Structure):
         ("gemm_launches", ctypes.c_int),
         ("gemm_ms", ctypes.c_double),
         ("gemm_flops", ctypes.c_double),
+        ("eig_splits", ctypes.c_int),
+        ("eig_leaves", ctypes.c_int),
+        ("eig_sweeps", ctypes.c_int),
+        ("eig_steps", ctypes.c_int),
+        ("eig_restarts", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -73,7 +78,9 @@ class PsInfo(ctypes.Structure):
             "step_change": self.step_change, "sigma_est": list(self.sigma_est),
             "phase_ms": list(self.phase_ms), "step2_terms": self.step2_terms,
             "gemm_launches": self.gemm_launches, "gemm_ms": self.gemm_ms,
-            "gemm_flops": self.gemm_flops,
+            "gemm_flops": self.gemm_flops, "eig_splits": self.eig_splits,
+            "eig_leaves": self.eig_leaves, "eig_sweeps": self.eig_sweeps,
+            "eig_steps": self.eig_steps, "eig_restarts": self.eig_restarts,
         }
 
 
@@ -119,10 +126,9 @@ def load():
         lib.pseudosym_divide.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
                                                ctypes.POINTER(PsInfo)]
         lib.pseudosym_divide.restype = ip
-        if hasattr(lib, "pseudosym_eig"):
-            lib.pseudosym_eig.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts),
-                                                ctypes.POINTER(PsInfo)]
-            lib.pseudosym_eig.restype = ip
+        lib.pseudosym_eig.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts),
+                                            ctypes.POINTER(PsInfo)]
+        lib.pseudosym_eig.restype = ip
         lib.ps_status_string.argtypes = [ip]
         lib.ps_status_string.restype = ctypes.c_char_p
         _lib = lib

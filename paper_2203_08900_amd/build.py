@@ -20,6 +20,7 @@ SOURCES = [
     "gemm_f64.hip",
     "chol_f64.hip",
     "misc_f64.hip",
+    "eig_f64.hip",
     "zolo_host.cpp",
     "pipeline.cpp",
 ]

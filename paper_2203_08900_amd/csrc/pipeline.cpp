@@ -47,7 +47,7 @@ namespace ps {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kPinned = 4096;  // doubles
+constexpr int kPinned = 1 << 16;  // doubles (host staging: up to m = 32768 values)
 
 struct Arena {
   char* base = nullptr;
@@ -97,7 +97,7 @@ void carve(Arena& a, Buffers& b, int m, int r, int what) {
   b.r = r;
   const size_t S = (size_t)b.mp * b.mp;
   b.S = S;
-  const int rr = std::max(r, 2);
+  const int rr = std::max(r, what >= 2 ? 8 : 2);   // the eig subproblems use 8 slots
   b.mk = a.take<double>(2 * S);
   b.wmk = a.take<double>(2 * S);
   b.tmp = a.take<double>((size_t)rr * b.mp * kNb);
@@ -152,9 +152,51 @@ int auto_r(double ell) {
 
 int resolve_r(const ps_opts& o) { return o.r <= 0 ? 8 : std::min(o.r, 8); }
 
+// Device buffers of the eigen-decomposition, placed after the largest divide or
+// subproblem layout (the recursion reuses that region for every subproblem).
+struct EigBuffers {
+  double *qf, *hraw, *hs, *qt, *qb, *vacc, *t, *vs, *zbd, *w, *wsorted, *dscratch;
+  int *perm, *leaf_o, *leaf_n, *sweeps;
+};
+
+size_t eig_region_offset(int m, const ps_opts& o) {
+  Arena a1, a2;
+  Buffers b1, b2;
+  carve(a1, b1, m, resolve_r(o), 1);
+  carve(a2, b2, m, 8, 2);
+  return std::max(a1.off, a2.off);
+}
+
+void carve_eig(Arena& a, EigBuffers& e, int m) {
+  const int mp = pad_to(m);
+  const size_t S = (size_t)mp * mp;
+  e.qf = a.take<double>((size_t)2 * m * m);
+  e.hraw = a.take<double>((size_t)m * m);
+  e.hs = a.take<double>(S);
+  e.qt = a.take<double>(S);
+  e.qb = a.take<double>(S);
+  e.vacc = a.take<double>(S);
+  e.t = a.take<double>(S);
+  e.vs = a.take<double>(S);
+  e.zbd = a.take<double>(S);
+  e.w = a.take<double>(mp);
+  e.wsorted = a.take<double>(mp);
+  e.dscratch = a.take<double>(mp);
+  e.perm = a.take<int>(mp);
+  e.leaf_o = a.take<int>(mp);
+  e.leaf_n = a.take<int>(mp);
+  e.sweeps = a.take<int>(16);
+}
+
 size_t workspace_bytes(int m, const ps_opts& o, int what) {
   Arena a;
   Buffers b;
+  if (what >= 2) {
+    a.off = eig_region_offset(m, o);
+    EigBuffers e;
+    carve_eig(a, e, m);
+    return a.off + kAlign;
+  }
   carve(a, b, m, resolve_r(o), what);
   return a.off + kAlign;
 }
@@ -312,15 +354,12 @@ void estimate_bounds(hipStream_t s, Buffers& b, const double* ymats, int steps, 
   *beta = 0.99 / smax[1];
 }
 
-int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
-        int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what) {
-  hipStream_t s = h->stream;
-  const int r = resolve_r(o);
-  // workspace
-  const size_t need = workspace_bytes(m, o, what);
+// The workspace (caller's, or the handle's own, grown on demand), aligned; null when
+// the caller's is too small.
+char* workspace_base(ps_handle h, size_t need) {
   char* base;
   if (h->user_ws) {
-    if (h->user_bytes < need) return PS_NO_WORKSPACE;
+    if (h->user_bytes < need) return nullptr;
     base = (char*)h->user_ws;
   } else {
     if (h->own_bytes < need) {
@@ -332,7 +371,101 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     }
     base = (char*)h->own_ws;
   }
-  base = (char*)(((uintptr_t)base + kAlign - 1) / kAlign * kAlign);
+  return (char*)(((uintptr_t)base + kAlign - 1) / kAlign * kAlign);
+}
+
+// The Zolotarev iteration of Alg. 8 on the core matrix y (padded b.mp x b.mp, zero
+// padding): X0 = y / alpha, l = beta / alpha, two steps per attempt, the stopping
+// test ||X2 - X1||_F / ||X2||_F <= u^{1/(2r+1)} and restarts from X2 with bounds
+// re-estimated on X2.  r_opt <= 0 picks r by the two-step rule.  Fills the iteration
+// fields of inf; on PS_OK the polar factor of y is in b.x2.  Uses b.dinfo[1..3].
+int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, double beta,
+                  int r_opt, const ps_opts& o, double* pin, ps_info& inf, Timer& tm) {
+  const int mp = b.mp;
+  const long long S = (long long)b.S;
+  const int r = r_opt <= 0 ? 8 : std::min(r_opt, 8);
+  scale_copy(s, y, b.x0, 1.0 / alpha, b.S);
+
+  double ell = std::min(beta / alpha, 1.0 - 1e-15);
+  const int r_run = (r_opt <= 0) ? auto_r(ell) : r;
+  inf.r = r_run;
+  const double tol = std::pow(std::ldexp(1.0, -53), 1.0 / (2 * r_run + 1));
+  int status = PS_OK;
+  const double* xin = b.x0;
+  int attempt = 0;
+  int ell_slot = 0;
+  for (;; ++attempt) {
+    ZoloHost c1, c2;
+    if (zolotarev_host(ell, r_run, &c1)) return PS_NOT_CONVERGED;
+    double ell1 = std::min(c1.ell_next, 1.0 - 1e-15);
+    if (zolotarev_host(ell1, r_run, &c2)) return PS_NOT_CONVERGED;
+    if (ell_slot < 4) inf.ell[ell_slot++] = ell;
+    if (ell_slot < 4) inf.ell[ell_slot++] = ell1;
+    zolo_step_f64(s, b, xin, b.x1, c1, b.dinfo + 1);
+    tm.mark(2);
+    if (o.max_steps == 1) {
+      inf.steps += 1;
+      std::swap(b.x1, b.x2);  // the sign assembly reads x2
+      break;
+    }
+    double gam[4];
+    const int P = o.step2_series ? series_terms(c2, ell1, gam) : 0;
+    inf.step2_terms = P;
+    if (P > 0)
+      zolo_step_series(s, b, b.x1, b.x2, c2, P, gam);
+    else
+      zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
+    tm.mark(3);
+    inf.steps += 2;
+    diff_norms(s, b.x1, b.x2, b.S, b.norms);
+    PS_HIP(hipMemcpyAsync(pin, b.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipStreamSynchronize(s));
+    const int* di = (const int*)(pin + 8);
+    if (di[1] || di[2]) {
+      status = PS_SHIFT_BREAKDOWN;
+      inf.failed_step = di[1] ? 1 : 2;
+      inf.failed_mask = di[1] ? di[1] : di[2];
+      break;
+    }
+    const double change = std::sqrt(pin[0]) / std::sqrt(pin[1]);
+    inf.step_change = change;
+    if (change <= tol) break;
+    if (attempt >= o.max_restarts) {
+      status = PS_NOT_CONVERGED;
+      break;
+    }
+    // restart from X2: new bounds from Golub-Kahan on X2 and on chol(X2^T X2)^{-1}
+    inf.restarts += 1;
+    {
+      GemmProblem pg = gemm_problem(mp, mp, mp, b.x2, mp, 1, b.x2, mp, 0, b.g, mp, 1.0, 0.0,
+                                    nullptr, 0, kOutUpper);
+      auto_split(pg, b.splitws);
+      gemm_f64(s, pg);
+      spd_pad(s, b.g, b.z, b.m, mp, 0.0);
+      potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, 1, b.dinfo + 3);
+      // estimator pair: y = [X2, W_G]
+      PS_HIP(hipMemcpyAsync(b.y, b.x2, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PS_HIP(hipMemcpyAsync(b.y + S, b.w, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
+      double est[2], a2, b2;
+      estimate_bounds(s, b, b.y, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a2, &b2,
+                      est);
+      // sigma_max(W_G) = 1 / sigma_min(X2)
+      scale_copy(s, b.x2, b.x0, 1.0 / a2, b.S);
+      xin = b.x0;
+      ell = std::min(b2 / a2, 1.0 - 1e-15);
+    }
+  }
+  return status;
+}
+
+int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
+        int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what) {
+  hipStream_t s = h->stream;
+  const int r = resolve_r(o);
+  // workspace
+  char* base = workspace_base(h, workspace_bytes(m, o, what));
+  if (!base) return PS_NO_WORKSPACE;
   Arena ar;
   ar.base = base;
   ar.dry = false;
@@ -407,79 +540,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   tm.mark(1);
 
   // ---- Zolotarev steps with the stopping test of Alg. 8
-  scale_copy(s, b.y, b.x0, 1.0 / alpha, b.S);
-
-  double ell = std::min(beta / alpha, 1.0 - 1e-15);
-  const int r_run = (o.r <= 0) ? auto_r(ell) : r;
-  inf.r = r_run;
-  const double tol = std::pow(std::ldexp(1.0, -53), 1.0 / (2 * r_run + 1));
-  int status = PS_OK;
-  const double* xin = b.x0;
-  int attempt = 0;
-  int ell_slot = 0;
-  for (;; ++attempt) {
-    ZoloHost c1, c2;
-    if (zolotarev_host(ell, r_run, &c1)) return PS_HIP_ERROR;
-    double ell1 = std::min(c1.ell_next, 1.0 - 1e-15);
-    if (zolotarev_host(ell1, r_run, &c2)) return PS_HIP_ERROR;
-    if (ell_slot < 4) inf.ell[ell_slot++] = ell;
-    if (ell_slot < 4) inf.ell[ell_slot++] = ell1;
-    zolo_step_f64(s, b, xin, b.x1, c1, b.dinfo + 1);
-    tm.mark(2);
-    if (o.max_steps == 1) {
-      inf.steps += 1;
-      std::swap(b.x1, b.x2);  // the sign assembly reads x2
-      break;
-    }
-    double gam[4];
-    const int P = o.step2_series ? series_terms(c2, ell1, gam) : 0;
-    inf.step2_terms = P;
-    if (P > 0)
-      zolo_step_series(s, b, b.x1, b.x2, c2, P, gam);
-    else
-      zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
-    tm.mark(3);
-    inf.steps += 2;
-    diff_norms(s, b.x1, b.x2, b.S, b.norms);
-    PS_HIP(hipMemcpyAsync(pin, b.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
-    PS_HIP(hipStreamSynchronize(s));
-    const int* di = (const int*)(pin + 8);
-    if (di[1] || di[2]) {
-      status = PS_SHIFT_BREAKDOWN;
-      inf.failed_step = di[1] ? 1 : 2;
-      inf.failed_mask = di[1] ? di[1] : di[2];
-      break;
-    }
-    const double change = std::sqrt(pin[0]) / std::sqrt(pin[1]);
-    inf.step_change = change;
-    if (change <= tol) break;
-    if (attempt >= o.max_restarts) {
-      status = PS_NOT_CONVERGED;
-      break;
-    }
-    // restart from X2: new bounds from Golub-Kahan on X2 and on chol(X2^T X2)^{-1}
-    inf.restarts += 1;
-    {
-      GemmProblem pg = gemm_problem(mp, mp, mp, b.x2, mp, 1, b.x2, mp, 0, b.g, mp, 1.0, 0.0,
-                                    nullptr, 0, kOutUpper);
-      auto_split(pg, b.splitws);
-      gemm_f64(s, pg);
-      double one = 0.0;
-      form_shifts_v(s, b.g, b.z, mp, &one, 1);
-      potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, 1, b.dinfo + 3);
-      // estimator pair: y = [X2, W_G]
-      PS_HIP(hipMemcpyAsync(b.y, b.x2, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
-      PS_HIP(hipMemcpyAsync(b.y + S, b.w, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
-      double est[2], a2, b2;
-      estimate_bounds(s, b, b.y, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a2, &b2,
-                      est);
-      // sigma_max(W_G) = 1 / sigma_min(X2)
-      scale_copy(s, b.x2, b.x0, 1.0 / a2, b.S);
-      xin = b.x0;
-      ell = std::min(b2 / a2, 1.0 - 1e-15);
-    }
-  }
+  const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm);
   if (status != PS_OK) {
     inf.status = status;
     tm.finish(inf.phase_ms);
@@ -560,6 +621,280 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     inf.gemm_flops += grec.flops[q];
   }
   inf.gemm_launches = grec.n;
+  inf.status = PS_OK;
+  if (info) *info = inf;
+  return PS_OK;
+}
+
+
+// ---------------------------------------------------------------- eigen-decomposition
+// Leaves of the recursion: subproblems of at most this size go to the Jacobi kernel.
+constexpr int kLeaf = 64;
+
+// One split of Alg. 2 on the subproblem spanned by columns o..o+n of the accumulated
+// basis V (H_+ restricted to it is A_sub = V_sub^T H_+ V_sub): shift sigma = median of
+// the diagonal of A_sub, U = sign(A_sub - sigma I) by the Zolotarev iteration (the
+// polar factor of a symmetric matrix is its sign), r_+ = trace((I + U)/2), bases of
+// range(P_+) and range(P_-) by Alg. 4 (Cholesky of a leading block of each projector,
+// the leading indices chosen as those with the largest diagonal of the projector), a
+// Cholesky-QR pass over [Q_- Q_+], and V_sub <- V_sub [Q_- Q_+].  On success *rminus is
+// the size of the lower part (eigenvalues below sigma), which occupies the first
+// columns.
+int eig_split(hipStream_t s, char* base, EigBuffers& e, int m, int o, int n, const ps_opts& o_,
+              double* pin, ps_info& inf, int* rminus) {
+  const int mp = pad_to(m);
+  Arena sa;
+  sa.base = base;
+  sa.dry = false;
+  Buffers b;
+  carve(sa, b, n, 8, 2);
+  const int np = b.mp;
+  const long long Sn = (long long)b.S;
+  // A_sub = V_sub^T (H_+ V_sub)
+  copy_pad(s, e.vacc + (size_t)o * mp, mp, mp, n, e.vs, mp, mp, np);
+  {
+    GemmProblem pt = gemm_problem(mp, np, mp, e.hs, mp, 0, e.vs, mp, 0, e.t, mp);
+    gemm_f64(s, pt);
+    GemmProblem pa = gemm_problem(np, np, mp, e.vs, mp, 1, e.t, mp, 0, e.zbd, np, 1.0, 0.0,
+                                  nullptr, 0, kOutUpper | kMirror);
+    gemm_f64(s, pa);
+  }
+  get_diag(s, e.zbd, np, n, e.dscratch);
+  PS_HIP(hipMemcpyAsync(pin, e.dscratch, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  std::vector<double> dg(pin, pin + n);
+  std::sort(dg.begin(), dg.end());
+  const double lo = dg.front(), hi = dg.back();
+  double sigma = (n & 1) ? dg[n / 2] : 0.5 * (dg[n / 2 - 1] + dg[n / 2]);
+  int rp = 0;
+  bool ok = false;
+  for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
+    if (attempt > 0) {
+      // nudge the shift away from the side that received everything (or, after a
+      // breakdown, just move it); the spread of the diagonal sets the step
+      const double step = (hi - lo > 0 ? hi - lo : std::fabs(hi) + 1.0) * 0.25 / attempt;
+      sigma += (rp == n) ? step : -step;
+      if (rp != 0 && rp != n) sigma += 1e-3 * step;
+    }
+    fill_int_zero(s, b.dinfo, 16);
+    scale_copy(s, e.zbd, b.y, 1.0, b.S);
+    shift_diag(s, b.y, np, n, -sigma);
+    // alpha >= sigma_max(Y), beta <= sigma_min(Y) = 1 / sigma_max(chol(Y^T Y)^{-1})
+    {
+      GemmProblem pg = gemm_problem(np, np, np, b.y, np, 1, b.y, np, 0, b.g, np, 1.0, 0.0,
+                                    nullptr, 0, kOutUpper);
+      auto_split(pg, b.splitws);
+      gemm_f64(s, pg);
+      spd_pad(s, b.g, b.z, n, np, 0.0);
+      potrf_inv_f64(s, b.z, Sn, b.w, Sn, b.tmp, np, 1, b.dinfo + 3);
+      PS_HIP(hipMemcpyAsync(b.y + Sn, b.w, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    // the estimator pair overwrites b.y: keep Y in x1 meanwhile
+    scale_copy(s, b.y, b.x1, 1.0, b.S);
+    double est[2], alpha, beta;
+    estimate_bounds(s, b, b.y, std::max(4, std::min(o_.lanczos_steps, 120)), pin, &alpha, &beta,
+                    est);
+    PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipStreamSynchronize(s));
+    if (((int*)pin)[3] != 0 || !(beta > 0.0) || !(alpha > beta)) {
+      rp = -1;   // (nearly) singular shift: move it
+      continue;
+    }
+    scale_copy(s, b.x1, b.y, 1.0, b.S);
+    ps_info pinf{};
+    Timer tm0{nullptr, false};
+    const int st = polar_iterate(s, b, b.y, alpha, beta, 0, o_, pin, pinf, tm0);
+    inf.eig_steps += pinf.steps;
+    inf.eig_restarts += pinf.restarts;
+    if (st != PS_OK) {
+      rp = -1;
+      continue;
+    }
+    get_diag(s, b.x2, np, n, e.dscratch);
+    PS_HIP(hipMemcpyAsync(pin, e.dscratch, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipStreamSynchronize(s));
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += pin[i];
+    rp = (int)std::lround(0.5 * (n + tr));
+    ok = rp > 0 && rp < n;
+  }
+  if (!ok) return PS_NOT_CONVERGED;
+  const int rm = n - rp;
+  // pivot order: indices by decreasing diagonal of P_+ = (I + U)/2 (ties by index)
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::vector<double> du(pin, pin + n);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return du[x] > du[y]; });
+  int* ipin = (int*)pin;
+  for (int i = 0; i < n; ++i) ipin[i] = idx[i];
+  PS_HIP(hipMemcpyAsync(e.perm, ipin, n * sizeof(int), hipMemcpyHostToDevice, s));
+  const int* pp = e.perm;        // r_+ pivots of P_+
+  const int* pm = e.perm + rp;   // the other r_- indices: pivots of P_-
+  const int npp = pad_to(rp), npm = pad_to(rm);
+  const double* U = b.x2;
+  double* z[8];
+  double* w[8];
+  for (int k = 0; k < 8; ++k) {
+    z[k] = b.z + k * Sn;
+    w[k] = b.w + k * Sn;
+  }
+  fill_int_zero(s, b.dinfo, 16);
+  // Alg. 4: P_+(pp, pp) = C_+ C_+^T (C_+ = R_+^T), Q_+ rows pp = C_+, rows pm = P_+(pm, pp) C_+^{-T}
+  gather_sym(s, U, np, pp, pp, rp, rp, 0.5, 0.5, z[0], npp, npp, npp, 1.0, 1);
+  gather_sym(s, U, np, pm, pp, rm, rp, 0.5, 0.5, z[1], npm, npm, npp, 0.0, 0);
+  gather_sym(s, U, np, pm, pm, rm, rm, -0.5, 0.5, z[3], npm, npm, npm, 1.0, 1);
+  gather_sym(s, U, np, pp, pm, rp, rm, -0.5, 0.5, z[4], npp, npp, npm, 0.0, 0);
+  potrf_inv_f64(s, z[0], 0, w[0], 0, b.tmp, npp, 1, b.dinfo + 4);
+  potrf_inv_f64(s, z[3], 0, w[1], 0, b.tmp, npm, 1, b.dinfo + 5);
+  {
+    GemmProblem q1 = gemm_problem(npm, npp, npp, z[1], npm, 0, w[0], npp, 0, z[2], npm, 1.0, 0.0,
+                                  nullptr, 0, kBUpper);
+    GemmProblem q2 = gemm_problem(npp, npm, npm, z[4], npp, 0, w[1], npm, 0, z[5], npp, 1.0, 0.0,
+                                  nullptr, 0, kBUpper);
+    gemm_f64(s, q1);
+    gemm_f64(s, q2);
+  }
+  // Q0 = [Q_- Q_+]
+  fill_zero(s, z[6], b.S);
+  scatter_rows(s, z[3], npm, 1, pm, rm, rm, z[6], np, 0);
+  scatter_rows(s, z[5], npp, 0, pp, rp, rm, z[6], np, 0);
+  scatter_rows(s, z[0], npp, 1, pp, rp, rp, z[6], np, rm);
+  scatter_rows(s, z[2], npm, 0, pm, rm, rp, z[6], np, rm);
+  // one Cholesky-QR pass: Q0 <- Q0 chol(Q0^T Q0)^{-1}
+  {
+    GemmProblem pg = gemm_problem(np, np, np, z[6], np, 1, z[6], np, 0, b.g, np, 1.0, 0.0,
+                                  nullptr, 0, kOutUpper);
+    auto_split(pg, b.splitws);
+    gemm_f64(s, pg);
+    spd_pad(s, b.g, z[7], n, np, 0.0);
+    potrf_inv_f64(s, z[7], 0, w[2], 0, b.tmp, np, 1, b.dinfo + 6);
+    GemmProblem pq = gemm_problem(np, np, np, z[6], np, 0, w[2], np, 0, b.x0, np, 1.0, 0.0,
+                                  nullptr, 0, kBUpper);
+    gemm_f64(s, pq);
+    mask_pad(s, b.x0, n, np, Sn, 1);
+  }
+  // V_sub <- V_sub Q0
+  {
+    GemmProblem pv = gemm_problem(mp, np, np, e.vs, mp, 0, b.x0, np, 0, e.t, mp);
+    gemm_f64(s, pv);
+    put_cols(s, e.t, mp, e.vacc, mp, o, n, mp);
+  }
+  PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  const int* di = (const int*)pin;
+  if (di[4] || di[5] || di[6]) return PS_BASIS_BREAKDOWN;
+  *rminus = rm;
+  return PS_OK;
+}
+
+int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* lam,
+            double* V, int ldv, const ps_opts& o, ps_info* info) {
+  hipStream_t s = h->stream;
+  char* base = workspace_base(h, workspace_bytes(m, o, 2));
+  if (!base) return PS_NO_WORKSPACE;
+  const int mp = pad_to(m);
+  const size_t S = (size_t)mp * mp;
+  Arena ea;
+  ea.base = base;
+  ea.off = eig_region_offset(m, o);
+  ea.dry = false;
+  EigBuffers e;
+  carve_eig(ea, e, m);
+  double* pin = h->pinned;
+  // ---- one spectral division step (Alg. 3 with Alg. 6 bases)
+  ps_info inf{};
+  int st = run(h, m, A, lda, B, ldb, e.qf, 2 * m, e.hraw, m, o, &inf, 1);
+  if (st != PS_OK) {
+    if (info) *info = inf;
+    return st;
+  }
+  copy_pad(s, e.qf, 2 * m, m, m, e.qt, mp, mp, mp);
+  copy_pad(s, e.qf + m, 2 * m, m, m, e.qb, mp, mp, mp);
+  copy_pad(s, e.hraw, m, m, m, e.hs, mp, mp, mp);
+  // ---- Alg. 2 on H_+: splits down to leaves of at most kLeaf
+  fill_zero(s, e.vacc, S);
+  shift_diag(s, e.vacc, mp, m, 1.0);
+  std::vector<std::pair<int, int>> stack{{0, m}}, leaves;
+  while (!stack.empty()) {
+    const auto [o0, n0] = stack.back();
+    stack.pop_back();
+    if (n0 <= kLeaf) {
+      leaves.push_back({o0, n0});
+      continue;
+    }
+    int rm = 0;
+    st = eig_split(s, base, e, m, o0, n0, o, pin, inf, &rm);
+    if (st != PS_OK) {
+      inf.status = st;
+      inf.failed_step = 5;
+      if (info) *info = inf;
+      return st;
+    }
+    inf.eig_splits += 1;
+    stack.push_back({o0 + rm, n0 - rm});   // upper part, processed after the lower one
+    stack.push_back({o0, rm});
+  }
+  // ---- leaves: B = V^T H_+ V is block diagonal up to rounding; Jacobi on its blocks
+  {
+    GemmProblem pt = gemm_problem(mp, mp, mp, e.hs, mp, 0, e.vacc, mp, 0, e.t, mp);
+    gemm_f64(s, pt);
+    GemmProblem pb = gemm_problem(mp, mp, mp, e.vacc, mp, 1, e.t, mp, 0, e.vs, mp, 1.0, 0.0,
+                                  nullptr, 0, kOutUpper | kMirror);
+    gemm_f64(s, pb);
+  }
+  const int nl = (int)leaves.size();
+  int* ipin = (int*)pin;
+  for (int l = 0; l < nl; ++l) {
+    ipin[l] = leaves[l].first;
+    ipin[nl + l] = leaves[l].second;
+  }
+  PS_HIP(hipMemcpyAsync(e.leaf_o, ipin, nl * sizeof(int), hipMemcpyHostToDevice, s));
+  PS_HIP(hipMemcpyAsync(e.leaf_n, ipin + nl, nl * sizeof(int), hipMemcpyHostToDevice, s));
+  fill_int_zero(s, e.sweeps, 16);
+  fill_zero(s, e.zbd, S);
+  jacobi_leaves(s, e.vs, mp, e.leaf_o, e.leaf_n, nl, e.zbd, mp, e.w, e.sweeps);
+  {
+    GemmProblem pz = gemm_problem(mp, mp, mp, e.vacc, mp, 0, e.zbd, mp, 0, e.t, mp);
+    gemm_f64(s, pz);
+  }
+  // ---- ascending order (the splits already order the blocks; this is a check)
+  PS_HIP(hipMemcpyAsync(pin, e.w, m * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipMemcpyAsync(pin + m, e.sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  inf.eig_leaves = nl;
+  inf.eig_sweeps = *(int*)(pin + m);
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  {
+    std::vector<double> wv(pin, pin + m);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return wv[x] < wv[y]; });
+  }
+  bool sorted = true;
+  for (int i = 0; i < m; ++i) sorted = sorted && ord[i] == i;
+  const double* wfin = e.w;
+  const double* vfin = e.t;
+  if (!sorted) {
+    for (int i = 0; i < m; ++i) ipin[i] = ord[i];
+    PS_HIP(hipMemcpyAsync(e.perm, ipin, m * sizeof(int), hipMemcpyHostToDevice, s));
+    permute_vec(s, e.w, e.perm, m, e.wsorted);
+    permute_cols(s, e.t, mp, e.perm, mp, m, e.vs, mp);
+    wfin = e.wsorted;
+    vfin = e.vs;
+  }
+  eig_lambda(s, wfin, m, lam);
+  if (V) {
+    // V = [Q_+ Z, Pi Q_+ Z], Q_+ = [Qt; Qb]
+    double* vt = (vfin == e.t) ? e.vs : e.t;
+    GemmProblem p1 = gemm_problem(mp, mp, mp, e.qt, mp, 0, vfin, mp, 0, vt, mp);
+    gemm_f64(s, p1);
+    copy_out(s, vt, mp, V, ldv, m, m);
+    GemmProblem p2 = gemm_problem(mp, mp, mp, e.qb, mp, 0, vfin, mp, 0, vt, mp);
+    gemm_f64(s, p2);
+    copy_out(s, vt, mp, V + m, ldv, m, m);
+    pi_columns(s, V, ldv, m);
+    canon_sign(s, V, ldv, 2 * m, 2 * m);
+  }
+  PS_HIP(hipStreamSynchronize(s));
   inf.status = PS_OK;
   if (info) *info = inf;
   return PS_OK;
@@ -708,6 +1043,20 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
   if (opts) o = *opts;
   o.max_steps = 0;
   return guarded(h, [&] { return run(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, info, 1); });
+}
+
+int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                  double* lambda, double* V, int ldv, const ps_opts* opts, ps_info* info) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (!lambda) return -7;
+  if (V && ldv < 2 * m) return -9;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  o.timing = 0;
+  return guarded(h, [&] { return run_eig(h, m, A, lda, B, ldb, lambda, V, ldv, o, info); });
 }
 
 const char* ps_status_string(int st) {

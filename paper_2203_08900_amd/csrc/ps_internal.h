@@ -123,6 +123,34 @@ void copy_out(hipStream_t s, const double* x, int ldx, double* y, int ldy, int r
               int cols);
 void diff_norms(hipStream_t s, const double* x1, const double* x2, size_t n, double* out2);
 
+// eigen-decomposition helpers (eig_f64.hip)
+void shift_diag(hipStream_t s, double* y, int ld, int n, double b);   // y(i,i) += b, i < n
+// z = upper(g) + c I on the first n diagonal entries, 1 on the padded diagonal
+void spd_pad(hipStream_t s, const double* g, double* z, int n, int np, double c);
+void get_diag(hipStream_t s, const double* x, int ld, int n, double* out);
+// dst(i,j) = src(i,j) for i < rows, j < cols, 0 elsewhere in rows_pad x cols_pad
+void copy_pad(hipStream_t s, const double* src, int lds, int rows, int cols, double* dst,
+              int ldd, int rows_pad, int cols_pad);
+void put_cols(hipStream_t s, const double* src, int lds, double* dst, int ldd, int o, int n,
+              int rows);   // dst(:, o + j) = src(:, j), j < n
+// dst(i,j) = sc src(ri[i], ci[j]) + dg [ri[i] == ci[j]] on rows x cols; padval on the
+// padded diagonal, 0 elsewhere; upper_only: 0 below the diagonal
+void gather_sym(hipStream_t s, const double* src, int lds, const int* ri, const int* ci, int rows,
+                int cols, double sc, double dg, double* dst, int ldd, int rows_pad, int cols_pad,
+                double padval, int upper_only);
+// dst(ri[i], c0 + j) = trans ? src(j, i) : src(i, j)
+void scatter_rows(hipStream_t s, const double* src, int lds, int trans, const int* ri, int rows,
+                  int cols, double* dst, int ldd, int c0);
+void permute_cols(hipStream_t s, const double* src, int lds, const int* perm, int rows, int cols,
+                  double* dst, int ldd);
+void permute_vec(hipStream_t s, const double* src, const int* perm, int n, double* dst);
+void eig_lambda(hipStream_t s, const double* w, int m, double* lam);
+void pi_columns(hipStream_t s, double* v, int ldv, int m);
+void canon_sign(hipStream_t s, double* v, int ldv, int rows, int cols);
+void jacobi_leaves(hipStream_t s, const double* b, int ld, const int* leaf_o, const int* leaf_n,
+                   int nleaves, double* z, int ldz, double* lam, int* sweeps_out);
+void fill_int_zero(hipStream_t s, int* x, int n);
+
 // Golub-Kahan bidiagonalization (batch of two matrices M_b with transposes Mt_b).
 void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned seed);
 void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
