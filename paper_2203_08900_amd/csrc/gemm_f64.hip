@@ -3,10 +3,11 @@
 // A workgroup computes a BM x BN tile of D = alpha op(A) op(B) + beta C; its waves
 // own (BM/WM) x (BN/WN) sub-tiles as MFMA 16x16 fragments.  Two shapes: 128 x 128 with
 // 8 waves of 64 x 32 (16 flops per byte loaded, two waves per SIMD) for large problems
-// and 64 x 64 with 4 waves of 32 x 32 for small ones.  Operand transposes are
-// template parameters; a group of problems is launched once per transpose pair.  K advances in steps of 16 through two LDS buffers (one
-// barrier per step); the next step's global loads are issued before the MFMAs of
-// the current step.
+// and 64 x 64 with 4 waves of 32 x 32 for small ones.  A group of up to four
+// independent problems (any operand transposes) shares one launch, so that problems
+// whose tile counts alone would leave compute units idle fill the machine together.
+// K advances in steps of 16 through two LDS buffers (one barrier per step); the next
+// step's global loads are issued before the MFMAs of the current step.
 //
 // LDS layouts per operand keep global loads coalesced along the contiguous
 // dimension and fragment reads on distinct banks:
@@ -48,30 +49,25 @@ __device__ inline void tri_index(int t, int& hi, int& lo) {
 
 }  // namespace
 
+template <int BM, int BN>
+struct GemmLds {
+  static constexpr int LDKM = BM + 16;
+  static constexpr int LDKN = BN + 16;
+  static constexpr int ASZ = (BK * LDKM > BM * LDIK) ? BK * LDKM : BM * LDIK;
+  static constexpr int BSZ = (BK * LDKN > BN * LDIK) ? BK * LDKN : BN * LDIK;
+};
+
+// One output tile of problem P (logical tile index bid within the launch).
 template <int BM, int BN, int WM, int WN, int TA, int TB>
-__global__ __launch_bounds__(WM * WN * 64) void gemm_f64_kernel(GemmGroup g) {
+__device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
+                                          double (*As)[GemmLds<BM, BN>::ASZ],
+                                          double (*Bs)[GemmLds<BM, BN>::BSZ]) {
   constexpr int NT = WM * WN * 64;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
-  constexpr int LDKM = BM + 16;
-  constexpr int LDKN = BN + 16;
-  constexpr int ASZ = (BK * LDKM > BM * LDIK) ? BK * LDKM : BM * LDIK;
-  constexpr int BSZ = (BK * LDKN > BN * LDIK) ? BK * LDKN : BN * LDIK;
+  constexpr int LDKM = GemmLds<BM, BN>::LDKM;
+  constexpr int LDKN = GemmLds<BM, BN>::LDKN;
   constexpr int APT = BM * BK / NT;
   constexpr int BPT = BN * BK / NT;
-  __shared__ double As[2][ASZ];
-  __shared__ double Bs[2][BSZ];
-
-  int bid = blockIdx.x;
-  if (g.remap) {
-    // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
-    // contiguous range of logical tiles [x * total/8, (x+1) * total/8).
-    const int per = g.total >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
-  }
-  int pi = 0;
-  while (pi + 1 < g.count && bid >= g.p[pi + 1].tile_begin) ++pi;
-  const GemmProblem& P = g.p[pi];
-
   const int local = bid - P.tile_begin;
   const int z = local / P.tiles_per_batch;
   const int tz = local - z * P.tiles_per_batch;
@@ -242,6 +238,33 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_f64_kernel(GemmGroup g) {
       }
 }
 
+// The operand transposes are per problem, so one launch covers a group of problems
+// with different transposes (each workgroup branches once, uniformly).
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_f64_kernel(GemmGroup g) {
+  __shared__ double As[2][GemmLds<BM, BN>::ASZ];
+  __shared__ double Bs[2][GemmLds<BM, BN>::BSZ];
+  int bid = blockIdx.x;
+  if (g.remap) {
+    // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
+    // contiguous range of logical tiles [x * total/8, (x+1) * total/8).
+    const int per = g.total >> 3;
+    bid = (bid & 7) * per + (bid >> 3);
+  }
+  int pi = 0;
+  while (pi + 1 < g.count && bid >= g.p[pi + 1].tile_begin) ++pi;
+  const GemmProblem& P = g.p[pi];
+  const int v = P.tA * 2 + P.tB;
+  if (v == 0)
+    gemm_tile<BM, BN, WM, WN, 0, 0>(P, bid, As, Bs);
+  else if (v == 1)
+    gemm_tile<BM, BN, WM, WN, 0, 1>(P, bid, As, Bs);
+  else if (v == 2)
+    gemm_tile<BM, BN, WM, WN, 1, 0>(P, bid, As, Bs);
+  else
+    gemm_tile<BM, BN, WM, WN, 1, 1>(P, bid, As, Bs);
+}
+
 // D = sum_s partial_s + beta C with the triangle / mirror conventions of the GEMM
 __global__ void gemm_split_reduce_kernel(GemmProblem P) {
   const long long M = P.M, N = P.N;
@@ -292,14 +315,13 @@ GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
 namespace {
 GemmRecorder* g_rec = nullptr;
 
-template <int BM, int BN, int WM, int WN, int TA, int TB>
-void launch_one(hipStream_t s, const GemmProblem* probs, int count) {
+template <int BM, int BN, int WM, int WN>
+void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
   GemmGroup g{};
   int total = 0;
   for (int q = 0; q < count; ++q) {
     GemmProblem p = probs[q];
     if (p.M <= 0 || p.N <= 0 || p.nb1 <= 0 || p.nb2 <= 0) continue;
-    if (p.tA != TA || p.tB != TB) continue;
     p.tm = p.M / BM;
     p.tn = p.N / BN;
     p.tiles = (p.flags & (kOutUpper | kOutLower)) ? p.tm * (p.tm + 1) / 2 : p.tm * p.tn;
@@ -313,7 +335,7 @@ void launch_one(hipStream_t s, const GemmProblem* probs, int count) {
   g.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
   const bool rec = BM == 128 && g_rec && g_rec->n < g_rec->cap;
   if (rec) PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n], s));
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB>), dim3(total), dim3(WM * WN * 64),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN>), dim3(total), dim3(WM * WN * 64),
                      0, s, g);
   PS_HIP(hipGetLastError());
   if (rec) {
@@ -334,13 +356,6 @@ void launch_one(hipStream_t s, const GemmProblem* probs, int count) {
   }
 }
 
-template <int BM, int BN, int WM, int WN>
-void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
-  launch_one<BM, BN, WM, WN, 0, 0>(s, probs, count);
-  launch_one<BM, BN, WM, WN, 0, 1>(s, probs, count);
-  launch_one<BM, BN, WM, WN, 1, 0>(s, probs, count);
-  launch_one<BM, BN, WM, WN, 1, 1>(s, probs, count);
-}
 }  // namespace
 
 void gemm_set_recorder(GemmRecorder* r) { g_rec = r; }
