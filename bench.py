@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--m", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--r", type=int, default=8)
-    ap.add_argument("--modes", default="fp64")
+    ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain device copy of 512 MiB three times (calibrates the "
@@ -213,7 +213,7 @@ def main():
                 "frac": achieved / PEAK["f64"],
                 "traffic": traffic_from_profile(os.path.join(
                     ROOT, "paper_2203_08900_amd", "csrc", "gemm_f64.hip")),
-                "kernel": "gemm_f64_kernel<128,128> (all transposes)",
+                "kernel": "gemm_mfma_kernel<double,128,128,2,4>",
                 "launches_per_step": gm["launches"] / args.steps,
                 "avg_launch_ms": gm["ms"] / gm["launches"],
                 "flops_per_launch": gm["flops"] / gm["launches"]}

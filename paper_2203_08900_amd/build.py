@@ -21,6 +21,7 @@ SOURCES = [
     "chol_f64.hip",
     "misc_f64.hip",
     "eig_f64.hip",
+    "mixed.hip",
     "zolo_host.cpp",
     "pipeline.cpp",
 ]

@@ -1,4 +1,5 @@
-// Batched FP64 Cholesky factorization with the inverse factor, Z = R^T R, W = R^{-1}.
+// Batched Cholesky factorization with the inverse factor, Z = R^T R, W = R^{-1}, in FP64
+// or FP32 (one template).
 //
 // Blocked right-looking algorithm over 64 x 64 diagonal blocks.  Per block step k:
 //   1. one workgroup per matrix factors the diagonal block and inverts it;
@@ -43,14 +44,15 @@ __device__ inline double rcp_nr(double x) {
   return y;
 }
 
-__device__ inline void chol4(double d[4][4], double w[4][4], bool& bad) {
+template <class T>
+__device__ inline void chol4(T d[4][4], T w[4][4], bool& bad) {
   // upper Cholesky of the 4 x 4 block d (upper triangle used) and w = R_d^{-1}
-  double rinv[4];
+  T rinv[4];
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
-    const double piv = d[p][p];
-    if (!(piv > 0.0)) bad = true;
-    const double ri = piv > 0.0 ? rsqrt_nr(piv) : 0.0;
+    const T piv = d[p][p];
+    if (!(piv > T(0))) bad = true;
+    const T ri = piv > T(0) ? (T)rsqrt_nr((double)piv) : T(0);
     rinv[p] = ri;
     d[p][p] = piv * ri;
 #pragma unroll
@@ -63,48 +65,48 @@ __device__ inline void chol4(double d[4][4], double w[4][4], bool& bad) {
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < x; ++y) d[x][y] = 0.0;
+    for (int y = 0; y < x; ++y) d[x][y] = T(0);
   // w = R_d^{-1}: columns by back substitution with the reciprocal diagonal
 #pragma unroll
   for (int y = 0; y < 4; ++y) {
 #pragma unroll
     for (int x = 3; x >= 0; --x) {
-      double acc = (x == y) ? 1.0 : 0.0;
+      T acc = (x == y) ? T(1) : T(0);
 #pragma unroll
       for (int q = x + 1; q < 4; ++q) acc -= d[x][q] * w[q][y];
-      w[x][y] = (x <= y) ? acc * rinv[x] : 0.0;
+      w[x][y] = (x <= y) ? acc * rinv[x] : T(0);
     }
   }
 }
 }  // namespace
 
-__global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz, double* w,
-                                                         long long sw, int ld, int k0,
-                                                         int* info) {
-  __shared__ double panel[4][NB];        // R(kb, :) of the current block row
-  __shared__ double wd[NB / 4][4][4];    // R_d^{-1} of every diagonal block
-  __shared__ double rfull[NB][NB + 1];   // R after the factorization
-  __shared__ double wrow[2][4][NB];      // published block row of W
+template <class T>
+__global__ __launch_bounds__(NTD) void potrf_diag_kernel(T* z, long long sz, T* w, long long sw,
+                                                         int ld, int k0, int* info) {
+  __shared__ T panel[4][NB];        // R(kb, :) of the current block row
+  __shared__ T wd[NB / 4][4][4];    // R_d^{-1} of every diagonal block
+  __shared__ T rfull[NB][NB + 1];   // R after the factorization
+  __shared__ T wrow[2][4][NB];      // published block row of W
   const int b = blockIdx.x;
-  double* Z = z + b * sz + k0 + (long long)k0 * ld;
-  double* W = w + b * sw + k0 + (long long)k0 * ld;
+  T* Z = z + b * sz + k0 + (long long)k0 * ld;
+  T* W = w + b * sw + k0 + (long long)k0 * ld;
   const int tid = threadIdx.x;
   const int bi = tid & 15, bj = tid >> 4;
   const int r0 = 4 * bi, c0 = 4 * bj;
   const bool active = bi <= bj;
-  double v[4][4];
+  T v[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int i = r0 + x, j = c0 + y;
-      v[x][y] = (active && i <= j) ? Z[i + (long long)j * ld] : 0.0;
+      v[x][y] = (active && i <= j) ? Z[i + (long long)j * ld] : T(0);
     }
   bool bad = false;
   for (int kb = 0; kb < NB / 4; ++kb) {
     // 1. diagonal block
     if (bi == kb && bj == kb) {
-      double wl[4][4];
+      T wl[4][4];
       chol4(v, wl, bad);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
@@ -121,12 +123,12 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
         for (int y = 0; y < 4; ++y) panel[x][c0 + y] = v[x][y];
     }
     if (bi == kb && bj > kb) {
-      double r[4][4];
+      T r[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-          double acc = 0.0;
+          T acc = T(0);
 #pragma unroll
           for (int p = 0; p <= x; ++p) acc += wd[kb][p][x] * v[p][y];
           r[x][y] = acc;
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
     __syncthreads();
     // 3. trailing update
     if (active && bi > kb) {
-      double ra[4][4], rb[4][4];
+      T ra[4][4], rb[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-          double acc = v[x][y];
+          T acc = v[x][y];
 #pragma unroll
           for (int p = 0; p < 4; ++p) acc -= ra[p][x] * rb[p][y];
           v[x][y] = acc;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int i = r0 + x, j = c0 + y;
-      const double rv = (active && i <= j) ? v[x][y] : 0.0;
+      const T rv = (active && i <= j) ? v[x][y] : T(0);
       v[x][y] = rv;
       rfull[i][j] = rv;
       Z[i + (long long)j * ld] = rv;
@@ -179,17 +181,17 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) v[x][y] = (r0 + x == c0 + y) ? 1.0 : 0.0;
+    for (int y = 0; y < 4; ++y) v[x][y] = (r0 + x == c0 + y) ? T(1) : T(0);
   __syncthreads();
   for (int lb = NB / 4 - 1; lb >= 0; --lb) {
     const int buf = lb & 1;
     if (bi == lb && bj >= lb) {
-      double t[4][4];
+      T t[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-          double acc = 0.0;
+          T acc = T(0);
 #pragma unroll
           for (int p = x; p < 4; ++p) acc += wd[lb][x][p] * v[p][y];
           t[x][y] = acc;
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
     }
     __syncthreads();
     if (bi < lb && bj >= lb) {
-      double rc[4][4], wr[4][4];
+      T rc[4][4], wr[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-          double acc = v[x][y];
+          T acc = v[x][y];
 #pragma unroll
           for (int p = 0; p < 4; ++p) acc -= rc[x][p] * wr[p][y];
           v[x][y] = acc;
@@ -229,12 +231,16 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(double* z, long long sz
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int i = r0 + x, j = c0 + y;
-      W[i + (long long)j * ld] = (active && i <= j) ? v[x][y] : 0.0;
+      W[i + (long long)j * ld] = (active && i <= j) ? v[x][y] : T(0);
     }
 }
 
-void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
-                   double* /*tmp*/, int mp, int batch, int* info) {
+inline void gemm_t(hipStream_t s, const GemmProblem* p, int n) { gemm_f64(s, p, n); }
+inline void gemm_t(hipStream_t s, const GemmProblemF* p, int n) { gemm_f32(s, p, n); }
+
+template <class T>
+void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, int batch,
+                 int* info) {
   zero_lower(s, w, mp, sw, batch);  // the diagonal blocks and W12 blocks cover the rest
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
   const int nbk = mp / NB;
@@ -242,31 +248,31 @@ void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long 
   for (int k = 0; k < nbk; ++k) {
     const int k0 = k * NB;
     const int rest = mp - k0 - NB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(batch), dim3(NTD), 0, s, z, sz, w, sw, mp, k0,
+    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(batch), dim3(NTD), 0, s, z, sz, w, sw, mp, k0,
                        info);
     PS_HIP(hipGetLastError());
     if (rest <= 0) break;
-    double* wkk = w + k0 + (long long)k0 * mp;
-    double* zr = z + k0 + (long long)(k0 + NB) * mp;
-    double* zt = z + (k0 + NB) + (long long)(k0 + NB) * mp;
+    T* wkk = w + k0 + (long long)k0 * mp;
+    T* zr = z + k0 + (long long)(k0 + NB) * mp;
+    T* zt = z + (k0 + NB) + (long long)(k0 + NB) * mp;
     // panel R(k, k+1:) = R_kk^{-T} Z(k, k+1:), in place (each tile reads its own columns)
-    GemmProblem pp = gemm_problem(NB, rest, NB, wkk, mp, 1, zr, mp, 0, zr, mp, 1.0, 0.0, nullptr,
+    GemmProblemT<T> pp = gemm_problem(NB, rest, NB, wkk, mp, 1, zr, mp, 0, zr, mp, 1.0, 0.0, nullptr,
                                   0, kALower);
     pp.nb1 = batch;
     pp.sA[0] = sw;
     pp.sB[0] = sz;
     pp.sC[0] = sz;
     pp.sD[0] = sz;
-    gemm_f64(s, pp);
+    gemm_t(s, &pp, 1);
     // trailing update Z(k+1:, k+1:) -= R(k, k+1:)^T R(k, k+1:)  (upper triangle)
-    GemmProblem pt = gemm_problem(rest, rest, NB, zr, mp, 1, zr, mp, 0, zt, mp, -1.0, 1.0, zt, mp,
+    GemmProblemT<T> pt = gemm_problem(rest, rest, NB, zr, mp, 1, zr, mp, 0, zt, mp, -1.0, 1.0, zt, mp,
                                   kOutUpper);
     pt.nb1 = batch;
     pt.sA[0] = sz;
     pt.sB[0] = sz;
     pt.sC[0] = sz;
     pt.sD[0] = sz;
-    gemm_f64(s, pt);
+    gemm_t(s, &pt, 1);
   }
   // ---- W = R^{-1} by recursive doubling over the block diagonal: at level S every
   // diagonal block of size S is already inverted, and for each pair of neighbours
@@ -278,19 +284,19 @@ void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long 
     const int full = mp / (2 * S);               // pairs whose right block has size S
     const int rem = mp - full * 2 * S;           // leftover rows after the full pairs
     const long long pstride = (long long)2 * S * (mp + 1);
-    GemmProblem t1[2], t2[2];
+    GemmProblemT<T> t1[2], t2[2];
     int n1 = 0;
     auto add_pair = [&](long long off, int sr, int nb2) {
-      double* w11 = w + off;
-      double* w22 = w + off + (long long)S * (mp + 1);
-      double* w21 = w + off + S;                  // rows right, cols left (sr x S)
-      double* w12 = w + off + (long long)S * mp;  // rows left, cols right (S x sr)
-      const double* r12 = z + off + (long long)S * mp;
-      GemmProblem a = gemm_problem(sr, S, sr, w22, mp, 1, r12, mp, 1, w21, mp, 1.0, 0.0, nullptr,
+      T* w11 = w + off;
+      T* w22 = w + off + (long long)S * (mp + 1);
+      T* w21 = w + off + S;                  // rows right, cols left (sr x S)
+      T* w12 = w + off + (long long)S * mp;  // rows left, cols right (S x sr)
+      const T* r12 = z + off + (long long)S * mp;
+      GemmProblemT<T> a = gemm_problem(sr, S, sr, w22, mp, 1, r12, mp, 1, w21, mp, 1.0, 0.0, nullptr,
                                    0, kALower);
-      GemmProblem b = gemm_problem(S, sr, S, w11, mp, 0, w21, mp, 1, w12, mp, -1.0, 0.0, nullptr,
+      GemmProblemT<T> b = gemm_problem(S, sr, S, w11, mp, 0, w21, mp, 1, w12, mp, -1.0, 0.0, nullptr,
                                    0, kAUpper);
-      for (GemmProblem* q : {&a, &b}) {
+      for (GemmProblemT<T>* q : {&a, &b}) {
         q->nb1 = batch;
         q->sA[0] = (q == &a) ? sw : sw;
         q->sB[0] = (q == &a) ? sz : sw;
@@ -306,13 +312,23 @@ void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long 
     if (full > 0) add_pair(0, S, full);
     if (rem > S) add_pair((long long)full * pstride, rem - S, 1);
     if (n1) {
-      gemm_f64(s, t1, n1);
-      gemm_f64(s, t2, n1);
+      gemm_t(s, t1, n1);
+      gemm_t(s, t2, n1);
       for (int q = 0; q < n1; ++q)
-        zero_block(s, const_cast<double*>(t2[q].B), t2[q].N, t2[q].K, mp, batch, sw, t2[q].nb2,
+        zero_block(s, const_cast<T*>(t2[q].B), t2[q].N, t2[q].K, mp, batch, sw, t2[q].nb2,
                    pstride);
     }
   }
+}
+
+void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
+                   double* /*tmp*/, int mp, int batch, int* info) {
+  potrf_inv_t(s, z, sz, w, sw, mp, batch, info);
+}
+
+void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,
+                   int batch, int* info) {
+  potrf_inv_t(s, z, sz, w, sw, mp, batch, info);
 }
 
 }  // namespace ps

@@ -1,4 +1,5 @@
-// FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
+// GEMM on CDNA4 matrix cores: FP64 (v_mfma_f64_16x16x4_f64) and FP32
+// (v_mfma_f32_16x16x4_f32), one templated kernel.
 //
 // A workgroup computes a BM x BN tile of D = alpha op(A) op(B) + beta C; its waves
 // own (BM/WM) x (BN/WN) sub-tiles as MFMA 16x16 fragments.  Two shapes: 128 x 128 with
@@ -22,15 +23,41 @@
 // lane l is D(4v + l/16, l%16).
 #include "ps_internal.h"
 
+#include <type_traits>
+
 namespace ps {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
+template <class T>
 struct GemmGroup {
   int count;
   int remap;   // nonzero: spread consecutive tiles over one XCD (8 XCDs, round-robin dispatch)
   int total;
-  GemmProblem p[kMaxGroup];
+  GemmProblemT<T> p[kMaxGroup];
+};
+
+// Matrix-core step and accumulator layout per element type (checked on the device):
+// both take A(l%16, l/16) and B(l/16, l%16) from lane l; accumulator element v of
+// lane l is D(4v + l/16, l%16) for FP64 and D(4(l/16) + v, l%16) for FP32.
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using acc_t = d4;
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  using acc_t = f4;
+  __device__ static acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int v) { return 4 * lk + v; }
 };
 
 namespace {
@@ -58,10 +85,10 @@ struct GemmLds {
 };
 
 // One output tile of problem P (logical tile index bid within the launch).
-template <int BM, int BN, int WM, int WN, int TA, int TB>
-__device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
-                                          double (*As)[GemmLds<BM, BN>::ASZ],
-                                          double (*Bs)[GemmLds<BM, BN>::BSZ]) {
+template <class T, int BM, int BN, int WM, int WN, int TA, int TB>
+__device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
+                                          T (*As)[GemmLds<BM, BN>::ASZ],
+                                          T (*Bs)[GemmLds<BM, BN>::BSZ]) {
   constexpr int NT = WM * WN * 64;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
   constexpr int LDKM = GemmLds<BM, BN>::LDKM;
@@ -83,10 +110,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
     J = t / P.tm;
   }
   const int z1 = z % P.nb1, z2 = z / P.nb1;
-  const double* __restrict__ A = P.A + z1 * P.sA[0] + z2 * P.sA[1];
-  const double* __restrict__ B = P.B + z1 * P.sB[0] + z2 * P.sB[1];
-  double* D = P.D + z1 * P.sD[0] + z2 * P.sD[1];
-  const double* C = P.C ? P.C + z1 * P.sC[0] + z2 * P.sC[1] : nullptr;
+  const T* __restrict__ A = P.A + z1 * P.sA[0] + z2 * P.sA[1];
+  const T* __restrict__ B = P.B + z1 * P.sB[0] + z2 * P.sB[1];
+  T* D = P.D + z1 * P.sD[0] + z2 * P.sD[1];
+  const T* C = P.C ? P.C + z1 * P.sC[0] + z2 * P.sC[1] : nullptr;
 
   const int i0 = I * BM, j0 = J * BN;
   const int flags = P.flags;
@@ -111,13 +138,14 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
   constexpr int tA = TA, tB = TB;
   const long long lda = P.lda, ldb = P.ldb;
 
-  d4 acc[FM][FN];
+  using acc_t = typename Mfma<T>::acc_t;
+  acc_t acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-  double ra[APT], rb[BPT];
+  T ra[APT], rb[BPT];
 
   auto load = [&](int kt) {
     const int s = kt / per;
@@ -128,10 +156,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
       const int idx = tid + p * NT;
       if (!tA) {
         const int i = idx % BM, k = idx / BM;
-        ra[p] = A[(i0 + i) + (long long)(k0 + k) * lda] * sc;
+        ra[p] = (T)(A[(i0 + i) + (long long)(k0 + k) * lda] * sc);
       } else {
         const int k = idx % BK, i = idx / BK;
-        ra[p] = A[(k0 + k) + (long long)(i0 + i) * lda] * sc;
+        ra[p] = (T)(A[(k0 + k) + (long long)(i0 + i) * lda] * sc);
       }
     }
 #pragma unroll
@@ -181,7 +209,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
         const int k = kk * 4 + lk;
-        double av[FM], bv[FN];
+        T av[FM], bv[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a) {
           const int i = wm * FM * 16 + a * 16 + li;
@@ -196,7 +224,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
         for (int a = 0; a < FM; ++a)
 #pragma unroll
           for (int b = 0; b < FN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
       }
       if (kt + 1 < kt_end) store(buf ^ 1);
       __syncthreads();
@@ -206,7 +234,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
   const double alpha = P.alpha, beta = P.beta;
   if (P.ksplit > 1) {
     // partial tile of split ks (batch extent is 1 for split problems)
-    double* W = P.ws + (long long)ks * P.M * P.N;
+    T* W = P.ws + (long long)ks * P.M * P.N;
     const long long M = P.M;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
@@ -214,9 +242,9 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = i0 + wm * FM * 16 + a * 16 + lk + 4 * v;
+          const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
           const int j = j0 + wn * FN * 16 + b * 16 + li;
-          W[i + j * M] = alpha * acc[a][b][v];
+          W[i + j * M] = (T)(alpha * acc[a][b][v]);
         }
     return;
   }
@@ -227,23 +255,23 @@ __device__ __forceinline__ void gemm_tile(const GemmProblem& P, int bid,
     for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wm * FM * 16 + a * 16 + lk + 4 * v;  // D(4v + lane/16, lane%16)
+        const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
         const int j = j0 + wn * FN * 16 + b * 16 + li;
         if ((flags & kOutUpper) && i > j) continue;
         if ((flags & kOutLower) && i < j) continue;
         double val = alpha * acc[a][b][v];
         if (beta != 0.0) val += beta * C[i + j * ldc];
-        D[i + j * ldd] = val;
-        if ((flags & kMirror) && i != j) D[j + i * ldd] = val;
+        D[i + j * ldd] = (T)val;
+        if ((flags & kMirror) && i != j) D[j + i * ldd] = (T)val;
       }
 }
 
 // The operand transposes are per problem, so one launch covers a group of problems
 // with different transposes (each workgroup branches once, uniformly).
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(WM * WN * 64) void gemm_f64_kernel(GemmGroup g) {
-  __shared__ double As[2][GemmLds<BM, BN>::ASZ];
-  __shared__ double Bs[2][GemmLds<BM, BN>::BSZ];
+template <class T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g) {
+  __shared__ T As[2][GemmLds<BM, BN>::ASZ];
+  __shared__ T Bs[2][GemmLds<BM, BN>::BSZ];
   int bid = blockIdx.x;
   if (g.remap) {
     // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
@@ -253,20 +281,21 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_f64_kernel(GemmGroup g) {
   }
   int pi = 0;
   while (pi + 1 < g.count && bid >= g.p[pi + 1].tile_begin) ++pi;
-  const GemmProblem& P = g.p[pi];
+  const GemmProblemT<T>& P = g.p[pi];
   const int v = P.tA * 2 + P.tB;
   if (v == 0)
-    gemm_tile<BM, BN, WM, WN, 0, 0>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 0, 0>(P, bid, As, Bs);
   else if (v == 1)
-    gemm_tile<BM, BN, WM, WN, 0, 1>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 0, 1>(P, bid, As, Bs);
   else if (v == 2)
-    gemm_tile<BM, BN, WM, WN, 1, 0>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 1, 0>(P, bid, As, Bs);
   else
-    gemm_tile<BM, BN, WM, WN, 1, 1>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 1, 1>(P, bid, As, Bs);
 }
 
 // D = sum_s partial_s + beta C with the triangle / mirror conventions of the GEMM
-__global__ void gemm_split_reduce_kernel(GemmProblem P) {
+template <class T>
+__global__ void gemm_split_reduce_kernel(GemmProblemT<T> P) {
   const long long M = P.M, N = P.N;
   const long long n = M * N;
   const long long MN = M * N;
@@ -278,15 +307,16 @@ __global__ void gemm_split_reduce_kernel(GemmProblem P) {
     double val = 0.0;
     for (int s = 0; s < P.ksplit; ++s) val += P.ws[s * MN + e];
     if (P.beta != 0.0) val += P.beta * P.C[i + (long long)j * P.ldc];
-    P.D[i + (long long)j * P.ldd] = val;
-    if ((P.flags & kMirror) && i != j) P.D[j + (long long)i * P.ldd] = val;
+    P.D[i + (long long)j * P.ldd] = (T)val;
+    if ((P.flags & kMirror) && i != j) P.D[j + (long long)i * P.ldd] = (T)val;
   }
 }
 
-GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
-                         const double* B, int ldb, int tB, double* D, int ldd, double alpha,
-                         double beta, const double* C, int ldc, int flags) {
-  GemmProblem p{};
+template <class T>
+GemmProblemT<T> make_problem(int M, int N, int K, const T* A, int lda, int tA, const T* B, int ldb,
+                             int tB, T* D, int ldd, double alpha, double beta, const T* C, int ldc,
+                             int flags) {
+  GemmProblemT<T> p{};
   p.A = A;
   p.B = B;
   p.C = C ? C : D;
@@ -312,15 +342,27 @@ GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
   return p;
 }
 
+GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA, const double* B,
+                         int ldb, int tB, double* D, int ldd, double alpha, double beta,
+                         const double* C, int ldc, int flags) {
+  return make_problem<double>(M, N, K, A, lda, tA, B, ldb, tB, D, ldd, alpha, beta, C, ldc, flags);
+}
+
+GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, const float* B,
+                          int ldb, int tB, float* D, int ldd, double alpha, double beta,
+                          const float* C, int ldc, int flags) {
+  return make_problem<float>(M, N, K, A, lda, tA, B, ldb, tB, D, ldd, alpha, beta, C, ldc, flags);
+}
+
 namespace {
 GemmRecorder* g_rec = nullptr;
 
-template <int BM, int BN, int WM, int WN>
-void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
-  GemmGroup g{};
+template <class T, int BM, int BN, int WM, int WN>
+void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
+  GemmGroup<T> g{};
   int total = 0;
   for (int q = 0; q < count; ++q) {
-    GemmProblem p = probs[q];
+    GemmProblemT<T> p = probs[q];
     if (p.M <= 0 || p.N <= 0 || p.nb1 <= 0 || p.nb2 <= 0) continue;
     p.tm = p.M / BM;
     p.tn = p.N / BN;
@@ -333,9 +375,9 @@ void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
   if (total == 0) return;
   g.total = total;
   g.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
-  const bool rec = BM == 128 && g_rec && g_rec->n < g_rec->cap;
+  const bool rec = BM == 128 && std::is_same<T, double>::value && g_rec && g_rec->n < g_rec->cap;
   if (rec) PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n], s));
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN>), dim3(total), dim3(WM * WN * 64),
+  hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN>), dim3(total), dim3(WM * WN * 64),
                      0, s, g);
   PS_HIP(hipGetLastError());
   if (rec) {
@@ -346,11 +388,11 @@ void launch_group(hipStream_t s, const GemmProblem* probs, int count) {
     g_rec->n += 1;
   }
   for (int q = 0; q < g.count; ++q) {
-    const GemmProblem& p = g.p[q];
+    const GemmProblemT<T>& p = g.p[q];
     if (p.ksplit > 1) {
       const long long n = (long long)p.M * p.N;
       const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 8192);
-      hipLaunchKernelGGL(gemm_split_reduce_kernel, dim3(nb), dim3(256), 0, s, p);
+      hipLaunchKernelGGL(gemm_split_reduce_kernel<T>, dim3(nb), dim3(256), 0, s, p);
       PS_HIP(hipGetLastError());
     }
   }
@@ -363,7 +405,8 @@ void gemm_set_recorder(GemmRecorder* r) { g_rec = r; }
 // 2 x (number of structurally non-zero products) over the stored output entries.  For
 // each output (i, j) the K range is the intersection of the non-zero bands of op(A) row
 // i and op(B) column j within every segment; the unstored triangle is not counted.
-double gemm_algorithmic_flops(const GemmProblem& p) {
+template <class T>
+double gemm_algorithmic_flops(const GemmProblemT<T>& p) {
   const long long M = p.M, N = p.N;
   const long long segK = p.kseg > 0 ? p.kseg : p.K;
   const long long nseg = p.kseg > 0 ? p.nseg : 1;
@@ -414,12 +457,13 @@ double gemm_algorithmic_flops(const GemmProblem& p) {
   return 2.0 * total * nseg * p.nb1 * p.nb2;
 }
 
-void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) {
+template <class T>
+void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
   bool big = true;
   long long tiles128 = 0;
   int live = 0;
   for (int q = 0; q < count; ++q) {
-    const GemmProblem& p = probs[q];
+    const GemmProblemT<T>& p = probs[q];
     if (p.M <= 0 || p.N <= 0 || p.nb1 <= 0 || p.nb2 <= 0) continue;
     ++live;
     if (p.M % 64 || p.N % 64 || p.K % BK || (p.kseg > 0 && p.kseg % BK))
@@ -437,9 +481,15 @@ void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) {
   }
   if (!live) return;
   if (big && tiles128 >= 128)
-    launch_group<128, 128, 2, 4>(s, probs, count);
+    launch_group<T, 128, 128, 2, 4>(s, probs, count);
   else
-    launch_group<64, 64, 2, 2>(s, probs, count);
+    launch_group<T, 64, 64, 2, 2>(s, probs, count);
 }
+
+template double gemm_algorithmic_flops<double>(const GemmProblem&);
+template double gemm_algorithmic_flops<float>(const GemmProblemF&);
+
+void gemm_f64(hipStream_t s, const GemmProblem* probs, int count) { gemm_any(s, probs, count); }
+void gemm_f32(hipStream_t s, const GemmProblemF* probs, int count) { gemm_any(s, probs, count); }
 
 }  // namespace ps

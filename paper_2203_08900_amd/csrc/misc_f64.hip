@@ -88,40 +88,58 @@ void fill_zero(hipStream_t s, double* x, size_t n) {
   PS_HIP(hipGetLastError());
 }
 
-__global__ void zero_lower_kernel(double* x, int mp, long long stride) {
-  double* X = x + blockIdx.y * stride;
+template <class T>
+__global__ void zero_lower_kernel(T* x, int mp, long long stride) {
+  T* X = x + blockIdx.y * stride;
   const size_t n = (size_t)mp * mp;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % mp), j = (int)(e / mp);
-    if (i > j) X[e] = 0.0;
+    if (i > j) X[e] = T(0);
   }
 }
 
-void zero_lower(hipStream_t s, double* x, int mp, long long stride, int batch) {
-  hipLaunchKernelGGL(zero_lower_kernel, dim3(blocks_for((size_t)mp * mp), batch), dim3(NT), 0, s,
-                     x, mp, stride);
+template <class T>
+void zero_lower_t(hipStream_t s, T* x, int mp, long long stride, int batch) {
+  hipLaunchKernelGGL(zero_lower_kernel<T>, dim3(blocks_for((size_t)mp * mp), batch), dim3(NT), 0,
+                     s, x, mp, stride);
   PS_HIP(hipGetLastError());
 }
+void zero_lower(hipStream_t s, double* x, int mp, long long stride, int batch) {
+  zero_lower_t(s, x, mp, stride, batch);
+}
+void zero_lower(hipStream_t s, float* x, int mp, long long stride, int batch) {
+  zero_lower_t(s, x, mp, stride, batch);
+}
 
-__global__ void zero_block_kernel(double* x, int rows, int cols, int ld, int nb1, long long s1,
+template <class T>
+__global__ void zero_block_kernel(T* x, int rows, int cols, int ld, int nb1, long long s1,
                                   long long s2) {
   const int b = blockIdx.y;
-  double* X = x + (b % nb1) * s1 + (b / nb1) * s2;
+  T* X = x + (b % nb1) * s1 + (b / nb1) * s2;
   const size_t n = (size_t)rows * cols;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % rows), j = (int)(e / rows);
-    X[i + (size_t)j * ld] = 0.0;
+    X[i + (size_t)j * ld] = T(0);
   }
 }
 
+template <class T>
+void zero_block_t(hipStream_t s, T* x, int rows, int cols, int ld, int nb1, long long s1, int nb2,
+                  long long s2) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(zero_block_kernel<T>, dim3(blocks_for((size_t)rows * cols), nb1 * nb2),
+                     dim3(NT), 0, s, x, rows, cols, ld, nb1, s1, s2);
+  PS_HIP(hipGetLastError());
+}
 void zero_block(hipStream_t s, double* x, int rows, int cols, int ld, int nb1, long long s1,
                 int nb2, long long s2) {
-  if (rows <= 0 || cols <= 0) return;
-  hipLaunchKernelGGL(zero_block_kernel, dim3(blocks_for((size_t)rows * cols), nb1 * nb2), dim3(NT),
-                     0, s, x, rows, cols, ld, nb1, s1, s2);
-  PS_HIP(hipGetLastError());
+  zero_block_t(s, x, rows, cols, ld, nb1, s1, nb2, s2);
+}
+void zero_block(hipStream_t s, float* x, int rows, int cols, int ld, int nb1, long long s1,
+                int nb2, long long s2) {
+  zero_block_t(s, x, rows, cols, ld, nb1, s1, nb2, s2);
 }
 
 // 64 x 64 tiles through LDS

@@ -41,6 +41,8 @@ struct ps_handle_s {
   bool events = false;
   std::vector<hipEvent_t> kev;  // per-launch GEMM timing (opts.timing == 2)
   std::vector<double> kflops;
+  hipStream_t side = nullptr;   // second stream: the FP32 shift group of a mixed step
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace ps {
@@ -70,6 +72,8 @@ struct Buffers {
   double *vv, *uu, *pp, *hist, *norms;
   double* splitws;   // kMaxSplit partial products of split-K GEMMs
   int* dinfo;
+  // mixed precision (null in FP64 mode)
+  float *z32, *w32, *n32, *x32, *d32, *t32, *u32, *y32;
 };
 
 constexpr int kMaxSplit = 8;
@@ -91,7 +95,7 @@ void auto_split(GemmProblem& p, double* ws, int maxsplit = kMaxSplit) {
   }
 }
 
-void carve(Arena& a, Buffers& b, int m, int r, int what) {
+void carve(Arena& a, Buffers& b, int m, int r, int what, bool mixed = false) {
   b.m = m;
   b.mp = pad_to(m);
   b.r = r;
@@ -134,6 +138,18 @@ void carve(Arena& a, Buffers& b, int m, int r, int what) {
   b.norms = a.take<double>(2 + 2 * 1024 + 16);
   b.splitws = a.take<double>((size_t)kMaxSplit * S);
   b.dinfo = a.take<int>(16);
+  if (mixed) {
+    b.z32 = a.take<float>((size_t)rr * S);
+    b.w32 = a.take<float>((size_t)rr * S);
+    b.n32 = a.take<float>(S);
+    b.x32 = a.take<float>(S);
+    b.d32 = a.take<float>(S);
+    b.t32 = a.take<float>(S);
+    b.u32 = a.take<float>(S);
+    b.y32 = a.take<float>(S);
+  } else {
+    b.z32 = b.w32 = b.n32 = b.x32 = b.d32 = b.t32 = b.u32 = b.y32 = nullptr;
+  }
 }
 
 // r = 0: the smallest r for which the two steps map [l, 1] into [1 - 1e-15, 1] (the
@@ -162,7 +178,7 @@ struct EigBuffers {
 size_t eig_region_offset(int m, const ps_opts& o) {
   Arena a1, a2;
   Buffers b1, b2;
-  carve(a1, b1, m, resolve_r(o), 1);
+  carve(a1, b1, m, resolve_r(o), 1, o.precision == PS_PREC_MIXED);
   carve(a2, b2, m, 8, 2);
   return std::max(a1.off, a2.off);
 }
@@ -197,7 +213,7 @@ size_t workspace_bytes(int m, const ps_opts& o, int what) {
     carve_eig(a, e, m);
     return a.off + kAlign;
   }
-  carve(a, b, m, resolve_r(o), what);
+  carve(a, b, m, resolve_r(o), what, o.precision == PS_PREC_MIXED);
   return a.off + kAlign;
 }
 
@@ -342,6 +358,119 @@ void zolo_step_series(hipStream_t s, Buffers& b, const double* x, double* xn, co
   gemm_f64(s, px);
 }
 
+// Mixed precision.  The iterate X and X^T X stay in FP64.  In a factorization step,
+// shift c_{2j-1} goes to FP32 when the condition number of its shifted Gram matrix,
+// at most (1 + c)/(l^2 + c) on [l, 1], is at most kappa; FP32 rounding then perturbs
+// X (I + N) by about kappa u_32 relative, which moves the polar factor's subspace by
+// the same order and the Rayleigh-Ritz eigenvalues of H_+ by its square.  The FP32
+// group is factorized on a second stream while the FP64 group runs on the first.
+struct MixedCtx {
+  hipStream_t side;
+  hipEvent_t fork, join;
+  double kappa;
+};
+
+void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double* x, double* xn,
+                     const ZoloHost& co, double ell, int* dinfo64, int* dinfo32, int* n64_out) {
+  const int mp = b.mp, r = co.r;
+  const long long S = (long long)b.S;
+  {
+    GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
+                                  kOutUpper);
+    auto_split(pg, b.splitws);
+    gemm_f64(s, pg);
+  }
+  double c64[8], a64[8], c32[8], a32[8];
+  int n64 = 0, n32 = 0;
+  for (int j = 0; j < r; ++j) {
+    const double c = co.c[2 * j];
+    const double kap = (1.0 + c) / (ell * ell + c);
+    if (kap > mx.kappa) {
+      c64[n64] = c;
+      a64[n64++] = co.a[j];
+    } else {
+      c32[n32] = c;
+      a32[n32++] = co.a[j];
+    }
+  }
+  *n64_out = n64;
+  if (n32 > 0) {
+    PS_HIP(hipEventRecord(mx.fork, s));
+    PS_HIP(hipStreamWaitEvent(mx.side, mx.fork, 0));
+    hipStream_t s2 = mx.side;
+    form_shifts_f32(s2, b.g, b.z32, mp, c32, n32);
+    potrf_inv_f32(s2, b.z32, S, b.w32, S, mp, n32, dinfo32);
+    GemmProblemF pn = gemm_problem(mp, mp, n32 * mp, b.w32, mp, 0, b.w32, mp, 1, b.n32, mp, 1.0,
+                                   0.0, nullptr, 0, kAUpper | kBLower | kOutUpper | kMirror);
+    pn.kseg = mp;
+    pn.nseg = n32;
+    for (int j = 0; j < n32; ++j) pn.kscale[j] = a32[j];
+    if (n32 > 1 && n32 <= kMaxSplit) {   // the FP32 factors are no longer needed: partials there
+      pn.ksplit = n32;
+      pn.ws = b.z32;
+    }
+    gemm_f32(s2, pn);
+    PS_HIP(hipEventRecord(mx.join, s2));
+  }
+  if (n64 > 0) {
+    form_shifts_v(s, b.g, b.z, mp, c64, n64);
+    potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, n64, dinfo64);
+    GemmProblem pn = gemm_problem(mp, mp, n64 * mp, b.w, mp, 0, b.w, mp, 1, b.nmat, mp, 1.0, 0.0,
+                                  nullptr, 0, kAUpper | kBLower | kOutUpper | kMirror);
+    pn.kseg = mp;
+    pn.nseg = n64;
+    for (int j = 0; j < n64; ++j) pn.kscale[j] = a64[j];
+    if (n64 > 1 && n64 <= kMaxSplit) {
+      pn.ksplit = n64;
+      pn.ws = b.splitws;
+    }
+    gemm_f64(s, pn);
+  } else {
+    fill_zero(s, b.nmat, b.S);
+  }
+  if (n32 > 0) {
+    PS_HIP(hipStreamWaitEvent(s, mx.join, 0));
+    axpy_f32(s, b.nmat, 1.0, 1.0, b.n32, b.S);
+  }
+  GemmProblem px = gemm_problem(mp, mp, mp, x, mp, 0, b.nmat, mp, 0, xn, mp, co.chat, co.chat, x,
+                                mp, 0);
+  auto_split(px, b.splitws);
+  gemm_f64(s, px);
+}
+
+// Second step by the series with Delta = X^T X - I in FP64 and the correction
+// T' = sum_{p >= 1} gam_p Delta^p and X T' in FP32: ||Delta|| <= 1 - l_1^2 is small, so
+// FP32 rounding of the correction is damped by that factor, and
+// X2 = hat C (1 + gam_0) X + hat C X T' is formed in FP64.
+void zolo_step_series_mixed(hipStream_t s, Buffers& b, const double* x, double* xn,
+                            const ZoloHost& co, int P, const double gam[4]) {
+  const int mp = b.mp;
+  GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
+                                kOutUpper | kMirror);
+  auto_split(pg, b.splitws);
+  gemm_f64(s, pg);
+  scale_copy(s, x, xn, co.chat * (1.0 + gam[0]), b.S);
+  if (P < 2) return;
+  axpb_identity(s, b.g, b.g, 1.0, -1.0, mp);   // Delta
+  cvt_f64_f32(s, b.g, b.d32, b.S);
+  cvt_f64_f32(s, x, b.x32, b.S);
+  // inner = gam_1 I + gam_2 Delta + ... + gam_{P-1} Delta^{P-2}, then T' = Delta inner
+  float* inner = b.t32;
+  float* tmp = b.u32;
+  axpb_identity_f32(s, b.d32, inner, P >= 3 ? (float)gam[P - 1] : 0.0f,
+                    (float)(P >= 3 ? gam[P - 2] : gam[1]), mp);
+  for (int q = P - 3; q >= 1; --q) {
+    GemmProblemF ph = gemm_problem(mp, mp, mp, b.d32, mp, 0, inner, mp, 0, tmp, mp);
+    gemm_f32(s, ph);
+    axpb_identity_f32(s, tmp, inner, 1.0f, (float)gam[q], mp);
+  }
+  GemmProblemF pt = gemm_problem(mp, mp, mp, b.d32, mp, 0, inner, mp, 0, tmp, mp);
+  gemm_f32(s, pt);
+  GemmProblemF py = gemm_problem(mp, mp, mp, b.x32, mp, 0, tmp, mp, 0, b.y32, mp);
+  gemm_f32(s, py);
+  axpy_f32(s, xn, 1.0, co.chat, b.y32, b.S);
+}
+
 // alpha, beta for the core matrix: sigma_max(Y) and 1/sigma_max(Y^{-1}) by Golub-Kahan.
 void estimate_bounds(hipStream_t s, Buffers& b, const double* ymats, int steps, double* pinned,
                      double* alpha, double* beta, double est[2]) {
@@ -380,7 +509,8 @@ char* workspace_base(ps_handle h, size_t need) {
 // re-estimated on X2.  r_opt <= 0 picks r by the two-step rule.  Fills the iteration
 // fields of inf; on PS_OK the polar factor of y is in b.x2.  Uses b.dinfo[1..3].
 int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, double beta,
-                  int r_opt, const ps_opts& o, double* pin, ps_info& inf, Timer& tm) {
+                  int r_opt, const ps_opts& o, double* pin, ps_info& inf, Timer& tm,
+                  const MixedCtx* mx = nullptr) {
   const int mp = b.mp;
   const long long S = (long long)b.S;
   const int r = r_opt <= 0 ? 8 : std::min(r_opt, 8);
@@ -401,7 +531,14 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
     if (zolotarev_host(ell1, r_run, &c2)) return PS_NOT_CONVERGED;
     if (ell_slot < 4) inf.ell[ell_slot++] = ell;
     if (ell_slot < 4) inf.ell[ell_slot++] = ell1;
-    zolo_step_f64(s, b, xin, b.x1, c1, b.dinfo + 1);
+    if (mx) {
+      int n64 = 0;
+      zolo_step_mixed(s, *mx, b, xin, b.x1, c1, ell, b.dinfo + 1, b.dinfo + 7, &n64);
+      inf.shifts_fp64[0] = n64;
+    } else {
+      zolo_step_f64(s, b, xin, b.x1, c1, b.dinfo + 1);
+      inf.shifts_fp64[0] = r_run;
+    }
     tm.mark(2);
     if (o.max_steps == 1) {
       inf.steps += 1;
@@ -411,10 +548,13 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
     double gam[4];
     const int P = o.step2_series ? series_terms(c2, ell1, gam) : 0;
     inf.step2_terms = P;
-    if (P > 0)
+    if (P > 0 && mx)
+      zolo_step_series_mixed(s, b, b.x1, b.x2, c2, P, gam);
+    else if (P > 0)
       zolo_step_series(s, b, b.x1, b.x2, c2, P, gam);
     else
       zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
+    inf.shifts_fp64[1] = (P > 0) ? 0 : r_run;
     tm.mark(3);
     inf.steps += 2;
     diff_norms(s, b.x1, b.x2, b.S, b.norms);
@@ -422,10 +562,10 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
     PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
     PS_HIP(hipStreamSynchronize(s));
     const int* di = (const int*)(pin + 8);
-    if (di[1] || di[2]) {
+    if (di[1] || di[2] || di[7]) {
       status = PS_SHIFT_BREAKDOWN;
-      inf.failed_step = di[1] ? 1 : 2;
-      inf.failed_mask = di[1] ? di[1] : di[2];
+      inf.failed_step = (di[1] || di[7]) ? 1 : 2;
+      inf.failed_mask = di[1] ? di[1] : (di[7] ? di[7] : di[2]);
       break;
     }
     const double change = std::sqrt(pin[0]) / std::sqrt(pin[1]);
@@ -470,7 +610,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   ar.base = base;
   ar.dry = false;
   Buffers b;
-  carve(ar, b, m, r, what);
+  carve(ar, b, m, r, what, o.precision == PS_PREC_MIXED);
   const int mp = b.mp;
   const long long S = (long long)b.S;
   double* pin = h->pinned;
@@ -540,7 +680,10 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   tm.mark(1);
 
   // ---- Zolotarev steps with the stopping test of Alg. 8
-  const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm);
+  MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
+  const bool mixed = o.precision == PS_PREC_MIXED;
+  const int status =
+      polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm, mixed ? &mxc : nullptr);
   if (status != PS_OK) {
     inf.status = status;
     tm.finish(inf.phase_ms);
@@ -909,7 +1052,7 @@ int check_common(ps_handle h, int m, const double* A, int lda, const double* B, 
   if (!B) return -5;
   if (ldb < m) return -6;
   if (o && (o->r < 0 || o->r > 8 || o->max_restarts < 0 || o->max_steps < 0 ||
-            o->max_steps > 1 || o->precision != PS_PREC_FP64))
+            o->max_steps > 1 || (o->precision != PS_PREC_FP64 && o->precision != PS_PREC_MIXED)))
     return -11;
   return 0;
 }
@@ -966,6 +1109,12 @@ int ps_create(ps_handle* h, void* stream) {
       return PS_HIP_ERROR;
     }
   p->events = true;
+  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess) {
+    delete p;
+    return PS_HIP_ERROR;
+  }
   *h = p;
   return PS_OK;
 }
@@ -979,6 +1128,12 @@ int ps_destroy(ps_handle h) {
   if (h->events)
     for (auto& e : h->ev) (void)hipEventDestroy(e);
   for (auto& e : h->kev) (void)hipEventDestroy(e);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->fork) (void)hipEventDestroy(h->fork);
+  if (h->join) (void)hipEventDestroy(h->join);
   delete h;
   return PS_OK;
 }

@@ -50,11 +50,12 @@ enum GemmFlags : int {
   kBLower = 64,    // op(B)(k,j) = 0 for k < j
 };
 
-struct GemmProblem {
-  const double* A;
-  const double* B;
-  const double* C;
-  double* D;
+template <class T>
+struct GemmProblemT {
+  const T* A;
+  const T* B;
+  const T* C;
+  T* D;
   long long sA[2], sB[2], sC[2], sD[2];  // strides of the two batch indices
   int M, N, K;
   int lda, ldb, ldc, ldd;
@@ -64,15 +65,21 @@ struct GemmProblem {
   int ksplit;       // > 1: split the K loop; partial products go to ws, then a reduction
   double alpha, beta;
   double kscale[kMaxSeg];
-  double* ws;       // ksplit * M * N doubles per batch entry (only when ksplit > 1)
+  T* ws;            // ksplit * M * N elements per batch entry (only when ksplit > 1)
   // filled by the launcher
   int tm, tn, tiles, tiles_per_batch, tile_begin;
 };
+using GemmProblem = GemmProblemT<double>;
+using GemmProblemF = GemmProblemT<float>;
 
 GemmProblem gemm_problem(int M, int N, int K, const double* A, int lda, int tA,
                          const double* B, int ldb, int tB, double* D, int ldd,
                          double alpha = 1.0, double beta = 0.0, const double* C = nullptr,
                          int ldc = 0, int flags = 0);
+GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, const float* B,
+                          int ldb, int tB, float* D, int ldd, double alpha = 1.0,
+                          double beta = 0.0, const float* C = nullptr, int ldc = 0,
+                          int flags = 0);
 
 // Optional per-launch timing of the large-tile GEMM kernel: when set, gemm_f64 brackets
 // each such launch with events from this recorder and adds the algorithmic flops.
@@ -83,13 +90,17 @@ struct GemmRecorder {
   int n = 0;                  // pairs used
 };
 void gemm_set_recorder(GemmRecorder* r);
-double gemm_algorithmic_flops(const GemmProblem& p);
+template <class T>
+double gemm_algorithmic_flops(const GemmProblemT<T>& p);
 
 // Launch up to kMaxGroup independent problems in one kernel.  Problems with
 // ksplit > 1 are followed by a reduction launch (sum of partials, beta C, triangle
 // and mirror handling); their batch extent must be 1.
 void gemm_f64(hipStream_t s, const GemmProblem* probs, int count);
 inline void gemm_f64(hipStream_t s, const GemmProblem& p) { gemm_f64(s, &p, 1); }
+// the same on FP32 operands (v_mfma_f32_16x16x4_f32, FP32 accumulation)
+void gemm_f32(hipStream_t s, const GemmProblemF* probs, int count);
+inline void gemm_f32(hipStream_t s, const GemmProblemF& p) { gemm_f32(s, &p, 1); }
 
 // ----------------------------------------------------------------- Cholesky
 // In-place upper Cholesky Z = R^T R of `batch` SPD matrices (mp x mp, ld = mp,
@@ -99,6 +110,9 @@ inline void gemm_f64(hipStream_t s, const GemmProblem& p) { gemm_f64(s, &p, 1); 
 // the device int *info.
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
                    double* tmp, int mp, int batch, int* info);
+// the same in FP32 (pivots taken and inverted through FP64 square roots)
+void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,
+                   int batch, int* info);
 
 // ----------------------------------------------------------------- elementwise
 void pack_casida(hipStream_t s, int m, int mp, const double* A, int lda, const double* B,
@@ -106,8 +120,11 @@ void pack_casida(hipStream_t s, int m, int mp, const double* A, int lda, const d
 void mask_pad(hipStream_t s, double* x, int m, int mp, long long stride, int batch);
 void fill_zero(hipStream_t s, double* x, size_t n);
 void zero_lower(hipStream_t s, double* x, int mp, long long stride, int batch);
+void zero_lower(hipStream_t s, float* x, int mp, long long stride, int batch);
 // zero `rows x cols` blocks (leading dimension ld) at x + b1*s1 + b2*s2
 void zero_block(hipStream_t s, double* x, int rows, int cols, int ld, int nb1, long long s1,
+                int nb2, long long s2);
+void zero_block(hipStream_t s, float* x, int rows, int cols, int ld, int nb1, long long s1,
                 int nb2, long long s2);
 void transpose(hipStream_t s, const double* x, double* y, int mp, long long stride, int batch);
 void form_shifts(hipStream_t s, const double* g, double* z, int mp, const double* shifts,
@@ -122,6 +139,13 @@ void basis_mix(hipStream_t s, const double* c, const double* qbot, double* top_o
 void copy_out(hipStream_t s, const double* x, int ldx, double* y, int ldy, int rows,
               int cols);
 void diff_norms(hipStream_t s, const double* x1, const double* x2, size_t n, double* out2);
+
+// mixed-precision helpers (mixed.hip)
+void form_shifts_f32(hipStream_t s, const double* g, float* z, int mp, const double* shifts,
+                     int r);   // z[j] = fp32(upper(G) + shifts[j] I)
+void cvt_f64_f32(hipStream_t s, const double* x, float* y, size_t n);
+void axpy_f32(hipStream_t s, double* y, double a, double b, const float* x, size_t n);
+void axpb_identity_f32(hipStream_t s, const float* x, float* y, float a, float b, int mp);
 
 // eigen-decomposition helpers (eig_f64.hip)
 void shift_diag(hipStream_t s, double* y, int ld, int n, double b);   // y(i,i) += b, i < n

@@ -216,3 +216,46 @@ def test_full_size_casida_n4096():
     assert np.abs(pq - Qp[:, cols]).max() < 1e-10
     e = np.eye(2 * m)[:, cols]
     assert np.abs(s @ (s @ e) - e).max() < 1e-10
+
+
+@pytest.mark.parametrize("m,seed,kind", [CASES[5], CASES[6], CASES[7]])
+def test_mixed_divide(m, seed, kind):
+    """Mixed precision: well-conditioned shifts of the first step and the second step's
+    correction in FP32, everything else FP64.  The subspace moves by about
+    kappa * u_32 (kappa = mixed_kappa), so Q_+ agrees with the FP64 oracle to ~1e-5,
+    Q_+ stays Sigma-orthonormal to FP64 accuracy (the FP64 Delta = X^T X - I of the
+    second step restores orthogonality) and the eigenvalues of H_+, Rayleigh-Ritz
+    values of that subspace, are within the square of that: target 1e-10."""
+    print(f"[mixed divide] m={m} seed={seed} kind={kind}", flush=True)
+    a, b = make(m, seed, kind)
+    al, be = bounds(a, b)
+    ref = dv.divide_casida(a, b, alpha=al, beta=be)
+    Qp, Hp, info = api.divide(dev(a), dev(b), alpha=al, beta=be, precision="mixed")
+    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+    assert info["status"] == 0
+    assert 0 < info["shifts_fp64"][0] < 8 and info["shifts_fp64"][1] == 0
+    assert rel(Qp, ref["Q_plus"]) < 1e-5
+    sigma = sg.casida_sigma(m)
+    assert np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max() < 1e-11
+    lam, _ = eg.eig_casida(a, b)
+    w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
+    assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-10
+
+
+@pytest.mark.timeout(400)
+def test_mixed_full_size_casida_n4096():
+    m = 2048
+    a, b = inputs.casida_like(m, 1)
+    print("[mixed full size] m=2048", flush=True)
+    Qp, Hp, info = api.divide(dev(a), dev(b), precision="mixed")
+    assert info["status"] == 0 and info["restarts"] == 0
+    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+    sigma = sg.casida_sigma(m)
+    # the Cholesky factor C of (I + A_s)/2 in Alg. 6 amplifies the orthogonality error
+    # of sign(H) by about cond(C)^2; at this size that leaves ~1e-11
+    orth = np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max()
+    print(f"[mixed full size] Sigma-orthonormality {orth:.3e}", flush=True)
+    assert orth < 1e-10
+    w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
+    lam, _ = eg.eig_casida(a, b)
+    assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-10
