@@ -79,7 +79,7 @@ typedef struct {
                        /* (1 + c)/(l^2 + c) exceeds this run in FP64               */
   int step2_series;    /* nonzero: when step 1 has left every singular value of the */
                        /* iterate within [l_1, 1] with (1 - l_1^2)^P < 1e-17 for    */
-                       /* P <= 4, evaluate the second step's sum                    */
+                       /* P <= 8, evaluate the second step's sum                    */
                        /* sum_j a_j (X^T X + c_{2j-1} I)^{-1} as the convergent     */
                        /* series in Delta = X^T X - I instead of r factorizations   */
                        /* (the same rational function to below 1e-17)               */

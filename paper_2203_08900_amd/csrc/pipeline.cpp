@@ -305,22 +305,24 @@ void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const
 // (1 + c)^{-1} sum_p (-Delta / (1 + c))^p, the p-th term of sum_j a_j (G + c_j I)^{-1} is
 // bounded by gamma_p ||Delta||^p, gamma_p = sum_j a_j / (1 + c_j)^{p+1}.  P terms are
 // used when the first omitted one is below 1e-17 relative to gamma_0.
-int series_terms(const ZoloHost& co, double ell_in, double gam[4]) {
+constexpr int kMaxSeries = 8;
+
+int series_terms(const ZoloHost& co, double ell_in, double gam[kMaxSeries]) {
   const long double d = 1.0L - (long double)ell_in * ell_in;
-  long double g[6] = {0, 0, 0, 0, 0, 0};
+  long double g[kMaxSeries + 2] = {};
   for (int j = 0; j < co.r; ++j) {
     long double f = 1.0L / (1.0L + co.c[2 * j]);
     long double t = co.a[j] * f;
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < kMaxSeries + 2; ++p) {
       g[p] += t;
       t *= f;
     }
   }
-  for (int P = 1; P <= 4; ++P) {
+  for (int P = 1; P <= kMaxSeries; ++P) {
     long double bound = g[P];
     for (int q = 0; q < P; ++q) bound *= d;
     if (bound <= 1e-17L * g[0]) {
-      for (int p = 0; p < 4; ++p) gam[p] = (double)((p & 1) ? -g[p] : g[p]);
+      for (int p = 0; p < kMaxSeries; ++p) gam[p] = (double)((p & 1) ? -g[p] : g[p]);
       return P;
     }
   }
@@ -330,7 +332,7 @@ int series_terms(const ZoloHost& co, double ell_in, double gam[4]) {
 // Second Zolotarev step by the series: xn = hat C x (I + sum_{p<P} gam_p Delta^p),
 // Delta = x^T x - I, evaluated by Horner's rule on the right.
 void zolo_step_series(hipStream_t s, Buffers& b, const double* x, double* xn, const ZoloHost& co,
-                      int P, const double gam[4]) {
+                      int P, const double gam[kMaxSeries]) {
   const int mp = b.mp;
   GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
                                 kOutUpper | kMirror);
@@ -443,7 +445,7 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
 // FP32 rounding of the correction is damped by that factor, and
 // X2 = hat C (1 + gam_0) X + hat C X T' is formed in FP64.
 void zolo_step_series_mixed(hipStream_t s, Buffers& b, const double* x, double* xn,
-                            const ZoloHost& co, int P, const double gam[4]) {
+                            const ZoloHost& co, int P, const double gam[kMaxSeries]) {
   const int mp = b.mp;
   GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
                                 kOutUpper | kMirror);
@@ -545,10 +547,13 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
       std::swap(b.x1, b.x2);  // the sign assembly reads x2
       break;
     }
-    double gam[4];
+    double gam[kMaxSeries];
     const int P = o.step2_series ? series_terms(c2, ell1, gam) : 0;
     inf.step2_terms = P;
-    if (P > 0 && mx)
+    // the FP32 correction is damped by ||Delta|| <= 1 - l1^2; use it only while that
+    // keeps its rounding below 1e-13 (else the FP64 series)
+    const bool series32 = mx && (1.0 - ell1 * ell1) * 6.0e-8 <= 1e-13;
+    if (P > 0 && series32)
       zolo_step_series_mixed(s, b, b.x1, b.x2, c2, P, gam);
     else if (P > 0)
       zolo_step_series(s, b, b.x1, b.x2, c2, P, gam);

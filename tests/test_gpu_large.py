@@ -1,0 +1,65 @@
+"""The large ill-separated workload: m = 8192 (n = 16384), eig(H) = +-sqrt(mu) with mu
+log-uniform in [1e-6, 1] (both ends pinned), so l = beta/alpha = 1e-3 exactly and the
+worst shifted Gram matrix of the first Zolotarev step has condition ~8e5.
+
+The oracle cannot factorize n = 16384 in test time, so the checks are properties that
+hold at any size, against closed forms of the construction:
+  * eigenvalues of H_+ against sqrt(mu) (the construction itself reproduces mu to
+    ~1e-11 relative, so the bar is 1e-9 for FP64 and 1e-8 for the mixed mode);
+  * Sigma-orthonormality of Q_+;
+  * trace(H_+) = sum sqrt(mu).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2203_08900_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+M = 8192
+
+
+@pytest.fixture(scope="module")
+def ill():
+    print("[large] generating m=8192 ill-separated blocks", flush=True)
+    a, b, mu = inputs.ill_separated(M, 4)
+    print("[large] generated", flush=True)
+    return a, b, mu
+
+
+def eigvals_sym(h):
+    try:
+        return torch.linalg.eigvalsh(h).cpu().numpy()
+    except Exception:   # pragma: no cover - fall back to LAPACK on the host
+        return np.linalg.eigvalsh(h.cpu().numpy())
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-8)])
+def test_ill_separated_m8192(ill, precision, tol):
+    a, b, mu = ill
+    A = torch.tensor(a, dtype=torch.float64, device="cuda")
+    B = torch.tensor(b, dtype=torch.float64, device="cuda")
+    print(f"[large] divide {precision}", flush=True)
+    Qp, Hp, info = api.divide(A, B, precision=precision)
+    torch.cuda.synchronize()
+    print(f"[large] info r={info['r']} ell={info['ell'][:2]} restarts={info['restarts']} "
+          f"fp64 shifts={info['shifts_fp64']}", flush=True)
+    assert info["status"] == 0
+    exact = np.sqrt(mu)
+    # l = beta / alpha: the estimator brackets the spectrum within a few percent
+    assert 0.9e-3 < info["beta"] / info["alpha"] < 1.0e-3
+    sig = torch.cat([torch.ones(M, dtype=torch.float64, device="cuda"),
+                     -torch.ones(M, dtype=torch.float64, device="cuda")])
+    G = Qp.T @ (sig[:, None] * Qp)
+    orth = (G - torch.eye(M, dtype=torch.float64, device="cuda")).abs().max().item()
+    print(f"[large] Sigma-orthonormality {orth:.3e}", flush=True)
+    assert orth < 1e-9
+    Hs = 0.5 * (Hp + Hp.T)
+    assert abs(torch.trace(Hs).item() - exact.sum()) / exact.sum() < 1e-11
+    w = np.sort(eigvals_sym(Hs))
+    err = np.max(np.abs(w - exact) / exact)
+    print(f"[large] relative eigenvalue error {err:.3e}", flush=True)
+    assert err < tol

@@ -68,7 +68,7 @@ def test_step2_forms_agree(m, seed, kind):
     ref = dv.divide_casida(a, b, alpha=al, beta=be)["S"]
     SA1, SB1, i1 = api.sign(dev(a), dev(b), alpha=al, beta=be, step2_series=False)
     SA2, SB2, i2 = api.sign(dev(a), dev(b), alpha=al, beta=be, step2_series=True)
-    assert i1["step2_terms"] == 0 and 1 <= i2["step2_terms"] <= 4
+    assert i1["step2_terms"] == 0 and 1 <= i2["step2_terms"] <= 8
     for SA in (SA1, SA2):
         assert rel(SA.cpu().numpy(), ref[:m, :m]) < 1e-12
     assert np.abs(SA1.cpu().numpy() - SA2.cpu().numpy()).max() < 1e-13
