@@ -97,6 +97,53 @@ def gpu_leg(args, a, b):
     return out
 
 
+def batched_leg(args):
+    """256 independent problems, m_i uniform over {32..512}: one batched call (worker
+    streams) against the same problems called one at a time."""
+    import numpy as np
+    import torch
+    from paper_2203_08900_amd import api, inputs
+
+    sizes = inputs.batched_sizes(256, 2)
+    probs = [inputs.small_dense(mi, i) for i, mi in enumerate(sizes)]
+    As = [torch.tensor(a, dtype=torch.float64, device="cuda:0") for a, _ in probs]
+    Bs = [torch.tensor(b, dtype=torch.float64, device="cuda:0") for _, b in probs]
+    out = {}
+    for mode in args.modes:
+        kw = dict(precision=mode, r=args.r)
+        for _ in range(args.warmup):
+            api.divide_batched(As, Bs, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, Hs, infos = api.divide_batched(As, Bs, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        for A, B in zip(As, Bs):
+            api.divide(A, B, **kw)
+        torch.cuda.synchronize()
+        ms_seq = (time.perf_counter() - t0) * 1e3
+        flops = sum(nominal_flops(mi, inf["r"], inf["step2_terms"]) for mi, inf in zip(sizes, infos))
+        err = 0.0
+        for i in range(0, 256, 32):
+            a, b = probs[i]
+            lam = np.sort(np.sqrt(np.linalg.eigvals((a - b) @ (a + b)).real))
+            w = np.sort(np.linalg.eigvalsh(0.5 * (Hs[i] + Hs[i].T).cpu().numpy()))
+            err = max(err, float(np.max(np.abs(w - lam) / lam)))
+        out[mode] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "ms_one_at_a_time": ms_seq,
+                     "rel_eig_err_sampled": err}
+    primary = "mixed" if "mixed" in out else args.modes[0]
+    return {"metric": "batched sign-fn+divide, 256 problems n_i in {64..1024}", "value":
+            out[primary]["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out[primary]["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if primary == "fp64" else "f32+f64",
+            "data": "synthetic", "config": {"workload": "batched_256: m_i uniform over {32..512} "
+                                            "(seed 2), small_dense(m_i, i) blocks",
+                                            "problems": 256, "precision": primary},
+            "modes": out}
+
+
 def copy_probe(nbytes: int = 512 << 20):
     """A plain streaming kernel of known size: y = -x over nbytes of FP64 (reads and
     writes nbytes each)."""
@@ -175,7 +222,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="casida_n4096",
-                    choices=["casida_n4096", "ill_separated_n16384"])
+                    choices=["casida_n4096", "ill_separated_n16384", "batched_256"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--modes", default="fp64,mixed")
@@ -196,6 +243,9 @@ def main():
     if args.copy_probe:
         copy_probe()
     exact = None
+    if args.workload == "batched_256":
+        print(json.dumps(batched_leg(args)), flush=True)
+        return
     if args.workload == "casida_n4096":
         args.m = args.m or 2048
         args.seed = 1

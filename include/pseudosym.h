@@ -177,6 +177,21 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
 int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                   double* lambda, double* V, int ldv, const ps_opts* opts, ps_info* info);
 
+/* pseudosym_divide for `batch` independent problems of (possibly) different sizes:
+ * problem i has half-size m[i], inputs A[i], B[i] (leading dimensions lda[i], ldb[i])
+ * and outputs Qp[i] (2m[i] x m[i], ldq[i] >= 2 m[i]) and Hp[i] (ldh[i] >= m[i]), with
+ * the conventions of pseudosym_divide.  m, lda, ldb, ldq, ldh and the pointer arrays
+ * are HOST arrays of length batch holding device pointers.  The problems run largest
+ * first on four worker streams owned by the handle (each with its own library-owned
+ * workspace; ps_set_workspace does not apply to them); the call returns when all are
+ * done.  infos (host, length batch, may be NULL) receives one record per problem;
+ * the return value is 0 or the status of the first failing problem in index order.
+ * Argument errors: -k as usual (k = 3..11 also when entry i of that array is invalid). */
+int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double* const* A,
+                             const int* lda, const double* const* B, const int* ldb,
+                             double* const* Qp, const int* ldq, double* const* Hp,
+                             const int* ldh, const ps_opts* opts, ps_info* infos);
+
 /* Human-readable name of a status code. */
 const char* ps_status_string(int status);
 

@@ -87,7 +87,7 @@ class PsInfo(ctypes.Structure):
 EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
     "ps_set_workspace", "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
-    "pseudosym_eig", "ps_status_string",
+    "pseudosym_eig", "pseudosym_divide_batched", "ps_status_string",
 ]
 
 _lib = None
@@ -129,6 +129,12 @@ def load():
         lib.pseudosym_eig.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts),
                                             ctypes.POINTER(PsInfo)]
         lib.pseudosym_eig.restype = ip
+        iarr = ctypes.POINTER(ctypes.c_int)
+        parr = ctypes.POINTER(ctypes.c_void_p)
+        lib.pseudosym_divide_batched.argtypes = [hp, ip, iarr, parr, iarr, parr, iarr, parr, iarr,
+                                                 parr, iarr, ctypes.POINTER(PsOpts),
+                                                 ctypes.POINTER(PsInfo)]
+        lib.pseudosym_divide_batched.restype = ip
         lib.ps_status_string.argtypes = [ip]
         lib.ps_status_string.restype = ctypes.c_char_p
         _lib = lib
@@ -289,3 +295,35 @@ def eig(A, B, want_vectors=True, raise_on_error=True, **kw):
     if rc != 0 and raise_on_error:
         raise PseudosymError(rc, info.as_dict())
     return lam, (Vt.t() if Vt is not None else None), info.as_dict() | {"rc": rc}
+
+
+def divide_batched(As, Bs, raise_on_error=True, **kw):
+    """pseudosym_divide for lists of independent problems (sizes may differ).
+    Returns (list of Qp, list of Hp, list of info)."""
+    torch = _torch()
+    opts = make_opts(**kw)
+    lib = load()
+    pairs = [_prepare(A, B) for A, B in zip(As, Bs)]
+    n = len(pairs)
+    if n == 0:
+        return [], [], []
+    dev = pairs[0][0].device
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        st = _handle(dev.index, stream.cuda_stream)
+    ms = [A.shape[0] for A, _ in pairs]
+    Qts = [torch.empty((mi, 2 * mi), dtype=torch.float64, device=dev) for mi in ms]
+    Hps = [torch.empty((mi, mi), dtype=torch.float64, device=dev) for mi in ms]
+    I = ctypes.c_int * n
+    P = ctypes.c_void_p * n
+    m_arr = I(*ms)
+    two_m = I(*[2 * mi for mi in ms])
+    infos = (PsInfo * n)()
+    rc = lib.pseudosym_divide_batched(
+        st.handle, n, m_arr, P(*[A.data_ptr() for A, _ in pairs]), m_arr,
+        P(*[B.data_ptr() for _, B in pairs]), m_arr, P(*[q.data_ptr() for q in Qts]), two_m,
+        P(*[h.data_ptr() for h in Hps]), m_arr, ctypes.byref(opts), infos)
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc)
+    return ([q.t() for q in Qts], [h.t() for h in Hps],
+            [infos[i].as_dict() | {"rc": rc} for i in range(n)])

@@ -355,7 +355,7 @@ GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, 
 }
 
 namespace {
-GemmRecorder* g_rec = nullptr;
+thread_local GemmRecorder* g_rec = nullptr;   // per host thread (batched calls use several)
 
 template <class T, int BM, int BN, int WM, int WN>
 void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {

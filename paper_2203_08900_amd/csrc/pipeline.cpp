@@ -15,9 +15,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "../../include/pseudosym.h"
@@ -43,6 +45,8 @@ struct ps_handle_s {
   std::vector<double> kflops;
   hipStream_t side = nullptr;   // second stream: the FP32 shift group of a mixed step
   hipEvent_t fork = nullptr, join = nullptr;
+  bool owns_stream = false;     // worker handles of batched calls own their stream
+  std::vector<ps_handle_s*> workers;
 };
 
 namespace ps {
@@ -1048,6 +1052,7 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
   return PS_OK;
 }
 
+
 int check_common(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                  const ps_opts* o) {
   if (!h) return -1;
@@ -1075,6 +1080,61 @@ int guarded(ps_handle h, F&& f) {
     return PS_HIP_ERROR;
   }
 }
+
+// Batched division of independent problems of uneven sizes.  The problems are dealt,
+// largest first, to kWorkers host threads; each drives its own handle (stream,
+// workspace, pinned staging) through the single-problem pipeline, so that the
+// latency-bound small factorizations of different problems overlap on the device.
+// kWorkers matches the hardware queues a process gets by default.
+constexpr int kWorkers = 4;
+
+int run_batched(ps_handle h, int batch, const int* m, const double* const* A, const int* lda,
+                const double* const* B, const int* ldb, double* const* Qp, const int* ldq,
+                double* const* Hp, const int* ldh, const ps_opts& o, ps_info* infos) {
+  const int nw = std::min(kWorkers, batch);
+  while ((int)h->workers.size() < nw) {
+    hipStream_t st;
+    PS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    ps_handle w = nullptr;
+    if (ps_create(&w, st) != PS_OK) {
+      (void)hipStreamDestroy(st);
+      return PS_HIP_ERROR;
+    }
+    w->owns_stream = true;
+    h->workers.push_back(w);
+  }
+  // the inputs may still be in flight on the caller's stream
+  PS_HIP(hipEventRecord(h->fork, h->stream));
+  for (int k = 0; k < nw; ++k) PS_HIP(hipStreamWaitEvent(h->workers[k]->stream, h->fork, 0));
+  std::vector<int> order(batch);
+  for (int i = 0; i < batch; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m[x] > m[y]; });
+  std::vector<int> status(batch, PS_OK);
+  std::atomic<int> next{0};
+  auto work = [&](int k) {
+    ps_handle w = h->workers[k];
+    if (hipSetDevice(h->device) != hipSuccess) {
+      for (int i; (i = next.fetch_add(1)) < batch;) status[order[i]] = PS_HIP_ERROR;
+      return;
+    }
+    for (int i; (i = next.fetch_add(1)) < batch;) {
+      const int p = order[i];
+      ps_info local{};
+      ps_info* inf = infos ? &infos[p] : &local;
+      status[p] = guarded(w, [&] {
+        return run(w, m[p], A[p], lda[p], B[p], ldb[p], Qp[p], ldq[p], Hp[p], ldh[p], o, inf, 1);
+      });
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int k = 1; k < nw; ++k) threads.emplace_back(work, k);
+  work(0);
+  for (auto& t : threads) t.join();
+  for (int p = 0; p < batch; ++p)
+    if (status[p] != PS_OK) return status[p];
+  return PS_OK;
+}
+
 
 }  // namespace
 }  // namespace ps
@@ -1139,6 +1199,12 @@ int ps_destroy(ps_handle h) {
   }
   if (h->fork) (void)hipEventDestroy(h->fork);
   if (h->join) (void)hipEventDestroy(h->join);
+  for (ps_handle w : h->workers) {
+    hipStream_t st = w->stream;
+    const bool own = w->owns_stream;
+    (void)ps_destroy(w);
+    if (own && st) (void)hipStreamDestroy(st);
+  }
   delete h;
   return PS_OK;
 }
@@ -1217,6 +1283,47 @@ int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B,
   o.max_steps = 0;
   o.timing = 0;
   return guarded(h, [&] { return run_eig(h, m, A, lda, B, ldb, lambda, V, ldv, o, info); });
+}
+
+int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double* const* A,
+                             const int* lda, const double* const* B, const int* ldb,
+                             double* const* Qp, const int* ldq, double* const* Hp,
+                             const int* ldh, const ps_opts* opts, ps_info* infos) {
+  if (!h) return -1;
+  if (batch < 0) return -2;
+  if (batch == 0) return PS_OK;
+  if (!m) return -3;
+  if (!A) return -4;
+  if (!lda) return -5;
+  if (!B) return -6;
+  if (!ldb) return -7;
+  if (!Qp) return -8;
+  if (!ldq) return -9;
+  if (!Hp) return -10;
+  if (!ldh) return -11;
+  for (int i = 0; i < batch; ++i) {
+    if (m[i] < 1) return -3;
+    if (!A[i]) return -4;
+    if (lda[i] < m[i]) return -5;
+    if (!B[i]) return -6;
+    if (ldb[i] < m[i]) return -7;
+    if (!Qp[i]) return -8;
+    if (ldq[i] < 2 * m[i]) return -9;
+    if (!Hp[i]) return -10;
+    if (ldh[i] < m[i]) return -11;
+  }
+  if (opts && (opts->r < 0 || opts->r > 8 || opts->max_restarts < 0 || opts->max_steps < 0 ||
+               opts->max_steps > 1 ||
+               (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED)))
+    return -12;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  o.timing = 0;
+  return guarded(h, [&] {
+    return run_batched(h, batch, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, infos);
+  });
 }
 
 const char* ps_status_string(int st) {

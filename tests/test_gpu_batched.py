@@ -1,0 +1,60 @@
+"""Batched division of independent problems of uneven sizes (pseudosym_divide_batched).
+
+Each problem runs the same single-problem pipeline on one of the handle's worker
+streams, so every result must equal, bit for bit, the one pseudosym_divide returns
+for that problem alone; a sample is also checked against the oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import divide as dv
+from oracle import sign as sg
+from paper_2203_08900_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def test_batched_matches_single_and_oracle():
+    sizes = [17, 300, 64, 1, 130, 65, 200, 33, 250, 96, 7, 180]
+    probs = [inputs.small_dense(mi, 100 + i) for i, mi in enumerate(sizes)]
+    As = [dev(a) for a, _ in probs]
+    Bs = [dev(b) for _, b in probs]
+    print(f"[batched] sizes {sizes}", flush=True)
+    Qs, Hs, infos = api.divide_batched(As, Bs)
+    assert all(inf["status"] == 0 for inf in infos)
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        Q1, H1, _ = api.divide(A, B)
+        assert torch.equal(Q1, Qs[i]) and torch.equal(H1, Hs[i])
+    for i in (0, 1, 4):
+        a, b = probs[i]
+        m = sizes[i]
+        amax, amin = sg.abs_eig_bounds(sg.casida_matrix(a, b), sg.casida_sigma(m))
+        ref = dv.divide_casida(a, b, alpha=1.01 * amax, beta=0.99 * amin)
+        w = np.linalg.eigvalsh(0.5 * (Hs[i] + Hs[i].T).cpu().numpy())
+        lam = np.sort(np.linalg.eigvalsh(0.5 * (ref["H_plus"] + ref["H_plus"].T)))
+        assert np.max(np.abs(w - lam) / lam) < 1e-12
+
+
+def test_batched_mixed_and_empty():
+    assert api.divide_batched([], []) == ([], [], [])
+    sizes = [40, 120, 260]
+    probs = [inputs.small_dense(mi, 7 + i) for i, mi in enumerate(sizes)]
+    Qs, Hs, infos = api.divide_batched([dev(a) for a, _ in probs], [dev(b) for _, b in probs],
+                                       precision="mixed")
+    for (a, b), H, inf, m in zip(probs, Hs, infos, sizes):
+        assert inf["status"] == 0
+        lam = np.sqrt(np.linalg.eigvals((a - b) @ (a + b)).real)
+        w = np.linalg.eigvalsh(0.5 * (H + H.T).cpu().numpy())
+        assert np.max(np.abs(np.sort(w) - np.sort(lam)) / np.sort(lam)) < 1e-10
+
+
+def test_batched_bad_arguments():
+    a, b = inputs.small_dense(8, 1)
+    with pytest.raises(api.PseudosymError):
+        api.divide_batched([dev(a)], [dev(b)], r=9)

@@ -41,6 +41,9 @@ def test_argument_errors_before_any_launch():
     rc = lib.pseudosym_eig(None, 4, None, 4, None, 4, None, None, 8, ctypes.byref(o),
                            ctypes.byref(info))
     assert rc == -1
+    rc = lib.pseudosym_divide_batched(None, 1, None, None, None, None, None, None, None, None,
+                                      None, ctypes.byref(o), None)
+    assert rc == -1
     assert lib.ps_workspace_size(64, ctypes.byref(o), 2) > lib.ps_workspace_size(
         64, ctypes.byref(o), 1) > lib.ps_workspace_size(64, ctypes.byref(o), 0) > 0
     assert lib.ps_zolotarev_coeffs(0.0, 8, None, None, None, None) == -1
