@@ -121,8 +121,8 @@ int ps_create(ps_handle* h, void* stream);
 int ps_destroy(ps_handle h);
 int ps_set_stream(ps_handle h, void* stream);
 
-/* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig)
- * needs at half-size m with options o (NULL = defaults). */
+/* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig and
+ * sign_fwd, 3 sign_bwd) needs at half-size m with options o (NULL = defaults). */
 size_t ps_workspace_size(int m, const ps_opts* o, int what);
 
 /* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the
@@ -191,6 +191,27 @@ int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double*
                              const int* lda, const double* const* B, const int* ldb,
                              double* const* Qp, const int* ldq, double* const* Hp,
                              const int* ldh, const ps_opts* opts, ps_info* infos);
+
+/* Differentiable sign function.  Forward: the blocks SA, SB of sign(H) (as
+ * pseudosym_sign, from the division step) together with the eigen-decomposition of
+ * pseudosym_eig (lambda, 2m values; V, 2m x 2m with ldv >= 2m), which the adjoint
+ * reuses.  The caller keeps lambda and V (device memory it owns) for the backward. */
+int pseudosym_sign_fwd(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                       double* SA, double* SB, int lds, double* lambda, double* V, int ldv,
+                       const ps_opts* opts, ps_info* info);
+
+/* Adjoint (backward) of the sign blocks.  Given gSA = dL/dS_A and gSB = dL/dS_B (m x m,
+ * leading dimension ldg) for a scalar loss L and the lambda, V of the forward, writes
+ * gA = dL/dA and gB = dL/dB (m x m, ldo), each the symmetric part, so that
+ * <gA, E_A> + <gB, E_B> is the derivative of L along symmetric (E_A, E_B).  With
+ * H = V diag(lambda) V^{-1} the derivative of sign is the divided-difference form
+ * L*(H, G) = V^{-T} (F o (V^T G V^{-T})) V^T, F_ij = (sign lambda_i - sign lambda_j) /
+ * (lambda_i - lambda_j); V^{-1} = diag(I, -I) V^T Sigma by the Sigma-orthogonality of V
+ * (Thm. EVREalSigmaOrth).  For L = trace(W P_+), P_+ = (I + sign(H))/2, the inputs are
+ * gSA = (W11 - W22)^T / 2 and gSB = (W21 - W12)^T / 2 (W in m x m blocks). */
+int pseudosym_sign_bwd(ps_handle h, int m, const double* lambda, const double* V, int ldv,
+                       const double* gSA, const double* gSB, int ldg, double* gA, double* gB,
+                       int ldo);
 
 /* Human-readable name of a status code. */
 const char* ps_status_string(int status);

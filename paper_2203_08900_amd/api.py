@@ -87,7 +87,8 @@ class PsInfo(ctypes.Structure):
 EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
     "ps_set_workspace", "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
-    "pseudosym_eig", "pseudosym_divide_batched", "ps_status_string",
+    "pseudosym_eig", "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
+    "ps_status_string",
 ]
 
 _lib = None
@@ -135,6 +136,11 @@ def load():
                                                  parr, iarr, ctypes.POINTER(PsOpts),
                                                  ctypes.POINTER(PsInfo)]
         lib.pseudosym_divide_batched.restype = ip
+        lib.pseudosym_sign_fwd.argtypes = mat + [vp, vp, ip, vp, vp, ip, ctypes.POINTER(PsOpts),
+                                                 ctypes.POINTER(PsInfo)]
+        lib.pseudosym_sign_fwd.restype = ip
+        lib.pseudosym_sign_bwd.argtypes = [hp, ip, vp, vp, ip, vp, vp, ip, vp, vp, ip]
+        lib.pseudosym_sign_bwd.restype = ip
         lib.ps_status_string.argtypes = [ip]
         lib.ps_status_string.restype = ctypes.c_char_p
         _lib = lib
@@ -327,3 +333,91 @@ def divide_batched(As, Bs, raise_on_error=True, **kw):
         raise PseudosymError(rc)
     return ([q.t() for q in Qts], [h.t() for h in Hps],
             [infos[i].as_dict() | {"rc": rc} for i in range(n)])
+
+
+def _colmajor(x):
+    """Contiguous buffer holding x in column-major order."""
+    return x.t().contiguous()
+
+
+def sign_fwd(A, B, raise_on_error=True, **kw):
+    """Sign blocks plus the eigen-decomposition the adjoint reuses.
+    Returns (SA, SB, lam, V, info)."""
+    torch = _torch()
+    opts = make_opts(**kw)
+    lib, st, A, B, m = _call_setup(A, B, opts, 2)
+    SA = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    SB = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    lam = torch.empty(2 * m, dtype=torch.float64, device=A.device)
+    Vt = torch.empty((2 * m, 2 * m), dtype=torch.float64, device=A.device)
+    info = PsInfo()
+    rc = lib.pseudosym_sign_fwd(st.handle, m, A.data_ptr(), m, B.data_ptr(), m, SA.data_ptr(),
+                                SB.data_ptr(), m, lam.data_ptr(), Vt.data_ptr(), 2 * m,
+                                ctypes.byref(opts), ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    return SA.t(), SB.t(), lam, Vt.t(), info.as_dict() | {"rc": rc}
+
+
+def sign_bwd(lam, V, gSA, gSB):
+    """(dL/dA, dL/dB) from (dL/dSA, dL/dSB) and the forward's lam, V."""
+    torch = _torch()
+    lib = load()
+    m = gSA.shape[0]
+    dev = V.device
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        st = _handle(dev.index, stream.cuda_stream)
+        need = int(lib.ps_workspace_size(int(m), None, 3))
+        if st.ws_bytes < need:
+            st.workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+            st.ws_bytes = need
+            aligned = (st.workspace.data_ptr() + 255) // 256 * 256
+            rc = lib.ps_set_workspace(st.handle, ctypes.c_void_p(aligned), ctypes.c_size_t(need))
+            if rc != 0:
+                raise PseudosymError(rc)
+    Vc = _colmajor(V.to(torch.float64))
+    ga_in = _colmajor(gSA.to(torch.float64))
+    gb_in = _colmajor(gSB.to(torch.float64))
+    lam = lam.contiguous()
+    gA = torch.empty((m, m), dtype=torch.float64, device=dev)
+    gB = torch.empty((m, m), dtype=torch.float64, device=dev)
+    rc = lib.pseudosym_sign_bwd(st.handle, m, lam.data_ptr(), Vc.data_ptr(), 2 * m,
+                                ga_in.data_ptr(), gb_in.data_ptr(), m, gA.data_ptr(),
+                                gB.data_ptr(), m)
+    if rc != 0:
+        raise PseudosymError(rc)
+    return gA.t(), gB.t()
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class PseudosymSign(torch.autograd.Function):
+        """(A, B) -> blocks (S_A, S_B) of sign([[A, B], [-B, -A]]), differentiable: the
+        backward is the library's adjoint, which reuses the forward's eigenvectors."""
+
+        @staticmethod
+        def forward(ctx, A, B):
+            SA, SB, lam, V, _ = sign_fwd(A.detach(), B.detach())
+            ctx.save_for_backward(lam, V)
+            return SA, SB
+
+        @staticmethod
+        def backward(ctx, gSA, gSB):
+            lam, V = ctx.saved_tensors
+            if gSA is None:
+                gSA = torch.zeros_like(V[: V.shape[0] // 2, : V.shape[0] // 2])
+            if gSB is None:
+                gSB = torch.zeros_like(V[: V.shape[0] // 2, : V.shape[0] // 2])
+            return sign_bwd(lam, V, gSA, gSB)
+
+    return PseudosymSign
+
+
+def __getattr__(name):
+    if name == "PseudosymSign":
+        cls = _make_autograd()
+        globals()["PseudosymSign"] = cls
+        return cls
+    raise AttributeError(name)

@@ -380,3 +380,70 @@ void jacobi_leaves(hipStream_t s, const double* b, int ld, const int* leaf_o, co
 }
 
 }  // namespace ps
+
+namespace ps {
+
+// ------------------------------------------------------------------ adjoint helpers
+// G (np x np, zero padded) = [[gA, -gB], [0, 0]]: the loss gradient with respect to
+// sign(H) = [[S_A, S_B], [-S_B, -S_A]], placed in the first block row, times Sigma.
+__global__ void build_gbar_kernel(const double* ga, const double* gb, int ldg, int m, double* g,
+                                  int np) {
+  PS_GRID_LOOP(e, (size_t)np * np) {
+    const int i = (int)(e % np), j = (int)(e / np);
+    double v = 0.0;
+    if (i < m) {
+      if (j < m) v = ga[i + (size_t)j * ldg];
+      else if (j < 2 * m) v = -gb[i + (size_t)(j - m) * ldg];
+    }
+    g[e] = v;
+  }
+}
+
+void build_gbar(hipStream_t s, const double* ga, const double* gb, int ldg, int m, double* g,
+                int np) {
+  hipLaunchKernelGGL(build_gbar_kernel, dim3(grid_for((size_t)np * np)), dim3(NT), 0, s, ga, gb,
+                     ldg, m, g, np);
+  PS_HIP(hipGetLastError());
+}
+
+// T(i, j) <- -F_ij T(i, j), F_ij = (s_i - s_j) / (lambda_i - lambda_j) (0 when s_i = s_j),
+// s = +1 on the first m indices, -1 on the next m; padding (>= 2m) cleared.
+__global__ void dk_hadamard_kernel(double* t, int np, const double* lam, int m) {
+  PS_GRID_LOOP(e, (size_t)np * np) {
+    const int i = (int)(e % np), j = (int)(e / np);
+    double v = 0.0;
+    if (i < 2 * m && j < 2 * m && ((i < m) != (j < m))) {
+      const double si = i < m ? 1.0 : -1.0;
+      v = -t[e] * (si - (-si)) / (lam[i] - lam[j]);
+    }
+    t[e] = v;
+  }
+}
+
+void dk_hadamard(hipStream_t s, double* t, int np, const double* lam, int m) {
+  hipLaunchKernelGGL(dk_hadamard_kernel, dim3(grid_for((size_t)np * np)), dim3(NT), 0, s, t, np,
+                     lam, m);
+  PS_HIP(hipGetLastError());
+}
+
+// gA = sym(K11 + K22), gB = sym(K12 + K21) for K (np x np), blocks of size m
+__global__ void grad_assemble_kernel(const double* k, int np, int m, double* ga, double* gb,
+                                     int ldo) {
+  PS_GRID_LOOP(e, (size_t)m * m) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    auto K = [&](int r, int c) { return k[r + (size_t)c * np]; };
+    ga[i + (size_t)j * ldo] =
+        0.5 * ((K(i, j) + K(m + i, m + j)) + (K(j, i) + K(m + j, m + i)));
+    gb[i + (size_t)j * ldo] =
+        0.5 * ((K(i, m + j) + K(m + i, j)) + (K(j, m + i) + K(m + j, i)));
+  }
+}
+
+void grad_assemble(hipStream_t s, const double* k, int np, int m, double* ga, double* gb,
+                   int ldo) {
+  hipLaunchKernelGGL(grad_assemble_kernel, dim3(grid_for((size_t)m * m)), dim3(NT), 0, s, k, np, m,
+                     ga, gb, ldo);
+  PS_HIP(hipGetLastError());
+}
+
+}  // namespace ps

@@ -940,7 +940,8 @@ int eig_split(hipStream_t s, char* base, EigBuffers& e, int m, int o, int n, con
 }
 
 int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* lam,
-            double* V, int ldv, const ps_opts& o, ps_info* info) {
+            double* V, int ldv, const ps_opts& o, ps_info* info, double* SA = nullptr,
+            double* SB = nullptr, int lds = 0) {
   hipStream_t s = h->stream;
   char* base = workspace_base(h, workspace_bytes(m, o, 2));
   if (!base) return PS_NO_WORKSPACE;
@@ -959,6 +960,16 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
   if (st != PS_OK) {
     if (info) *info = inf;
     return st;
+  }
+  if (SA && SB) {
+    // the blocks of sign(H) from the division step, before the recursion reuses its buffers
+    Arena ra;
+    ra.base = base;
+    ra.dry = false;
+    Buffers db;
+    carve(ra, db, m, resolve_r(o), 1, o.precision == PS_PREC_MIXED);
+    copy_out(s, db.as, mp, SA, lds, m, m);
+    copy_out(s, db.bs, mp, SB, lds, m, m);
   }
   copy_pad(s, e.qf, 2 * m, m, m, e.qt, mp, mp, mp);
   copy_pad(s, e.qf + m, 2 * m, m, m, e.qb, mp, mp, mp);
@@ -1052,6 +1063,48 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
   return PS_OK;
 }
 
+
+
+// Adjoint of the sign function: with H = V diag(lambda) V^{-1} from the eigen-
+// decomposition (V^{-1} = Sigma_hat V^T Sigma, Thm. EVREalSigmaOrth), the gradient of a
+// loss with respect to H is V^{-T} (F o (V^T G V^{-T})) V^T, F the divided differences
+// of sign on the eigenvalues; the blocks of dH = [[dA, dB], [-dB, -dA]] then give the
+// gradients of A and B.  Four 2m x 2m matrix-core GEMMs and element-wise kernels.
+size_t adjoint_bytes(int m) {
+  const size_t np = (size_t)pad_to(2 * m);
+  return 4 * np * np * sizeof(double) + 5 * kAlign;
+}
+
+int run_sign_bwd(ps_handle h, int m, const double* lam, const double* V, int ldv,
+                 const double* gSA, const double* gSB, int ldg, double* gA, double* gB,
+                 int ldo) {
+  hipStream_t s = h->stream;
+  char* base = workspace_base(h, adjoint_bytes(m));
+  if (!base) return PS_NO_WORKSPACE;
+  const int np = pad_to(2 * m);
+  const size_t S = (size_t)np * np;
+  Arena a;
+  a.base = base;
+  a.dry = false;
+  double* vp = a.take<double>(S);
+  double* g = a.take<double>(S);
+  double* u = a.take<double>(S);
+  double* t = a.take<double>(S);
+  copy_pad(s, V, ldv, 2 * m, 2 * m, vp, np, np, np);
+  build_gbar(s, gSA, gSB, ldg, m, g, np);
+  GemmProblem p1 = gemm_problem(np, np, np, g, np, 0, vp, np, 0, u, np);     // (G Sigma) V
+  gemm_f64(s, p1);
+  GemmProblem p2 = gemm_problem(np, np, np, vp, np, 1, u, np, 0, t, np);     // V^T (G Sigma) V
+  gemm_f64(s, p2);
+  dk_hadamard(s, t, np, lam, m);
+  GemmProblem p3 = gemm_problem(np, np, np, vp, np, 0, t, np, 0, u, np);     // V M
+  gemm_f64(s, p3);
+  GemmProblem p4 = gemm_problem(np, np, np, u, np, 0, vp, np, 1, g, np);     // V M V^T
+  gemm_f64(s, p4);
+  grad_assemble(s, g, np, m, gA, gB, ldo);
+  PS_HIP(hipStreamSynchronize(s));
+  return PS_OK;
+}
 
 int check_common(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                  const ps_opts* o) {
@@ -1219,7 +1272,8 @@ size_t ps_workspace_size(int m, const ps_opts* o, int what) {
   ps_opts d;
   ps_opts_default(&d);
   if (m < 1) return 0;
-  return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : (what > 2 ? 2 : what));
+  if (what >= 3) return adjoint_bytes(m);
+  return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : what);
 }
 
 int ps_set_workspace(ps_handle h, void* dptr, size_t bytes) {
@@ -1324,6 +1378,44 @@ int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double*
   return guarded(h, [&] {
     return run_batched(h, batch, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, infos);
   });
+}
+
+int pseudosym_sign_fwd(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                       double* SA, double* SB, int lds, double* lambda, double* V, int ldv,
+                       const ps_opts* opts, ps_info* info) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (!SA) return -7;
+  if (!SB) return -8;
+  if (lds < m) return -9;
+  if (!lambda) return -10;
+  if (!V) return -11;
+  if (ldv < 2 * m) return -12;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  o.timing = 0;
+  return guarded(h, [&] {
+    return run_eig(h, m, A, lda, B, ldb, lambda, V, ldv, o, info, SA, SB, lds);
+  });
+}
+
+int pseudosym_sign_bwd(ps_handle h, int m, const double* lambda, const double* V, int ldv,
+                       const double* gSA, const double* gSB, int ldg, double* gA, double* gB,
+                       int ldo) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (!lambda) return -3;
+  if (!V) return -4;
+  if (ldv < 2 * m) return -5;
+  if (!gSA) return -6;
+  if (!gSB) return -7;
+  if (ldg < m) return -8;
+  if (!gA) return -9;
+  if (!gB) return -10;
+  if (ldo < m) return -11;
+  return guarded(h, [&] { return run_sign_bwd(h, m, lambda, V, ldv, gSA, gSB, ldg, gA, gB, ldo); });
 }
 
 const char* ps_status_string(int st) {

@@ -174,6 +174,12 @@ void canon_sign(hipStream_t s, double* v, int ldv, int rows, int cols);
 void jacobi_leaves(hipStream_t s, const double* b, int ld, const int* leaf_o, const int* leaf_n,
                    int nleaves, double* z, int ldz, double* lam, int* sweeps_out);
 void fill_int_zero(hipStream_t s, int* x, int n);
+// adjoint of the sign function (divided-difference form in the eigenbasis)
+void build_gbar(hipStream_t s, const double* ga, const double* gb, int ldg, int m, double* g,
+                int np);
+void dk_hadamard(hipStream_t s, double* t, int np, const double* lam, int m);
+void grad_assemble(hipStream_t s, const double* k, int np, int m, double* ga, double* gb,
+                   int ldo);
 
 // Golub-Kahan bidiagonalization (batch of two matrices M_b with transposes Mt_b).
 void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned seed);
