@@ -144,6 +144,81 @@ def batched_leg(args):
             "modes": out}
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, out
+
+
+def eig_leg(args):
+    """All eigenpairs (pseudosym_eig): n = 128 (the plain-method case, seed 0) or
+    n = 4096 (the Casida-like workload); error against the oracle's definition."""
+    import numpy as np
+    import torch
+    from oracle import eig as eg
+    from oracle import sign as sg
+    from paper_2203_08900_amd import api, inputs
+
+    if args.workload == "eig_n128":
+        m = 64
+        a, b = inputs.small_dense(m, 0)
+        desc = "small_dense m=64 (n=128) seed 0: A = Q diag(U[1,10]) Q^T, ||B|| = 0.5 lambda_min(A)"
+    else:
+        m = 2048
+        a, b = inputs.casida_like(m, 1)
+        desc = "casida_like m=2048 (n=4096) seed 1"
+    A = torch.tensor(a, dtype=torch.float64, device="cuda:0")
+    B = torch.tensor(b, dtype=torch.float64, device="cuda:0")
+    ms, (lam, V, info) = _timed(lambda: api.eig(A, B), args.steps, args.warmup)
+    lam_ref, _ = eg.eig_casida(a, b)
+    lam = lam.cpu().numpy()
+    Vn = V.cpu().numpy()
+    h = sg.casida_matrix(a, b)
+    res = float(np.abs(h @ Vn - Vn * lam[None, :]).max() / np.abs(h).max())
+    err = float(np.max(np.abs(lam - lam_ref) / np.abs(lam_ref)))
+    return {"metric": "all eigenpairs of H (pseudosym_eig)", "value": ms, "unit": "ms",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": desc, "n": 2 * m, "m": m},
+            "rel_eig_err": err, "residual": res, "splits": info["eig_splits"],
+            "leaves": info["eig_leaves"], "max_jacobi_sweeps": info["eig_sweeps"]}
+
+
+def adjoint_leg(args):
+    """Forward (sign blocks + eigen-decomposition) and backward (adjoint) of the
+    differentiable sign at n = 2048: casida_like(1024, 3), loss trace(W P_+)."""
+    import numpy as np
+    import torch
+    from oracle import grad as gr
+    from paper_2203_08900_amd import api, inputs
+
+    m = 1024
+    a, b = inputs.casida_like(m, 3)
+    w = inputs.gradient_weight(m, 1003)
+    A = torch.tensor(a, dtype=torch.float64, device="cuda:0")
+    B = torch.tensor(b, dtype=torch.float64, device="cuda:0")
+    ms_f, (SA, SB, lam, V, _) = _timed(lambda: api.sign_fwd(A, B), args.steps, args.warmup)
+    gsa = torch.tensor(0.5 * (w[:m, :m] - w[m:, m:]).T, dtype=torch.float64, device="cuda:0")
+    gsb = torch.tensor(0.5 * (w[m:, :m] - w[:m, m:]).T, dtype=torch.float64, device="cuda:0")
+    ms_b, (gA, gB) = _timed(lambda: api.sign_bwd(lam, V, gsa, gsb), args.steps, args.warmup)
+    ra, rb = gr.projector_loss_grad(a, b, w)
+    err = float(max(np.linalg.norm(gA.cpu().numpy() - ra) / np.linalg.norm(ra),
+                    np.linalg.norm(gB.cpu().numpy() - rb) / np.linalg.norm(rb)))
+    return {"metric": "gradient of trace(W P_+) w.r.t. (A, B)", "value": ms_f + ms_b,
+            "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_f + ms_b, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "casida_like m=1024 (n=2048) seed 3, W symmetric Gaussian "
+                                   "seed 1003", "n": 2 * m, "m": m},
+            "forward_ms": ms_f, "backward_ms": ms_b, "rel_grad_err_vs_oracle": err}
+
+
 def copy_probe(nbytes: int = 512 << 20):
     """A plain streaming kernel of known size: y = -x over nbytes of FP64 (reads and
     writes nbytes each)."""
@@ -222,7 +297,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="casida_n4096",
-                    choices=["casida_n4096", "ill_separated_n16384", "batched_256"])
+                    choices=["casida_n4096", "ill_separated_n16384", "batched_256", "eig_n128",
+                             "eig_n4096", "adjoint_n2048"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--modes", default="fp64,mixed")
@@ -245,6 +321,12 @@ def main():
     exact = None
     if args.workload == "batched_256":
         print(json.dumps(batched_leg(args)), flush=True)
+        return
+    if args.workload in ("eig_n128", "eig_n4096"):
+        print(json.dumps(eig_leg(args)), flush=True)
+        return
+    if args.workload == "adjoint_n2048":
+        print(json.dumps(adjoint_leg(args)), flush=True)
         return
     if args.workload == "casida_n4096":
         args.m = args.m or 2048
