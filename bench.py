@@ -3,13 +3,19 @@
 H = [[A, B], [-B, -A]] at n = 4096 (A, B of size m = 2048), Casida-like blocks.
 
 One "step" is one pseudosym_divide call (estimate alpha/beta, two Zolotarev steps,
-sign(H) blocks, Alg. 6 basis, decoupled H_+) on inputs already resident in device
-memory.  Prints one JSON line (rank 0, one GPU).
+Sigma-orthonormal basis of the positive invariant subspace, decoupled H_+) on inputs
+already resident in device memory.  Prints one JSON line (rank 0, one GPU).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes fp64,mixed] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes ...] [--no-cpu]
+                    [--workload casida_n4096|ill_separated_n16384|batched_256|eig_n128|
+                                eig_n4096|adjoint_n2048]
 
-value      : TFLOP/s of the primary precision mode = nominal algorithmic flops of the
-             executed variant / measured time (flop convention below).
+modes      : fp64 / mixed (precision of the Zolotarev steps) x basis (Alg. 6, or
+             "-core": the basis from the half-size core); all are timed and reported,
+             the primary one (the first of mixed-core, mixed, fp64-core, fp64 that was
+             run) gives `value`.
+value      : TFLOP/s of the primary mode = nominal algorithmic flops of the executed
+             variant / measured time (flop convention below).
 roofline   : the large-tile FP64 GEMM kernel (the dominant kernel class), its
              algorithmic flops per launch over its average launch duration, timed
              with HIP events around each launch on the library's stream during a
@@ -34,10 +40,10 @@ METRIC = "sign-fn+divide time & TFLOP/s at n=4096, mixed vs FP64, rel eig err â‰
 PEAK = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix-core peaks, TFLOP/s
 
 
-def nominal_flops(m: int, r: int, step2_terms: int) -> float:
+def nominal_flops(m: int, r: int, step2_terms: int, basis: str = "alg6") -> float:
     """Algorithmic flops of the executed divide (standard LAPACK conventions: GEMM 2mnk,
-    SYRK n^2 k, POTRF m^3/3, TRTRI m^3/3, triangular x full m^3, triangular x
-    triangular 2m^3/3)."""
+    SYRK n^2 k, POTRF m^3/3, TRTRI m^3/3, triangular x full m^3, upper x lower
+    triangular 2m^3/3, upper x upper triangular m^3/3)."""
     m3 = float(m) ** 3
     setup = 2 * (m3 / 3 + m3 / 3) + 2 * (2 * m3 / 3)        # chol+inverse of A+-B, Y0, Y0^-1
     step1 = m3 + r * (m3 / 3 + m3 / 3 + m3 / 3) + 2 * m3     # X^T X, r x (POTRF, TRTRI, W W^T), X(I+N)
@@ -45,10 +51,15 @@ def nominal_flops(m: int, r: int, step2_terms: int) -> float:
         step2 = m3 + max(step2_terms - 2, 0) * 2 * m3 + 2 * m3   # X^T X, Horner, X T
     else:
         step2 = step1
-    assemble = 4 * m3                                         # S12 = W_M U R_K, S21 = R_M^T U W_K^T
-    bases = 2 * m3 / 3 + m3                                   # chol+inverse of (I+A_s)/2, B_s C^{-1}
-    decouple = 2 * m3 + 2 * m3                                # R_M a, R_K b, F^T F (K = 2m)
-    return setup + step1 + step2 + assemble + bases + decouple
+    if basis == "core":
+        # R_M^-1 U, R_K^-T (.), chol+inverse of G, (.) R_G^-1, R_K^-1 R_G^-1, H_+ (upper half)
+        tail = m3 + m3 + 2 * m3 / 3 + m3 + m3 / 3 + m3 / 3
+    else:
+        assemble = 4 * m3                                     # S12 = W_M U R_K, S21 = R_M^T U W_K^T
+        bases = 2 * m3 / 3 + m3                               # chol+inverse of (I+A_s)/2, B_s C^{-1}
+        decouple = 2 * m3 + 2 * m3                            # R_M a, R_K b, F^T F (K = 2m)
+        tail = assemble + bases + decouple
+    return setup + step1 + step2 + tail
 
 
 def gpu_leg(args, a, b):
@@ -61,7 +72,8 @@ def gpu_leg(args, a, b):
     torch.cuda.synchronize()
     out = {}
     for mode in args.modes:
-        kw = dict(precision=mode, r=args.r)
+        kw = dict(precision=mode.split("-")[0], r=args.r,
+                  basis="core" if mode.endswith("-core") else "alg6")
         for _ in range(args.warmup):
             api.divide(A, B, **kw)
         torch.cuda.synchronize()
@@ -73,7 +85,7 @@ def gpu_leg(args, a, b):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         info = infos[-1]
-        flops = nominal_flops(args.m, info["r"], info["step2_terms"])
+        flops = nominal_flops(args.m, info["r"], info["step2_terms"], kw["basis"])
         # instrumented pass: per-phase and per-launch kernel times
         gl, gms, gfl = 0, 0.0, 0.0
         phase = [0.0] * 8
@@ -110,7 +122,8 @@ def batched_leg(args):
     Bs = [torch.tensor(b, dtype=torch.float64, device="cuda:0") for _, b in probs]
     out = {}
     for mode in args.modes:
-        kw = dict(precision=mode, r=args.r)
+        kw = dict(precision=mode.split("-")[0], r=args.r,
+                  basis="core" if mode.endswith("-core") else "alg6")
         for _ in range(args.warmup):
             api.divide_batched(As, Bs, **kw)
         torch.cuda.synchronize()
@@ -124,7 +137,8 @@ def batched_leg(args):
             api.divide(A, B, **kw)
         torch.cuda.synchronize()
         ms_seq = (time.perf_counter() - t0) * 1e3
-        flops = sum(nominal_flops(mi, inf["r"], inf["step2_terms"]) for mi, inf in zip(sizes, infos))
+        flops = sum(nominal_flops(mi, inf["r"], inf["step2_terms"], kw["basis"])
+                    for mi, inf in zip(sizes, infos))
         err = 0.0
         for i in range(0, 256, 32):
             a, b = probs[i]
@@ -133,11 +147,12 @@ def batched_leg(args):
             err = max(err, float(np.max(np.abs(w - lam) / lam)))
         out[mode] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "ms_one_at_a_time": ms_seq,
                      "rel_eig_err_sampled": err}
-    primary = "mixed" if "mixed" in out else args.modes[0]
+    primary = next((k for k in ("mixed-core", "mixed", "fp64-core", "fp64") if k in out),
+                   args.modes[0])
     return {"metric": "batched sign-fn+divide, 256 problems n_i in {64..1024}", "value":
             out[primary]["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": out[primary]["ms"], "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if primary == "fp64" else "f32+f64",
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if primary.startswith("fp64") else "f32+f64",
             "data": "synthetic", "config": {"workload": "batched_256: m_i uniform over {32..512} "
                                             "(seed 2), small_dense(m_i, i) blocks",
                                             "problems": 256, "precision": primary},
@@ -301,7 +316,7 @@ def main():
                              "eig_n4096", "adjoint_n2048"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
     ap.add_argument("--r", type=int, default=8)
-    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--modes", default="fp64,mixed,fp64-core,mixed-core")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain device copy of 512 MiB three times (calibrates the "
@@ -342,7 +357,8 @@ def main():
         desc = (f"ill_separated m={args.m} (n={2 * args.m}) seed 4: eig((A-B)(A+B)) = mu, "
                 "log-uniform in [1e-6, 1], l = 1e-3")
     g = gpu_leg(args, a, b)
-    primary = "mixed" if "mixed" in g else args.modes[0]
+    primary = next((k for k in ("mixed-core", "mixed", "fp64-core", "fp64") if k in g),
+                   args.modes[0])
     res = g[primary]
 
     cpu = None
@@ -387,7 +403,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if primary == "fp64" else "f32+f64",
+        "dtype": "f64" if primary.startswith("fp64") else "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc,
                    "n": 2 * args.m, "m": args.m, "r": args.r, "precision": primary,

@@ -61,6 +61,19 @@ enum {
                               FP64 refinement and subspace orthogonalization */
 };
 
+/* Sigma-orthonormal basis Q_+ of the positive invariant subspace (pseudosym_divide):
+ *  PS_BASIS_ALG6: Alg. 6, Q_+ = [C^T; P_{+,21} C^{-1}] with C = chol of the leading
+ *                 block (I + A_s)/2 of P_+ = (I + sign(H))/2; unique (its top block is
+ *                 lower triangular with positive diagonal).
+ *  PS_BASIS_CORE: the same subspace from the half-size core: with Y0 = R_M R_K^T and
+ *                 its polar factor U, Z = Q_h [R_M^{-1} U; R_K^{-1}] (Q_h the symmetric
+ *                 orthogonal [[I, I], [I, -I]]/sqrt(2)) spans it, Z^T Sigma Z = G =
+ *                 Y0^{-1} U + (Y0^{-1} U)^T = R_G^T R_G, Q_+ = Z R_G^{-1} and
+ *                 H_+ = 2 R_G^{-T} R_G^{-1}.  It needs neither the sign blocks nor the
+ *                 Alg. 6 decoupling products; Q_+ differs from the Alg. 6 basis by an
+ *                 orthogonal factor G (H_+ by G^T H_+ G). */
+enum { PS_BASIS_ALG6 = 0, PS_BASIS_CORE = 1 };
+
 typedef struct {
   int precision;       /* PS_PREC_*                                               */
   int r;               /* Zolotarev degree parameter (type (2r+1, 2r)), 1..8;    */
@@ -83,6 +96,8 @@ typedef struct {
                        /* sum_j a_j (X^T X + c_{2j-1} I)^{-1} as the convergent     */
                        /* series in Delta = X^T X - I instead of r factorizations   */
                        /* (the same rational function to below 1e-17)               */
+  int basis;           /* pseudosym_divide / pseudosym_eig: PS_BASIS_ALG6 (default) */
+                       /* or PS_BASIS_CORE, see below                             */
 } ps_opts;
 
 typedef struct {
@@ -112,7 +127,8 @@ typedef struct {
 } ps_info;
 
 /* Fill *o with the defaults: FP64, r = 8, 2 restarts, full method, 20 Lanczos
- * steps, no timing, estimated alpha/beta, mixed_kappa = 20, step2_series = 1. */
+ * steps, no timing, estimated alpha/beta, mixed_kappa = 20, step2_series = 1,
+ * basis = PS_BASIS_ALG6. */
 void ps_opts_default(ps_opts* o);
 
 /* Create a handle bound to `stream` (a hipStream_t, NULL = default stream) on

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libpseudosym.so")
 
 PS_PREC_FP64 = 0
 PS_PREC_MIXED = 1
+PS_BASIS_ALG6 = 0
+PS_BASIS_CORE = 1
 
 STATUS = {
     0: "ok", 1: "not definite", 2: "shift breakdown", 3: "not converged",
@@ -40,6 +42,7 @@ class PsOpts(ctypes.Structure):
         ("beta", ctypes.c_double),
         ("mixed_kappa", ctypes.c_double),
         ("step2_series", ctypes.c_int),
+        ("basis", ctypes.c_int),
     ]
 
 
@@ -162,7 +165,7 @@ def zolotarev_coeffs(ell: float, r: int):
 
 def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=20,
               timing=False, alpha=0.0, beta=0.0, mixed_kappa=20.0,
-              step2_series=True) -> PsOpts:
+              step2_series=True, basis="alg6") -> PsOpts:
     lib = load()
     o = PsOpts()
     lib.ps_opts_default(ctypes.byref(o))
@@ -177,6 +180,8 @@ def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=
     o.beta = float(beta or 0.0)
     o.mixed_kappa = float(mixed_kappa)
     o.step2_series = 1 if step2_series else 0
+    o.basis = {"alg6": PS_BASIS_ALG6, "core": PS_BASIS_CORE}[basis] \
+        if isinstance(basis, str) else int(basis)
     return o
 
 

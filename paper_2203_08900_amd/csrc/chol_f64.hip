@@ -240,7 +240,7 @@ inline void gemm_t(hipStream_t s, const GemmProblemF* p, int n) { gemm_f32(s, p,
 
 template <class T>
 void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, int batch,
-                 int* info) {
+                 int* info, bool inverse = true) {
   zero_lower(s, w, mp, sw, batch);  // the diagonal blocks and W12 blocks cover the rest
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
   const int nbk = mp / NB;
@@ -274,6 +274,7 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     pt.sD[0] = sz;
     gemm_t(s, &pt, 1);
   }
+  if (!inverse) return;   // W then holds only the inverted diagonal blocks
   // ---- W = R^{-1} by recursive doubling over the block diagonal: at level S every
   // diagonal block of size S is already inverted, and for each pair of neighbours
   //   W12 = -W11 R12 W22.
@@ -322,8 +323,8 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
 }
 
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
-                   double* /*tmp*/, int mp, int batch, int* info) {
-  potrf_inv_t(s, z, sz, w, sw, mp, batch, info);
+                   double* /*tmp*/, int mp, int batch, int* info, bool inverse) {
+  potrf_inv_t(s, z, sz, w, sw, mp, batch, info, inverse);
 }
 
 void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,

@@ -458,4 +458,40 @@ void gk_update(hipStream_t s, const double* p, long long pstride, double* w, lon
   PS_HIP(hipGetLastError());
 }
 
+__global__ void sym_scale_upper_kernel(const double* x, double* z, int m, int mp, double scale) {
+  const size_t n = (size_t)mp * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    double v = 0.0;
+    if (i < m && j < m && i <= j) v = scale * (x[e] + x[j + (size_t)i * mp]);
+    else if (i == j) v = 1.0;
+    z[e] = v;
+  }
+}
+
+void sym_scale_upper(hipStream_t s, const double* x, double* z, int m, int mp, double scale) {
+  hipLaunchKernelGGL(sym_scale_upper_kernel, dim3(blocks_for((size_t)mp * mp)), dim3(NT), 0, s, x,
+                     z, m, mp, scale);
+  PS_HIP(hipGetLastError());
+}
+
+__global__ void sum_diff_scaled_kernel(const double* e1, const double* e2, double* top,
+                                       double* bot, double c, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double a = e1[e], b = e2[e];
+    top[e] = c * (a + b);
+    bot[e] = c * (a - b);
+  }
+}
+
+void sum_diff_scaled(hipStream_t s, const double* e1, const double* e2, double* top, double* bot,
+                     double c, int mp) {
+  const size_t n = (size_t)mp * mp;
+  hipLaunchKernelGGL(sum_diff_scaled_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, e1, e2, top, bot,
+                     c, n);
+  PS_HIP(hipGetLastError());
+}
+
 }  // namespace ps

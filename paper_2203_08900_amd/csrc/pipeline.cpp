@@ -700,8 +700,49 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     return status;
   }
 
-  // ---- blocks of sign(H):  S12 = W_M U R_K,  S21 = R_M^T U W_K^T
   const double* U = b.x2;
+  if (what == 1 && o.basis == PS_BASIS_CORE) {
+    // ---- basis from the half-size core (no sign blocks needed).  With Q_h the
+    // orthogonal symmetric [[I, I], [I, -I]]/sqrt(2), Q_h H Q_h = [[0, K], [M, 0]] maps
+    // Z = Q_h [R_M^{-1} U; R_K^{-1}] onto Z P, P = U^T Y0, when U is the polar factor of
+    // Y0, so range(Z) is the invariant subspace of the positive eigenvalues.  For any U,
+    // Z^T Sigma Z = G = Y0^{-1} U + (Y0^{-1} U)^T (Y0^{-1} = R_K^{-T} R_M^{-1}) and
+    // Z^T Sigma H Z = I + U^T U; with G = R_G^T R_G the basis Q_+ = Z R_G^{-1} is
+    // Sigma-orthonormal whatever the accuracy of U, and H_+ = R_G^{-T} (I + U^T U) R_G^{-1}
+    // = 2 R_G^{-T} R_G^{-1} (U orthogonal), the Rayleigh-Ritz block of that subspace.
+    tm.mark(5);
+    GemmProblem pt = gemm_problem(mp, mp, mp, b.wmk, mp, 0, U, mp, 0, b.t1, mp, 1.0, 0.0, nullptr,
+                                  0, kAUpper);                    // T1 = R_M^{-1} U
+    auto_split(pt, b.splitws);
+    gemm_f64(s, pt);
+    GemmProblem pv = gemm_problem(mp, mp, mp, b.wmk + S, mp, 1, b.t1, mp, 0, b.t2, mp, 1.0, 0.0,
+                                  nullptr, 0, kALower);           // R_K^{-T} T1 = Y0^{-1} U
+    auto_split(pv, b.splitws);
+    gemm_f64(s, pv);
+    sym_scale_upper(s, b.t2, b.p11, m, mp, 1.0);              // upper(G), padding I
+    potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4);
+    {
+      GemmProblem pe[2];
+      pe[0] = gemm_problem(mp, mp, mp, b.t1, mp, 0, b.wc, mp, 0, b.t2, mp, 1.0, 0.0, nullptr, 0,
+                           kBUpper);                              // R_M^{-1} U R_G^{-1}
+      pe[1] = gemm_problem(mp, mp, mp, b.wmk + S, mp, 0, b.wc, mp, 0, b.s12, mp, 1.0, 0.0,
+                           nullptr, 0, kAUpper | kBUpper);        // R_K^{-1} R_G^{-1}
+      gemm_f64(s, pe, 2);
+      sum_diff_scaled(s, b.t2, b.s12, b.top, b.qbot, M_SQRT1_2, mp);
+    }
+    tm.mark(6);
+    {
+      GemmProblem ph = gemm_problem(mp, mp, mp, b.wc, mp, 1, b.wc, mp, 0, b.hp, mp, 2.0, 0.0,
+                                    nullptr, 0, kALower | kBUpper | kOutUpper | kMirror);
+      auto_split(ph, b.splitws);
+      gemm_f64(s, ph);
+    }
+    tm.mark(7);
+    copy_out(s, b.top, mp, out1, ld1, m, m);
+    copy_out(s, b.qbot, mp, out1 + m, ld1, m, m);
+    copy_out(s, b.hp, mp, out2, ld2, m, m);
+  } else {
+  // ---- blocks of sign(H):  S12 = W_M U R_K,  S21 = R_M^T U W_K^T
   {
     GemmProblem pg[2];
     pg[0] = gemm_problem(mp, mp, mp, U, mp, 0, b.mk + S, mp, 0, b.t1, mp, 1.0, 0.0, nullptr, 0,
@@ -754,6 +795,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     copy_out(s, b.top, mp, out1, ld1, m, m);
     copy_out(s, b.qbot, mp, out1 + m, ld1, m, m);
     copy_out(s, b.hp, mp, out2, ld2, m, m);
+  }
   }
   PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
@@ -1115,7 +1157,8 @@ int check_common(ps_handle h, int m, const double* A, int lda, const double* B, 
   if (!B) return -5;
   if (ldb < m) return -6;
   if (o && (o->r < 0 || o->r > 8 || o->max_restarts < 0 || o->max_steps < 0 ||
-            o->max_steps > 1 || (o->precision != PS_PREC_FP64 && o->precision != PS_PREC_MIXED)))
+            o->max_steps > 1 || (o->precision != PS_PREC_FP64 && o->precision != PS_PREC_MIXED) ||
+            (o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE)))
     return -11;
   return 0;
 }
@@ -1209,6 +1252,7 @@ void ps_opts_default(ps_opts* o) {
   o->beta = 0.0;
   o->mixed_kappa = 20.0;
   o->step2_series = 1;
+  o->basis = PS_BASIS_ALG6;
 }
 
 int ps_create(ps_handle* h, void* stream) {
@@ -1396,6 +1440,7 @@ int pseudosym_sign_fwd(ps_handle h, int m, const double* A, int lda, const doubl
   if (opts) o = *opts;
   o.max_steps = 0;
   o.timing = 0;
+  o.basis = PS_BASIS_ALG6;   // the forward returns the sign blocks of that path
   return guarded(h, [&] {
     return run_eig(h, m, A, lda, B, ldb, lambda, V, ldv, o, info, SA, SB, lds);
   });

@@ -109,7 +109,7 @@ inline void gemm_f32(hipStream_t s, const GemmProblemF& p) { gemm_f32(s, &p, 1);
 // batch * mp * kNb doubles.  A non-positive pivot in matrix b sets bit min(b, 30) of
 // the device int *info.
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
-                   double* tmp, int mp, int batch, int* info);
+                   double* tmp, int mp, int batch, int* info, bool inverse = true);
 // the same in FP32 (pivots taken and inverted through FP64 square roots)
 void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,
                    int batch, int* info);
@@ -139,6 +139,12 @@ void basis_mix(hipStream_t s, const double* c, const double* qbot, double* top_o
 void copy_out(hipStream_t s, const double* x, int ldx, double* y, int ldy, int rows,
               int cols);
 void diff_norms(hipStream_t s, const double* x1, const double* x2, size_t n, double* out2);
+
+// z = upper(scale (x + x^T)) on the first m rows/columns, 1 on the padded diagonal
+void sym_scale_upper(hipStream_t s, const double* x, double* z, int m, int mp, double scale);
+// top = c (e1 + e2), bot = c (e1 - e2)
+void sum_diff_scaled(hipStream_t s, const double* e1, const double* e2, double* top, double* bot,
+                     double c, int mp);
 
 // mixed-precision helpers (mixed.hip)
 void form_shifts_f32(hipStream_t s, const double* g, float* z, int mp, const double* shifts,

@@ -259,3 +259,32 @@ def test_mixed_full_size_casida_n4096():
     w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
     lam, _ = eg.eig_casida(a, b)
     assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-10
+
+
+@pytest.mark.parametrize("m,seed,kind", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_divide_core_basis(m, seed, kind, precision):
+    """The core basis spans the same subspace as Alg. 6: the projector Q_+ Q_+^T Sigma
+    agrees with the oracle's element by element, G = Q_alg6^T Sigma Q_core is orthogonal
+    and H_+ (core) = G^T H_+ (oracle) G."""
+    print(f"[core basis] m={m} seed={seed} kind={kind} {precision}", flush=True)
+    a, b = make(m, seed, kind)
+    al, be = bounds(a, b)
+    ref = dv.divide_casida(a, b, alpha=al, beta=be)
+    Qp, Hp, info = api.divide(dev(a), dev(b), alpha=al, beta=be, basis="core",
+                              precision=precision)
+    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+    assert info["status"] == 0
+    sigma = sg.casida_sigma(m)
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    assert np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max() < 1e-12
+    P = Qp @ (Qp.T * sigma[None, :])
+    Pref = ref["Q_plus"] @ (ref["Q_plus"].T * sigma[None, :])
+    assert np.abs(P - Pref).max() < tol * max(1.0, np.abs(Pref).max())
+    G = ref["Q_plus"].T @ (sigma[:, None] * Qp)
+    assert np.abs(G.T @ G - np.eye(m)).max() < (1e-11 if precision == "fp64" else 1e-5)
+    assert rel(Hp, G.T @ ref["H_plus"] @ G) < tol
+    assert np.array_equal(Hp, Hp.T)
+    lam, _ = eg.eig_casida(a, b)
+    w = np.linalg.eigvalsh(Hp)
+    assert np.max(np.abs(w - lam[:m]) / lam[:m]) < (1e-12 if precision == "fp64" else 1e-10)
