@@ -58,7 +58,9 @@ enum {
 enum {
   PS_PREC_FP64 = 0,        /* everything in FP64 (plain form) */
   PS_PREC_MIXED = 1        /* FP32 matrix-core bulk, FP64 for ill-conditioned shifts,
-                              FP64 refinement and subspace orthogonalization */
+                              FP64 refinement and subspace orthogonalization; problems
+                              with m < 1024 (padded) run in FP64, where the split does
+                              not pay */
 };
 
 /* Sigma-orthonormal basis Q_+ of the positive invariant subspace (pseudosym_divide):

@@ -690,7 +690,10 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
 
   // ---- Zolotarev steps with the stopping test of Alg. 8
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
-  const bool mixed = o.precision == PS_PREC_MIXED;
+  // below kMixedMin the FP32 group's extra launches and stream hand-offs cost more than
+  // its arithmetic saves (measured on 256 problems of 32..512): those sizes run in FP64
+  constexpr int kMixedMin = 1024;
+  const bool mixed = o.precision == PS_PREC_MIXED && mp >= kMixedMin;
   const int status =
       polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm, mixed ? &mxc : nullptr);
   if (status != PS_OK) {

@@ -218,28 +218,41 @@ def test_full_size_casida_n4096():
     assert np.abs(s @ (s @ e) - e).max() < 1e-10
 
 
-@pytest.mark.parametrize("m,seed,kind", [CASES[5], CASES[6], CASES[7]])
-def test_mixed_divide(m, seed, kind):
-    """Mixed precision: well-conditioned shifts of the first step and the second step's
-    correction in FP32, everything else FP64.  The subspace moves by about
-    kappa * u_32 (kappa = mixed_kappa), so Q_+ agrees with the FP64 oracle to ~1e-5,
-    Q_+ stays Sigma-orthonormal to FP64 accuracy (the FP64 Delta = X^T X - I of the
-    second step restores orthogonality) and the eigenvalues of H_+, Rayleigh-Ritz
-    values of that subspace, are within the square of that: target 1e-10."""
-    print(f"[mixed divide] m={m} seed={seed} kind={kind}", flush=True)
+@pytest.mark.parametrize("m,seed,kind", [CASES[5], CASES[7]])
+def test_mixed_small_falls_back_to_fp64(m, seed, kind):
+    """Below the padded size 1024 the mixed mode runs the FP64 steps: same result."""
     a, b = make(m, seed, kind)
-    al, be = bounds(a, b)
-    ref = dv.divide_casida(a, b, alpha=al, beta=be)
-    Qp, Hp, info = api.divide(dev(a), dev(b), alpha=al, beta=be, precision="mixed")
-    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
-    assert info["status"] == 0
-    assert 0 < info["shifts_fp64"][0] < 8 and info["shifts_fp64"][1] == 0
-    assert rel(Qp, ref["Q_plus"]) < 1e-5
+    Q1, H1, i1 = api.divide(dev(a), dev(b), precision="fp64")
+    Q2, H2, i2 = api.divide(dev(a), dev(b), precision="mixed")
+    assert i2["shifts_fp64"][0] == 8
+    assert torch.equal(Q1, Q2) and torch.equal(H1, H2)
+
+
+@pytest.mark.timeout(300)
+def test_mixed_divide_m1100():
+    """Mixed precision: well-conditioned shifts of the first step (and the second step's
+    correction when ||Delta|| is tiny) in FP32, everything else FP64.  The subspace moves
+    by about kappa * u_32 (kappa = mixed_kappa), so the projector agrees with the
+    definition to ~1e-5, Q_+ stays Sigma-orthonormal to FP64 accuracy and the
+    eigenvalues of H_+, Rayleigh-Ritz values of that subspace, are within the square of
+    that: target 1e-10."""
+    m = 1100
+    a, b = inputs.casida_like(m, 21, rank=16)
+    print("[mixed divide] m=1100", flush=True)
     sigma = sg.casida_sigma(m)
-    assert np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max() < 1e-11
     lam, _ = eg.eig_casida(a, b)
-    w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
-    assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-10
+    s = sg.sign_definition(sg.casida_matrix(a, b), sigma)
+    Pref = 0.5 * (np.eye(2 * m) + s)
+    for basis in ("alg6", "core"):
+        Qp, Hp, info = api.divide(dev(a), dev(b), precision="mixed", basis=basis)
+        Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+        assert info["status"] == 0
+        assert 0 < info["shifts_fp64"][0] < 8
+        assert np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max() < 1e-11
+        P = Qp @ (Qp.T * sigma[None, :])
+        assert np.abs(P - Pref).max() < 1e-5
+        w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
+        assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-10
 
 
 @pytest.mark.timeout(400)
