@@ -17,8 +17,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -208,6 +210,25 @@ void carve_eig(Arena& a, EigBuffers& e, int m) {
   e.sweeps = a.take<int>(16);
 }
 
+// Subtrees of at most this many columns run on the recursion workers, each with a
+// scratch region sized for it.
+inline int eig_worker_cap(int m) { return std::max(64, pad_to((m + 1) / 2)); }
+constexpr int kEigWorkers = 4;
+
+void carve_eig_worker(Arena& a, int m, char** base, double** vs, double** t, double** zbd,
+                      double** dscr, int** perm) {
+  const int mp = pad_to(m), cap = eig_worker_cap(m);
+  Arena d;
+  Buffers b;
+  carve(d, b, cap, 8, 2);
+  *base = a.take<char>(d.off);
+  *vs = a.take<double>((size_t)mp * cap);
+  *t = a.take<double>((size_t)mp * cap);
+  *zbd = a.take<double>((size_t)cap * cap);
+  *dscr = a.take<double>(mp);
+  *perm = a.take<int>(mp);
+}
+
 size_t workspace_bytes(int m, const ps_opts& o, int what) {
   Arena a;
   Buffers b;
@@ -215,6 +236,12 @@ size_t workspace_bytes(int m, const ps_opts& o, int what) {
     a.off = eig_region_offset(m, o);
     EigBuffers e;
     carve_eig(a, e, m);
+    for (int k = 0; k < kEigWorkers; ++k) {
+      char* base;
+      double *vs, *t, *zbd, *dscr;
+      int* perm;
+      carve_eig_worker(a, m, &base, &vs, &t, &zbd, &dscr, &perm);
+    }
     return a.off + kAlign;
   }
   carve(a, b, m, resolve_r(o), what, o.precision == PS_PREC_MIXED);
@@ -837,11 +864,27 @@ constexpr int kLeaf = 64;
 // Cholesky-QR pass over [Q_- Q_+], and V_sub <- V_sub [Q_- Q_+].  On success *rminus is
 // the size of the lower part (eigenvalues below sigma), which occupies the first
 // columns.
-int eig_split(hipStream_t s, char* base, EigBuffers& e, int m, int o, int n, const ps_opts& o_,
-              double* pin, ps_info& inf, int* rminus) {
+// Scratch of one recursion worker: the subproblem layout at `base` and the column
+// block buffers (vs, t: mp x pad(n); zbd: pad(n)^2), host staging and stream.
+struct SplitCtx {
+  hipStream_t s;
+  char* base;
+  double *vs, *t, *zbd, *dscratch;
+  int* perm;
+  double* pin;
+};
+
+int eig_split(const SplitCtx& c, const EigBuffers& gl, int m, int o, int n, const ps_opts& o_,
+              ps_info& inf, int* rminus) {
+  hipStream_t s = c.s;
+  double* pin = c.pin;
+  struct {
+    double *vacc, *hs, *vs, *t, *zbd, *dscratch;
+    int* perm;
+  } e{gl.vacc, gl.hs, c.vs, c.t, c.zbd, c.dscratch, c.perm};
   const int mp = pad_to(m);
   Arena sa;
-  sa.base = base;
+  sa.base = c.base;
   sa.dry = false;
   Buffers b;
   carve(sa, b, n, 8, 2);
@@ -1019,10 +1062,14 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
   copy_pad(s, e.qf, 2 * m, m, m, e.qt, mp, mp, mp);
   copy_pad(s, e.qf + m, 2 * m, m, m, e.qb, mp, mp, mp);
   copy_pad(s, e.hraw, m, m, m, e.hs, mp, mp, mp);
-  // ---- Alg. 2 on H_+: splits down to leaves of at most kLeaf
+  // ---- Alg. 2 on H_+: splits down to leaves of at most kLeaf.  Blocks wider than the
+  // worker cap are split here; the subtrees below it are independent and go, largest
+  // first, to kEigWorkers host threads with their own streams and scratch.
   fill_zero(s, e.vacc, S);
   shift_diag(s, e.vacc, mp, m, 1.0);
-  std::vector<std::pair<int, int>> stack{{0, m}}, leaves;
+  SplitCtx main_ctx{s, base, e.vs, e.t, e.zbd, e.dscratch, e.perm, pin};
+  const int cap = eig_worker_cap(m);
+  std::vector<std::pair<int, int>> stack{{0, m}}, leaves, subtrees;
   while (!stack.empty()) {
     const auto [o0, n0] = stack.back();
     stack.pop_back();
@@ -1030,8 +1077,12 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
       leaves.push_back({o0, n0});
       continue;
     }
+    if (n0 <= cap) {
+      subtrees.push_back({o0, n0});
+      continue;
+    }
     int rm = 0;
-    st = eig_split(s, base, e, m, o0, n0, o, pin, inf, &rm);
+    st = eig_split(main_ctx, e, m, o0, n0, o, inf, &rm);
     if (st != PS_OK) {
       inf.status = st;
       inf.failed_step = 5;
@@ -1039,8 +1090,107 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
       return st;
     }
     inf.eig_splits += 1;
-    stack.push_back({o0 + rm, n0 - rm});   // upper part, processed after the lower one
+    stack.push_back({o0 + rm, n0 - rm});
     stack.push_back({o0, rm});
+  }
+  if (!subtrees.empty()) {
+    PS_HIP(hipStreamSynchronize(s));   // the workers' streams start from the current V
+    const int nw = kEigWorkers;
+    while ((int)h->workers.size() < nw) {
+      hipStream_t ws;
+      PS_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+      ps_handle w = nullptr;
+      if (ps_create(&w, ws) != PS_OK) {
+        (void)hipStreamDestroy(ws);
+        return PS_HIP_ERROR;
+      }
+      w->owns_stream = true;
+      h->workers.push_back(w);
+    }
+    std::vector<SplitCtx> ctx(nw);
+    for (int k = 0; k < nw; ++k) {
+      ctx[k].s = h->workers[k]->stream;
+      ctx[k].pin = h->workers[k]->pinned;
+      carve_eig_worker(ea, m, &ctx[k].base, &ctx[k].vs, &ctx[k].t, &ctx[k].zbd,
+                       &ctx[k].dscratch, &ctx[k].perm);
+    }
+    // shared pool: a worker takes the widest pending block and returns its two halves
+    std::mutex mu;
+    std::condition_variable cv;
+    int busy = 0;
+    bool failed = false;
+    std::vector<std::vector<std::pair<int, int>>> wleaves(nw);
+    std::vector<ps_info> winf(nw);
+    std::vector<int> wst(nw, PS_OK);
+    auto work = [&](int k) {
+      if (hipSetDevice(h->device) != hipSuccess) {
+        std::lock_guard<std::mutex> g(mu);
+        wst[k] = PS_HIP_ERROR;
+        failed = true;
+        cv.notify_all();
+        return;
+      }
+      for (;;) {
+        std::pair<int, int> node;
+        {
+          std::unique_lock<std::mutex> g(mu);
+          cv.wait(g, [&] { return failed || !subtrees.empty() || busy == 0; });
+          if (failed || subtrees.empty()) return;
+          auto it = std::max_element(subtrees.begin(), subtrees.end(),
+                                     [](const std::pair<int, int>& x,
+                                        const std::pair<int, int>& y) {
+                                       return x.second < y.second;
+                                     });
+          node = *it;
+          subtrees.erase(it);
+          ++busy;
+        }
+        int rm = 0, r1 = PS_HIP_ERROR;
+        if (node.second <= kLeaf) {
+          r1 = PS_OK;
+        } else {
+          try {
+            r1 = eig_split(ctx[k], e, m, node.first, node.second, o, winf[k], &rm);
+          } catch (...) {
+            r1 = PS_HIP_ERROR;
+          }
+        }
+        std::lock_guard<std::mutex> g(mu);
+        --busy;
+        if (r1 != PS_OK) {
+          wst[k] = r1;
+          failed = true;
+        } else if (node.second <= kLeaf) {
+          wleaves[k].push_back(node);
+        } else {
+          winf[k].eig_splits += 1;
+          for (const auto& c : {std::make_pair(node.first, rm),
+                                std::make_pair(node.first + rm, node.second - rm)}) {
+            if (c.second <= kLeaf)
+              wleaves[k].push_back(c);
+            else
+              subtrees.push_back(c);
+          }
+        }
+        cv.notify_all();
+      }
+    };
+    std::vector<std::thread> threads;
+    for (int k = 1; k < nw; ++k) threads.emplace_back(work, k);
+    work(0);
+    for (auto& t : threads) t.join();
+    for (int k = 0; k < nw; ++k) {
+      inf.eig_splits += winf[k].eig_splits;
+      inf.eig_steps += winf[k].eig_steps;
+      inf.eig_restarts += winf[k].eig_restarts;
+      leaves.insert(leaves.end(), wleaves[k].begin(), wleaves[k].end());
+      if (wst[k] != PS_OK) {
+        inf.status = wst[k];
+        inf.failed_step = 5;
+        if (info) *info = inf;
+        return wst[k];
+      }
+    }
   }
   // ---- leaves: B = V^T H_+ V is block diagonal up to rounding; Jacobi on its blocks
   {
