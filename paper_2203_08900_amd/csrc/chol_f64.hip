@@ -9,6 +9,7 @@
 // blocks by recursive doubling, one pair of GEMM launches per level.  The batch index
 // runs over independent matrices (the r shifted Gram matrices of a Zolotarev step, or
 // A+B and A-B), so every launch covers all of them at once.
+#include "chol_block.h"
 #include "ps_internal.h"
 
 namespace ps {
@@ -18,221 +19,20 @@ constexpr int NB = kNb;
 constexpr int NTD = 256;
 }
 
-// Factor and invert one 64 x 64 diagonal block per workgroup.  Thread (bi, bj) of a
-// 16 x 16 grid owns the 4 x 4 register block rows 4bi.., columns 4bj.. (blocks with
-// bi <= bj carry data).  Factorization, blocked by 4 pivots (kb = 0..15):
-//   1. thread (kb, kb) factors its block D = R_d^T R_d and inverts R_d, in registers;
-//   2. threads (kb, bj > kb) form the panel R(kb, bj) = R_d^{-T} U(kb, bj);
-//   3. every thread with kb < bi <= bj applies U(bi, bj) -= R(kb, bi)^T R(kb, bj).
-// The inverse W = R^{-1} is built bottom-up by block rows: W(lb, :) = R_d(lb)^{-1} B(lb, :)
-// followed by B(bi, :) -= R(bi, lb) W(lb, :) for bi < lb, with B initialized to I.
-// Two barriers per 4 pivots in the factorization, one per 4 rows in the inverse.
-namespace {
-// 1/sqrt(x) and 1/x from the hardware approximations, each refined by two Newton
-// steps (y <- y (3 - x y^2)/2 and y <- y (2 - x y)), which brings the approximations
-// to full double precision; x > 0 is checked by the caller.
-__device__ inline double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-__device__ inline double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
-  y = fma(y, fma(-x, y, 1.0), y);
-  return y;
-}
-
-template <class T>
-__device__ inline void chol4(T d[4][4], T w[4][4], bool& bad) {
-  // upper Cholesky of the 4 x 4 block d (upper triangle used) and w = R_d^{-1}
-  T rinv[4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const T piv = d[p][p];
-    if (!(piv > T(0))) bad = true;
-    const T ri = piv > T(0) ? (T)rsqrt_nr((double)piv) : T(0);
-    rinv[p] = ri;
-    d[p][p] = piv * ri;
-#pragma unroll
-    for (int y = p + 1; y < 4; ++y) d[p][y] *= ri;
-#pragma unroll
-    for (int x = p + 1; x < 4; ++x)
-#pragma unroll
-      for (int y = x; y < 4; ++y) d[x][y] -= d[p][x] * d[p][y];
-  }
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < x; ++y) d[x][y] = T(0);
-  // w = R_d^{-1}: columns by back substitution with the reciprocal diagonal
-#pragma unroll
-  for (int y = 0; y < 4; ++y) {
-#pragma unroll
-    for (int x = 3; x >= 0; --x) {
-      T acc = (x == y) ? T(1) : T(0);
-#pragma unroll
-      for (int q = x + 1; q < 4; ++q) acc -= d[x][q] * w[q][y];
-      w[x][y] = (x <= y) ? acc * rinv[x] : T(0);
-    }
-  }
-}
-}  // namespace
-
+// Factor and invert one 64 x 64 diagonal block per workgroup.
 template <class T>
 __global__ __launch_bounds__(NTD) void potrf_diag_kernel(T* z, long long sz, T* w, long long sw,
                                                          int ld, int k0, int* info) {
-  __shared__ T panel[4][NB];        // R(kb, :) of the current block row
-  __shared__ T wd[NB / 4][4][4];    // R_d^{-1} of every diagonal block
-  __shared__ T rfull[NB][NB + 1];   // R after the factorization
-  __shared__ T wrow[2][4][NB];      // published block row of W
+  __shared__ T lds[blk::kLdsElems];
   const int b = blockIdx.x;
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
-  const int tid = threadIdx.x;
-  const int bi = tid & 15, bj = tid >> 4;
-  const int r0 = 4 * bi, c0 = 4 * bj;
-  const bool active = bi <= bj;
-  T v[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = r0 + x, j = c0 + y;
-      v[x][y] = (active && i <= j) ? Z[i + (long long)j * ld] : T(0);
-    }
-  bool bad = false;
-  for (int kb = 0; kb < NB / 4; ++kb) {
-    // 1. diagonal block
-    if (bi == kb && bj == kb) {
-      T wl[4][4];
-      chol4(v, wl, bad);
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) wd[kb][x][y] = wl[x][y];
-    }
-    __syncthreads();
-    // 2. panel blocks of block row kb (the panel buffer is free: every reader of the
-    // previous one has passed the barrier above)
-    if (bi == kb && bj == kb) {
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) panel[x][c0 + y] = v[x][y];
-    }
-    if (bi == kb && bj > kb) {
-      T r[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          T acc = T(0);
-#pragma unroll
-          for (int p = 0; p <= x; ++p) acc += wd[kb][p][x] * v[p][y];
-          r[x][y] = acc;
-        }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          v[x][y] = r[x][y];
-          panel[x][c0 + y] = r[x][y];
-        }
-    }
-    __syncthreads();
-    // 3. trailing update
-    if (active && bi > kb) {
-      T ra[4][4], rb[4][4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          ra[p][y] = panel[p][r0 + y];
-          rb[p][y] = panel[p][c0 + y];
-        }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          T acc = v[x][y];
-#pragma unroll
-          for (int p = 0; p < 4; ++p) acc -= ra[p][x] * rb[p][y];
-          v[x][y] = acc;
-        }
-    }
-    // the next step's diagonal thread works in its own registers and on wd[kb + 1];
-    // the panel buffer is rewritten only after the next step's first barrier
+  for (int e = threadIdx.x; e < NB * NB; e += NTD) {
+    const int i = e % NB, j = e / NB;
+    if (i <= j) lds[blk::kStage + i * blk::kLdS + j] = Z[i + (long long)j * ld];
   }
-  if (bad) atomicOr(info, 1 << (b < 30 ? b : 30));
-  // R out (zero below the diagonal) and into LDS
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = r0 + x, j = c0 + y;
-      const T rv = (active && i <= j) ? v[x][y] : T(0);
-      v[x][y] = rv;
-      rfull[i][j] = rv;
-      Z[i + (long long)j * ld] = rv;
-    }
-  // W: B = I, bottom-up block rows
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) v[x][y] = (r0 + x == c0 + y) ? T(1) : T(0);
   __syncthreads();
-  for (int lb = NB / 4 - 1; lb >= 0; --lb) {
-    const int buf = lb & 1;
-    if (bi == lb && bj >= lb) {
-      T t[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          T acc = T(0);
-#pragma unroll
-          for (int p = x; p < 4; ++p) acc += wd[lb][x][p] * v[p][y];
-          t[x][y] = acc;
-        }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          v[x][y] = t[x][y];
-          wrow[buf][x][c0 + y] = t[x][y];
-        }
-    }
-    __syncthreads();
-    if (bi < lb && bj >= lb) {
-      T rc[4][4], wr[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) rc[x][p] = rfull[r0 + x][4 * lb + p];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) wr[p][y] = wrow[buf][p][c0 + y];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          T acc = v[x][y];
-#pragma unroll
-          for (int p = 0; p < 4; ++p) acc -= rc[x][p] * wr[p][y];
-          v[x][y] = acc;
-        }
-    }
-  }
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = r0 + x, j = c0 + y;
-      W[i + (long long)j * ld] = (active && i <= j) ? v[x][y] : T(0);
-    }
+  blk::factor_invert_block(lds, Z, W, ld, info, b < 30 ? b : 30);
 }
 
 inline void gemm_t(hipStream_t s, const GemmProblem* p, int n) { gemm_f64(s, p, n); }

@@ -86,9 +86,9 @@ struct GemmLds {
 
 // One output tile of problem P (logical tile index bid within the launch).
 template <class T, int BM, int BN, int WM, int WN, int TA, int TB>
-__device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
-                                          T (*As)[GemmLds<BM, BN>::ASZ],
-                                          T (*Bs)[GemmLds<BM, BN>::BSZ]) {
+__device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* smem) {
+  auto As = reinterpret_cast<T(*)[GemmLds<BM, BN>::ASZ]>(smem);
+  auto Bs = reinterpret_cast<T(*)[GemmLds<BM, BN>::BSZ]>(smem + 2 * GemmLds<BM, BN>::ASZ);
   constexpr int NT = WM * WN * 64;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
   constexpr int LDKM = GemmLds<BM, BN>::LDKM;
@@ -96,15 +96,60 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
   constexpr int APT = BM * BK / NT;
   constexpr int BPT = BN * BK / NT;
   const int local = bid - P.tile_begin;
-  const int z = local / P.tiles_per_batch;
-  const int tz = local - z * P.tiles_per_batch;
+  // Triangular operands make the K extent differ from tile to tile.  Such problems (with
+  // a full output) are launched without the XCD remap (dispatch is round-robin over the
+  // XCDs) and enumerate their tiles longest first, batch entries interleaved, so the
+  // long tiles start in the first wave of workgroups and the short ones fill in behind
+  // them.  Triangular outputs keep the remap: their columns-ascending order already puts
+  // the long tiles of the usual lower-K-bound operands first.
+  const int tri_ops = (P.flags & (kOutUpper | kOutLower))
+                          ? 0
+                          : P.flags & (kAUpper | kALower | kBUpper | kBLower);
+  const int nbat = P.nb1 * P.nb2;
+  int z, tz;
+  if (tri_ops) {
+    z = local % nbat;
+    tz = local / nbat;
+  } else {
+    z = local / P.tiles_per_batch;
+    tz = local - z * P.tiles_per_batch;
+  }
   const int ks = tz / P.tiles;          // split index
   const int t = tz - ks * P.tiles;
   int I, J;
   if (P.flags & kOutUpper) {
-    tri_index(t, J, I);
+    tri_index(t, J, I);                 // columns J ascending
   } else if (P.flags & kOutLower) {
     tri_index(t, I, J);
+  } else if (tri_ops == kAUpper) {      // K from i0: rows ascending
+    I = t / P.tn;
+    J = t - I * P.tn;
+  } else if (tri_ops == kALower) {      // K to i0 + BM: rows descending
+    I = t / P.tn;
+    J = t - I * P.tn;
+    I = P.tm - 1 - I;
+  } else if (tri_ops == kBUpper) {      // K to j0 + BN: columns descending
+    J = t / P.tm;
+    I = t - J * P.tm;
+    J = P.tn - 1 - J;
+  } else if ((tri_ops == (kAUpper | kBLower) || tri_ops == (kALower | kBUpper)) && P.tm == P.tn) {
+    // K from max(i0, j0) (resp. to min(i0, j0) + 128): shells of equal max(I, J),
+    // innermost first (resp. mirrored through the far corner)
+    int sh = (int)sqrtf((float)t);
+    while (sh * sh > t) --sh;
+    while ((sh + 1) * (sh + 1) <= t) ++sh;
+    const int r = t - sh * sh;
+    if (r <= sh) {
+      I = sh;
+      J = r;
+    } else {
+      I = r - sh - 1;
+      J = sh;
+    }
+    if (tri_ops == (kALower | kBUpper)) {
+      I = P.tm - 1 - I;
+      J = P.tn - 1 - J;
+    }
   } else {
     I = t % P.tm;
     J = t / P.tm;
@@ -146,20 +191,23 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
     for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
   T ra[APT], rb[BPT];
+  double rsc = 1.0;   // segment scale of the A values in flight
 
+  // Global loads of step kt into registers; nothing consumes them until store(), so
+  // their latency overlaps the matrix-core work of the current step.
   auto load = [&](int kt) {
     const int s = kt / per;
     const int k0 = s * segK + kb + (kt - s * per) * BK;
-    const double sc = P.kseg > 0 ? P.kscale[s] : 1.0;
+    rsc = P.kseg > 0 ? P.kscale[s] : 1.0;
 #pragma unroll
     for (int p = 0; p < APT; ++p) {
       const int idx = tid + p * NT;
       if (!tA) {
         const int i = idx % BM, k = idx / BM;
-        ra[p] = (T)(A[(i0 + i) + (long long)(k0 + k) * lda] * sc);
+        ra[p] = A[(i0 + i) + (long long)(k0 + k) * lda];
       } else {
         const int k = idx % BK, i = idx / BK;
-        ra[p] = (T)(A[(k0 + k) + (long long)(i0 + i) * lda] * sc);
+        ra[p] = A[(k0 + k) + (long long)(i0 + i) * lda];
       }
     }
 #pragma unroll
@@ -178,12 +226,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
 #pragma unroll
     for (int p = 0; p < APT; ++p) {
       const int idx = tid + p * NT;
+      const T v = P.kseg > 0 ? (T)((double)ra[p] * rsc) : ra[p];
       if (!tA) {
         const int i = idx % BM, k = idx / BM;
-        As[buf][k * LDKM + i] = ra[p];
+        As[buf][k * LDKM + i] = v;
       } else {
         const int k = idx % BK, i = idx / BK;
-        As[buf][i * LDIK + k] = ra[p];
+        As[buf][i * LDIK + k] = v;
       }
     }
 #pragma unroll
@@ -249,8 +298,25 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
     return;
   }
   const long long ldc = P.ldc, ldd = P.ldd;
+  // C may be D itself (in-place updates), so the compiler cannot move a C load above an
+  // earlier D store: loaded one by one, every element would wait a full memory latency.
+  // The C values of fragment row a + 1 are therefore loaded before the stores of row a
+  // (they are other elements, so the order is safe whether or not C aliases D).
+  T cur[FN][4], nxt[FN][4];
+  auto load_c = [&](int a, T (*dst)[4]) {
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
+        const int j = j0 + wn * FN * 16 + b * 16 + li;
+        dst[b][v] = C[i + j * ldc];
+      }
+  };
+  if (beta != 0.0) load_c(0, cur);
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    if (beta != 0.0 && a + 1 < FM) load_c(a + 1, nxt);
 #pragma unroll
     for (int b = 0; b < FN; ++b)
 #pragma unroll
@@ -260,18 +326,22 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid,
         if ((flags & kOutUpper) && i > j) continue;
         if ((flags & kOutLower) && i < j) continue;
         double val = alpha * acc[a][b][v];
-        if (beta != 0.0) val += beta * C[i + j * ldc];
+        if (beta != 0.0) val += beta * (double)cur[b][v];
         D[i + j * ldd] = (T)val;
         if ((flags & kMirror) && i != j) D[j + i * ldd] = (T)val;
       }
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cur[b][v] = nxt[b][v];
+  }
 }
 
 // The operand transposes are per problem, so one launch covers a group of problems
 // with different transposes (each workgroup branches once, uniformly).
 template <class T, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g) {
-  __shared__ T As[2][GemmLds<BM, BN>::ASZ];
-  __shared__ T Bs[2][GemmLds<BM, BN>::BSZ];
+  __shared__ T smem[2 * GemmLds<BM, BN>::ASZ + 2 * GemmLds<BM, BN>::BSZ];
   int bid = blockIdx.x;
   if (g.remap) {
     // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
@@ -284,13 +354,13 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g)
   const GemmProblemT<T>& P = g.p[pi];
   const int v = P.tA * 2 + P.tB;
   if (v == 0)
-    gemm_tile<T, BM, BN, WM, WN, 0, 0>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 0, 0>(P, bid, smem);
   else if (v == 1)
-    gemm_tile<T, BM, BN, WM, WN, 0, 1>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 0, 1>(P, bid, smem);
   else if (v == 2)
-    gemm_tile<T, BM, BN, WM, WN, 1, 0>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 1, 0>(P, bid, smem);
   else
-    gemm_tile<T, BM, BN, WM, WN, 1, 1>(P, bid, As, Bs);
+    gemm_tile<T, BM, BN, WM, WN, 1, 1>(P, bid, smem);
 }
 
 // D = sum_s partial_s + beta C with the triangle / mirror conventions of the GEMM
@@ -374,7 +444,11 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
   }
   if (total == 0) return;
   g.total = total;
-  g.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
+  bool tri_ops = false;
+  for (int q = 0; q < g.count; ++q)
+    tri_ops = tri_ops || ((g.p[q].flags & (kAUpper | kALower | kBUpper | kBLower)) &&
+                          !(g.p[q].flags & (kOutUpper | kOutLower)));
+  g.remap = (!tri_ops && total % 8 == 0 && total >= 64) ? 1 : 0;
   const bool rec = BM == 128 && std::is_same<T, double>::value && g_rec && g_rec->n < g_rec->cap;
   if (rec) PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n], s));
   hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN>), dim3(total), dim3(WM * WN * 64),
@@ -480,7 +554,7 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
                 p.ksplit * p.nb1 * p.nb2;
   }
   if (!live) return;
-  if (big && tiles128 >= 128)
+  if (big && tiles128 >= 256)
     launch_group<T, 128, 128, 2, 4>(s, probs, count);
   else
     launch_group<T, 64, 64, 2, 2>(s, probs, count);
