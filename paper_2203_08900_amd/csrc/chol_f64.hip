@@ -27,9 +27,18 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(T* z, long long sz, T* 
   const int b = blockIdx.x;
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
-  for (int e = threadIdx.x; e < NB * NB; e += NTD) {
-    const int i = e % NB, j = e / NB;
-    if (i <= j) lds[blk::kStage + i * blk::kLdS + j] = Z[i + (long long)j * ld];
+  // all loads in flight at once, then into LDS (the lower triangle is staged too and
+  // ignored)
+  T val[NB * NB / NTD];
+#pragma unroll
+  for (int q = 0; q < NB * NB / NTD; ++q) {
+    const int e = threadIdx.x + q * NTD;
+    val[q] = Z[e % NB + (long long)(e / NB) * ld];
+  }
+#pragma unroll
+  for (int q = 0; q < NB * NB / NTD; ++q) {
+    const int e = threadIdx.x + q * NTD;
+    lds[blk::kStage + (e % NB) * blk::kLdS + e / NB] = val[q];
   }
   __syncthreads();
   blk::factor_invert_block(lds, Z, W, ld, info, b < 30 ? b : 30);

@@ -7,8 +7,8 @@
 // and 64 x 64 with 4 waves of 32 x 32 for small ones.  A group of up to four
 // independent problems (any operand transposes) shares one launch, so that problems
 // whose tile counts alone would leave compute units idle fill the machine together.
-// K advances in steps of 16 through two LDS buffers (one barrier per step); the next
-// step's global loads are issued before the MFMAs of the current step.
+// K advances in steps of 16 through two LDS buffers (one barrier per step); the global
+// loads run two steps ahead of the MFMAs, through two register slots.
 //
 // LDS layouts per operand keep global loads coalesced along the contiguous
 // dimension and fragment reads on distinct banks:
@@ -190,12 +190,14 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-  T ra[APT], rb[BPT];
-  double rsc = 1.0;   // segment scale of the A values in flight
+  // Two register slots for the global loads of the next two K steps: the loads of step
+  // kt + 2 are issued before the matrix-core work of step kt and land in LDS only after
+  // that of step kt + 1, so two steps of compute cover their latency (a single step of
+  // a 64 x 64 tile is shorter than a trip to memory).
+  T ra0[APT], rb0[BPT], ra1[APT], rb1[BPT];
+  double rsc0 = 1.0, rsc1 = 1.0;   // segment scale of the A values in each slot
 
-  // Global loads of step kt into registers; nothing consumes them until store(), so
-  // their latency overlaps the matrix-core work of the current step.
-  auto load = [&](int kt) {
+  auto load = [&](int kt, T* ra, T* rb, double& rsc) {
     const int s = kt / per;
     const int k0 = s * segK + kb + (kt - s * per) * BK;
     rsc = P.kseg > 0 ? P.kscale[s] : 1.0;
@@ -222,7 +224,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const T* ra, const T* rb, double rsc) {
 #pragma unroll
     for (int p = 0; p < APT; ++p) {
       const int idx = tid + p * NT;
@@ -247,35 +249,46 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
       }
     }
   };
-
-  if (kt_end > kt_begin) {
-    load(kt_begin);
-    store(0);
-    __syncthreads();
-    for (int kt = kt_begin; kt < kt_end; ++kt) {
-      const int buf = (kt - kt_begin) & 1;
-      if (kt + 1 < kt_end) load(kt + 1);
+  auto compute = [&](int buf) {
 #pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        const int k = kk * 4 + lk;
-        T av[FM], bv[FN];
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int k = kk * 4 + lk;
+      T av[FM], bv[FN];
 #pragma unroll
-        for (int a = 0; a < FM; ++a) {
-          const int i = wm * FM * 16 + a * 16 + li;
-          av[a] = !tA ? As[buf][k * LDKM + i] : As[buf][i * LDIK + k];
-        }
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          const int j = wn * FN * 16 + b * 16 + li;
-          bv[b] = !tB ? Bs[buf][j * LDIK + k] : Bs[buf][k * LDKN + j];
-        }
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-          for (int b = 0; b < FN; ++b)
-            acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+      for (int a = 0; a < FM; ++a) {
+        const int i = wm * FM * 16 + a * 16 + li;
+        av[a] = !tA ? As[buf][k * LDKM + i] : As[buf][i * LDIK + k];
       }
-      if (kt + 1 < kt_end) store(buf ^ 1);
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int j = wn * FN * 16 + b * 16 + li;
+        bv[b] = !tB ? Bs[buf][j * LDIK + k] : Bs[buf][k * LDKN + j];
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+    }
+  };
+
+  // Steps alternate between (LDS buffer 0, slot 0 refilled) and (buffer 1, slot 1): the
+  // store after a step's compute writes the other buffer, whose readers finished before
+  // the previous barrier, from the slot loaded one step earlier.
+  const int nkt = kt_end - kt_begin;
+  if (nkt > 0) {
+    load(kt_begin, ra0, rb0, rsc0);
+    if (nkt > 1) load(kt_begin + 1, ra1, rb1, rsc1);
+    store(0, ra0, rb0, rsc0);
+    __syncthreads();
+    for (int it = 0; it < nkt; it += 2) {
+      if (it + 2 < nkt) load(kt_begin + it + 2, ra0, rb0, rsc0);
+      compute(0);
+      if (it + 1 < nkt) store(1, ra1, rb1, rsc1);
+      __syncthreads();
+      if (it + 1 >= nkt) break;
+      if (it + 3 < nkt) load(kt_begin + it + 3, ra1, rb1, rsc1);
+      compute(1);
+      if (it + 2 < nkt) store(0, ra0, rb0, rsc0);
       __syncthreads();
     }
   }
