@@ -69,6 +69,17 @@ __device__ inline typename BlkMfma<T>::acc_t tile_mm(const T* A, int lda, const 
   return acc;
 }
 
+// Same with A given transposed: A(i, k) = At[k * ldat + i].
+template <class T>
+__device__ inline typename BlkMfma<T>::acc_t tile_mm_ta(const T* At, int ldat, const T* B, int ldb,
+                                                        int K) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  typename BlkMfma<T>::acc_t acc = {0, 0, 0, 0};
+  for (int k = 0; k < K; k += 4)
+    acc = BlkMfma<T>::step(At[(k + lk) * ldat + li], B[(k + lk) * ldb + li], acc);
+  return acc;
+}
+
 // Store -acc of tile_mm into a row-major LDS array.
 template <class T>
 __device__ inline void tile_store_neg(const typename BlkMfma<T>::acc_t& acc, T* D, int ldd) {
@@ -141,10 +152,14 @@ __device__ inline void chol4(T d[4][4], T w[4][4], bool& bad) {
 
 // The block's upper triangle is staged in lds[kStage + i * kLdS + j] (entry (i, j),
 // i <= j) and a barrier has passed since.  Stores R (zero below the diagonal) at Z and
-// R^{-1} at W (leading dimension ld for both) and sets bit `bit` of *info on a
-// non-positive pivot.  Every thread of the workgroup must call this (at least 256).
+// R^{-1} at W (leading dimension ld for both; only with `store`) and sets bit `bit` of
+// *info on a non-positive pivot.  R stays in the staging area and R^{-1} in
+// lds[kWl + i * kLdS + j]; after the final barrier inside, only the W stores remain, so
+// the caller may reuse the staging area at once.  Every thread of the workgroup must
+// call this (at least 256).
 template <class T>
-__device__ void factor_invert_block(T* lds, T* Z, T* W, long long ld, int* info, int bit) {
+__device__ void factor_invert_block(T* lds, T* Z, T* W, long long ld, int* info, int bit,
+                                    bool store) {
   auto panels = reinterpret_cast<T(*)[4][kB]>(lds + kPanel);
   auto wd = reinterpret_cast<T(*)[4][4]>(lds + kWd);
   T* stage = lds + kStage;
@@ -244,7 +259,7 @@ __device__ void factor_invert_block(T* lds, T* Z, T* W, long long ld, int* info,
         const T rv = (active && i <= j) ? v[x][y] : T(0);
         v[x][y] = rv;
         stage[i * kLdS + j] = rv;
-        Z[i + (long long)j * ld] = rv;
+        if (store) Z[i + (long long)j * ld] = rv;
       }
   }
   // ---- W = R^{-1} by recursive doubling (R now in stage, zero below the diagonal)
@@ -300,9 +315,11 @@ __device__ void factor_invert_block(T* lds, T* Z, T* W, long long ld, int* info,
     tile_store_neg(tile_mm(Wl + 16 * ti * kLdS, kLdS, tmp + 16 * tj, kLdT, 32),
                    Wl + 16 * ti * kLdS + 32 + 16 * tj, kLdS);
   __syncthreads();
-  for (int e = tid; e < kB * kB; e += blockDim.x) {
-    const int i = e % kB, j = e / kB;
-    W[i + (long long)j * ld] = Wl[i * kLdS + j];
+  if (store) {
+    for (int e = tid; e < kB * kB; e += blockDim.x) {
+      const int i = e % kB, j = e / kB;
+      W[i + (long long)j * ld] = Wl[i * kLdS + j];
+    }
   }
 }
 

@@ -2,9 +2,10 @@
 // or FP32 (one template).
 //
 // Blocked right-looking algorithm over 64 x 64 diagonal blocks.  Per block step k:
-//   1. one workgroup per matrix factors the diagonal block and inverts it;
-//   2. the panel R(k, k+1:) = R_kk^{-T} Z(k, k+1:) (GEMM with the inverted block);
-//   3. the symmetric trailing update Z(k+1:, k+1:) -= R(k, k+1:)^T R(k, k+1:).
+//   1. one launch factors and inverts the diagonal block and forms the panel
+//      R(k, k+1:) = R_kk^{-T} Z(k, k+1:) (each panel tile's workgroup factors the block
+//      itself);
+//   2. the symmetric trailing update Z(k+1:, k+1:) -= R(k, k+1:)^T R(k, k+1:).
 // The full inverse factor W = R^{-1} is then assembled from the inverted diagonal
 // blocks by recursive doubling, one pair of GEMM launches per level.  The batch index
 // runs over independent matrices (the r shifted Gram matrices of a Zolotarev step, or
@@ -19,29 +20,74 @@ constexpr int NB = kNb;
 constexpr int NTD = 256;
 }
 
-// Factor and invert one 64 x 64 diagonal block per workgroup.
+// One step of the blocked factorization, diagonal block and panel together.  Every
+// workgroup (ntiles per matrix) factors and inverts the 64 x 64 diagonal block at k0 in
+// LDS (the same arithmetic in each, so all agree; tile 0 stores R_kk^{-1} and R_kk) and
+// then forms its 64-column tile of the panel R(k, k+1:) = R_kk^{-T} Z(k, k+1:) on the
+// matrix cores, in place.  The redundant factorizations run side by side on otherwise
+// idle compute units; what they save is a dependent launch per step.
 template <class T>
 __global__ __launch_bounds__(NTD) void potrf_diag_kernel(T* z, long long sz, T* w, long long sw,
-                                                         int ld, int k0, int* info) {
+                                                         int ld, int k0, int rest, int ntiles,
+                                                         int* info) {
   __shared__ T lds[blk::kLdsElems];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x / ntiles, t = blockIdx.x - b * ntiles;
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
+  constexpr int Q = NB * NB / NTD;
   // all loads in flight at once, then into LDS (the lower triangle is staged too and
   // ignored)
-  T val[NB * NB / NTD];
+  T val[Q];
 #pragma unroll
-  for (int q = 0; q < NB * NB / NTD; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int e = threadIdx.x + q * NTD;
     val[q] = Z[e % NB + (long long)(e / NB) * ld];
   }
 #pragma unroll
-  for (int q = 0; q < NB * NB / NTD; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int e = threadIdx.x + q * NTD;
     lds[blk::kStage + (e % NB) * blk::kLdS + e / NB] = val[q];
   }
   __syncthreads();
-  blk::factor_invert_block(lds, Z, W, ld, info, b < 30 ? b : 30);
+  // The other workgroups of this matrix may still be reading the diagonal block, so
+  // tile 0 leaves it untouched: R_kk goes to the (unused, zero) block below W_kk and
+  // moves into place in the next step's launch, which also clears that block; the last
+  // step (a single workgroup) writes it directly.
+  if (t == 0 && k0 > 0) {
+    T* src = W - (long long)NB * ld;              // block (k, k-1) of W
+    T* dst = Z - NB - (long long)NB * ld;         // block (k-1, k-1) of Z
+    for (int e = threadIdx.x; e < NB * NB; e += NTD) {
+      const long long o = e % NB + (long long)(e / NB) * ld;
+      dst[o] = src[o];
+      src[o] = T(0);
+    }
+  }
+  blk::factor_invert_block(lds, rest > 0 ? W + NB : Z, W, ld, info, b < 30 ? b : 30, t == 0);
+  if (rest <= 0) return;
+  // panel tile t: rows k0.., columns k0 + 64 + 64t.., staged where R was
+  T* Zt = Z + (long long)(NB + NB * t) * ld;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + q * NTD;
+    val[q] = Zt[e % NB + (long long)(e / NB) * ld];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + q * NTD;
+    lds[blk::kStage + (e % NB) * blk::kLdS + e / NB] = val[q];
+  }
+  __syncthreads();
+  // wave w: rows 16w.. of the tile, four 16-column tiles, P = W_kk^T Z_tile
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  const T* Wl = lds + blk::kWl;
+  const T* St = lds + blk::kStage;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const auto acc = blk::tile_mm_ta(Wl + 16 * wave, blk::kLdS, St + 16 * c, blk::kLdS, NB);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      Zt[(16 * wave + blk::BlkMfma<T>::row(lk, v)) + (long long)(16 * c + li) * ld] = acc[v];
+  }
 }
 
 inline void gemm_t(hipStream_t s, const GemmProblem* p, int n) { gemm_f64(s, p, n); }
@@ -53,26 +99,18 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   zero_lower(s, w, mp, sw, batch);  // the diagonal blocks and W12 blocks cover the rest
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
   const int nbk = mp / NB;
-  // ---- blocked right-looking Cholesky; the diagonal kernel also inverts R_kk
+  // ---- blocked right-looking Cholesky: per step one launch for the diagonal block and
+  // its panel, one for the trailing update
   for (int k = 0; k < nbk; ++k) {
     const int k0 = k * NB;
     const int rest = mp - k0 - NB;
-    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(batch), dim3(NTD), 0, s, z, sz, w, sw, mp, k0,
-                       info);
+    const int nt = rest > 0 ? rest / NB : 1;
+    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(batch * nt), dim3(NTD), 0, s, z, sz, w, sw, mp,
+                       k0, rest, nt, info);
     PS_HIP(hipGetLastError());
     if (rest <= 0) break;
-    T* wkk = w + k0 + (long long)k0 * mp;
     T* zr = z + k0 + (long long)(k0 + NB) * mp;
     T* zt = z + (k0 + NB) + (long long)(k0 + NB) * mp;
-    // panel R(k, k+1:) = R_kk^{-T} Z(k, k+1:), in place (each tile reads its own columns)
-    GemmProblemT<T> pp = gemm_problem(NB, rest, NB, wkk, mp, 1, zr, mp, 0, zr, mp, 1.0, 0.0, nullptr,
-                                  0, kALower);
-    pp.nb1 = batch;
-    pp.sA[0] = sw;
-    pp.sB[0] = sz;
-    pp.sC[0] = sz;
-    pp.sD[0] = sz;
-    gemm_t(s, &pp, 1);
     // trailing update Z(k+1:, k+1:) -= R(k, k+1:)^T R(k, k+1:)  (upper triangle)
     GemmProblemT<T> pt = gemm_problem(rest, rest, NB, zr, mp, 1, zr, mp, 0, zt, mp, -1.0, 1.0, zt, mp,
                                   kOutUpper);
