@@ -384,7 +384,7 @@ def main():
                 "frac": achieved / PEAK["f64"],
                 "traffic": traffic_from_profile(os.path.join(
                     ROOT, "paper_2203_08900_amd", "csrc", "gemm_f64.hip")),
-                "kernel": "gemm_mfma_kernel<double,128,128,2,4>",
+                "kernel": "gemm_mfma_kernel<double,128,128,4,4>",
                 "launches_per_step": gm["launches"] / args.steps,
                 "avg_launch_ms": gm["ms"] / gm["launches"],
                 "flops_per_launch": gm["flops"] / gm["launches"]}

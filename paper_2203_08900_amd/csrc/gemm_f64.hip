@@ -3,8 +3,8 @@
 //
 // A workgroup computes a BM x BN tile of D = alpha op(A) op(B) + beta C; its waves
 // own (BM/WM) x (BN/WN) sub-tiles as MFMA 16x16 fragments.  Two shapes: 128 x 128 with
-// 8 waves of 64 x 32 (16 flops per byte loaded, two waves per SIMD) for large problems
-// and 64 x 64 with 4 waves of 32 x 32 for small ones.  A group of up to four
+// 16 waves of 32 x 32 (16 flops per byte loaded, four waves per SIMD) for problems whose
+// tiles fill the chip, and 64 x 64 with 4 waves of 32 x 32 for the others.  A group of up to four
 // independent problems (any operand transposes) shares one launch, so that problems
 // whose tile counts alone would leave compute units idle fill the machine together.
 // K advances in steps of 16 through two LDS buffers (one barrier per step); the global
@@ -271,6 +271,25 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
     }
   };
 
+  // 64 x 64 tiles (short-K trailing updates of the factorizations among them) load their
+  // C values before the K loop, so that trip to memory overlaps the loop instead of
+  // following it; the large tiles keep their registers for occupancy and prefetch C
+  // row by row in the epilogue.
+  constexpr bool kEarlyC = (BM == 64);
+  T cpre[kEarlyC ? FM : 1][FN][4];
+  if (kEarlyC && P.beta != 0.0) {
+#pragma unroll
+    for (int a = 0; a < (kEarlyC ? FM : 1); ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
+          const int j = j0 + wn * FN * 16 + b * 16 + li;
+          cpre[a][b][v] = C[i + j * (long long)P.ldc];
+        }
+  }
+
   // Steps alternate between (LDS buffer 0, slot 0 refilled) and (buffer 1, slot 1): the
   // store after a step's compute writes the other buffer, whose readers finished before
   // the previous barrier, from the slot loaded one step earlier.
@@ -326,10 +345,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
         dst[b][v] = C[i + j * ldc];
       }
   };
-  if (beta != 0.0) load_c(0, cur);
+  if (!kEarlyC && beta != 0.0) load_c(0, cur);
 #pragma unroll
   for (int a = 0; a < FM; ++a) {
-    if (beta != 0.0 && a + 1 < FM) load_c(a + 1, nxt);
+    if (!kEarlyC && beta != 0.0 && a + 1 < FM) load_c(a + 1, nxt);
 #pragma unroll
     for (int b = 0; b < FN; ++b)
 #pragma unroll
@@ -339,7 +358,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
         if ((flags & kOutUpper) && i > j) continue;
         if ((flags & kOutLower) && i < j) continue;
         double val = alpha * acc[a][b][v];
-        if (beta != 0.0) val += beta * (double)cur[b][v];
+        if (beta != 0.0)
+          val += beta * (double)(kEarlyC ? cpre[kEarlyC ? a : 0][b][v] : cur[b][v]);
         D[i + j * ldd] = (T)val;
         if ((flags & kMirror) && i != j) D[j + i * ldd] = (T)val;
       }
@@ -568,7 +588,7 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
   }
   if (!live) return;
   if (big && tiles128 >= 256)
-    launch_group<T, 128, 128, 2, 4>(s, probs, count);
+    launch_group<T, 128, 128, 4, 4>(s, probs, count);
   else
     launch_group<T, 64, 64, 2, 2>(s, probs, count);
 }
