@@ -63,3 +63,34 @@ def test_ill_separated_m8192(ill, precision, tol):
     err = np.max(np.abs(w - exact) / exact)
     print(f"[large] relative eigenvalue error {err:.3e}", flush=True)
     assert err < tol
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cholesky_grid_beyond_one_wave_m2560(precision):
+    """m = 2560 (padded size 2560): a Cholesky step of the eight shifted factorizations
+    launches 8 x 39 panel workgroups, more than the compute units hold at once, so some
+    start after the first has finished its diagonal block.  Regression test for that
+    case (the factor of the diagonal block must not be written where the late
+    workgroups still read their input); the same properties as above, at a size the
+    host checks quickly."""
+    m = 2560
+    a, b, mu = inputs.ill_separated(m, 11, mu_lo=1e-4)
+    A = torch.tensor(a, dtype=torch.float64, device="cuda")
+    B = torch.tensor(b, dtype=torch.float64, device="cuda")
+    print(f"[grid] divide m={m} {precision}", flush=True)
+    Qp, Hp, info = api.divide(A, B, precision=precision, r=8)
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    sig = torch.cat([torch.ones(m, dtype=torch.float64, device="cuda"),
+                     -torch.ones(m, dtype=torch.float64, device="cuda")])
+    G = Qp.T @ (sig[:, None] * Qp)
+    orth = (G - torch.eye(m, dtype=torch.float64, device="cuda")).abs().max().item()
+    print(f"[grid] Sigma-orthonormality {orth:.3e}", flush=True)
+    assert orth < 1e-10
+    exact = np.sqrt(mu)
+    Hs = 0.5 * (Hp + Hp.T)
+    w = np.sort(eigvals_sym(Hs))
+    err = np.max(np.abs(w - exact) / exact)
+    print(f"[grid] relative eigenvalue error {err:.3e}", flush=True)
+    assert err < (1e-11 if precision == "fp64" else 1e-9)
