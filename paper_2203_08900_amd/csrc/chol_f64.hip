@@ -1,16 +1,18 @@
 // Batched Cholesky factorization with the inverse factor, Z = R^T R, W = R^{-1}, in FP64
 // or FP32 (one template).
 //
-// Blocked right-looking algorithm over 64 x 64 diagonal blocks.  Per block step k:
-//   1. one launch factors and inverts the diagonal block and forms the panel
-//      R(k, k+1:) = R_kk^{-T} Z(k, k+1:) (each panel tile's workgroup factors the block
-//      itself);
-//   2. the symmetric trailing update Z(k+1:, k+1:) -= R(k, k+1:)^T R(k, k+1:).
+// Blocked right-looking algorithm over 64 x 64 diagonal blocks with a look-ahead of one
+// block row.  Per block step k:
+//   1. a small GEMM applies panel k to block row k+1;
+//   2. one launch factors and inverts diagonal block k+1 and forms its panel
+//      R(k+1, k+2:) = R^{-T} Z(k+1, k+2:) (each panel tile's workgroup factors the block
+//      itself) while its other workgroups apply panel k to the rows below block row k+1.
 // The full inverse factor W = R^{-1} is then assembled from the inverted diagonal
 // blocks by recursive doubling, one pair of GEMM launches per level.  The batch index
 // runs over independent matrices (the r shifted Gram matrices of a Zolotarev step, or
 // A+B and A-B), so every launch covers all of them at once.
 #include "chol_block.h"
+#include "gemm_tile.h"
 #include "ps_internal.h"
 
 namespace ps {
@@ -27,11 +29,9 @@ constexpr int NTD = 256;
 // matrix cores, in place.  The redundant factorizations run side by side on otherwise
 // idle compute units; what they save is a dependent launch per step.
 template <class T>
-__global__ __launch_bounds__(NTD) void potrf_diag_kernel(T* z, long long sz, T* w, long long sw,
-                                                         int ld, int k0, int rest, int ntiles,
-                                                         int* info) {
-  __shared__ T lds[blk::kLdsElems];
-  const int b = blockIdx.x / ntiles, t = blockIdx.x - b * ntiles;
+__device__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long sw, int ld, int k0,
+                           int rest, int ntiles, int* info) {
+  const int b = bid / ntiles, t = bid - b * ntiles;
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
   constexpr int Q = NB * NB / NTD;
@@ -90,6 +90,23 @@ __global__ __launch_bounds__(NTD) void potrf_diag_kernel(T* z, long long sz, T* 
   }
 }
 
+// One launch of the factorization: workgroups below ndiag run diag_panel for the block
+// at k0; the others are tiles of the trailing update `tp` that the step before k0 still
+// owes to the rows below block row k0 (look-ahead: the row block at k0 was updated
+// first, by a launch of its own, so its diagonal block and panel need not wait for the
+// whole trailing update).  The two roles touch disjoint parts of Z.
+template <class T>
+__global__ __launch_bounds__(NTD) void chol_step_kernel(T* z, long long sz, T* w, long long sw,
+                                                        int ld, int k0, int rest, int ntiles,
+                                                        int* info, GemmProblemT<T> tp, int ndiag) {
+  constexpr int kAB = 2 * GemmLds<64, 64>::ASZ + 2 * GemmLds<64, 64>::BSZ;
+  __shared__ T lds[blk::kLdsElems > kAB ? blk::kLdsElems : kAB];
+  if ((int)blockIdx.x < ndiag)
+    diag_panel(lds, blockIdx.x, z, sz, w, sw, ld, k0, rest, ntiles, info);
+  else
+    gemm_tile<T, 64, 64, 2, 2, 1, 0>(tp, blockIdx.x - ndiag, lds);
+}
+
 inline void gemm_t(hipStream_t s, const GemmProblem* p, int n) { gemm_f64(s, p, n); }
 inline void gemm_t(hipStream_t s, const GemmProblemF* p, int n) { gemm_f32(s, p, n); }
 
@@ -99,27 +116,62 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   zero_lower(s, w, mp, sw, batch);  // the diagonal blocks and W12 blocks cover the rest
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
   const int nbk = mp / NB;
-  // ---- blocked right-looking Cholesky: per step one launch for the diagonal block and
-  // its panel, one for the trailing update
-  for (int k = 0; k < nbk; ++k) {
-    const int k0 = k * NB;
+  // ---- blocked right-looking Cholesky with a look-ahead of one block row:
+  //   C_0 = diagonal block and panel of block row 0;
+  //   for k = 0, 1, ...:  A_k = update of block row k+1 by panel k (one small GEMM);
+  //                       C_{k+1} = diagonal block and panel of block row k+1, together
+  //                       with the update by panel k of the rows below block row k+1.
+  // Per step the chain waits for A_k and C_{k+1}; the bulk of the trailing update runs
+  // beside the next diagonal factorization instead of before it.
+  auto step = [&](int k0, const GemmProblemT<T>* tp) {
     const int rest = mp - k0 - NB;
     const int nt = rest > 0 ? rest / NB : 1;
-    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(batch * nt), dim3(NTD), 0, s, z, sz, w, sw, mp,
-                       k0, rest, nt, info);
+    const int ndiag = batch * nt;
+    GemmProblemT<T> t{};
+    int ntrail = 0;
+    if (tp) {
+      t = *tp;
+      t.tm = t.M / 64;
+      t.tn = t.N / 64;
+      t.tiles = t.tm * (t.tm + 1) / 2;   // upper-triangular output
+      t.tiles_per_batch = t.tiles;
+      t.tile_begin = 0;
+      ntrail = t.tiles * batch;
+    }
+    hipLaunchKernelGGL(chol_step_kernel<T>, dim3(ndiag + ntrail), dim3(NTD), 0, s, z, sz, w, sw,
+                       mp, k0, rest, nt, info, t, ndiag);
     PS_HIP(hipGetLastError());
-    if (rest <= 0) break;
-    T* zr = z + k0 + (long long)(k0 + NB) * mp;
-    T* zt = z + (k0 + NB) + (long long)(k0 + NB) * mp;
-    // trailing update Z(k+1:, k+1:) -= R(k, k+1:)^T R(k, k+1:)  (upper triangle)
-    GemmProblemT<T> pt = gemm_problem(rest, rest, NB, zr, mp, 1, zr, mp, 0, zt, mp, -1.0, 1.0, zt, mp,
-                                  kOutUpper);
-    pt.nb1 = batch;
-    pt.sA[0] = sz;
-    pt.sB[0] = sz;
-    pt.sC[0] = sz;
-    pt.sD[0] = sz;
-    gemm_t(s, &pt, 1);
+  };
+  step(0, nullptr);
+  for (int k = 0; k + 1 < nbk; ++k) {
+    const int k0 = k * NB;
+    const int rest = mp - k0 - NB;   // > 0
+    T* zr = z + k0 + (long long)(k0 + NB) * mp;          // R(k, k+1:)
+    T* zn = z + (k0 + NB) + (long long)(k0 + NB) * mp;   // Z(k+1, k+1:)
+    // A_k: Z(k+1, k+1:) -= R(k, k+1)^T R(k, k+1:)
+    GemmProblemT<T> pa = gemm_problem(NB, rest, NB, zr, mp, 1, zr, mp, 0, zn, mp, -1.0, 1.0, zn, mp, 0);
+    pa.nb1 = batch;
+    pa.sA[0] = sz;
+    pa.sB[0] = sz;
+    pa.sC[0] = sz;
+    pa.sD[0] = sz;
+    gemm_t(s, &pa, 1);
+    // C_{k+1} with the rest of the trailing update of step k:
+    // Z(k+2:, k+2:) -= R(k, k+2:)^T R(k, k+2:)  (upper triangle)
+    if (rest > NB) {
+      T* zr2 = zr + (long long)NB * mp;
+      T* zt2 = zn + NB + (long long)NB * mp;
+      GemmProblemT<T> pt = gemm_problem(rest - NB, rest - NB, NB, zr2, mp, 1, zr2, mp, 0, zt2, mp,
+                                        -1.0, 1.0, zt2, mp, kOutUpper);
+      pt.nb1 = batch;
+      pt.sA[0] = sz;
+      pt.sB[0] = sz;
+      pt.sC[0] = sz;
+      pt.sD[0] = sz;
+      step(k0 + NB, &pt);
+    } else {
+      step(k0 + NB, nullptr);
+    }
   }
   if (!inverse) return;   // W then holds only the inverted diagonal blocks
   // ---- W = R^{-1} by recursive doubling over the block diagonal: at level S every
