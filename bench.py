@@ -242,10 +242,22 @@ def copy_probe(nbytes: int = 512 << 20):
     torch.cuda.synchronize()
 
 
-def traffic_from_profile(kernel_src: str):
-    """HBM bytes per launch of the large-tile GEMM from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def kernel_source_hash(paths) -> str:
+    """sha256 (first 16 hex digits) of the concatenated kernel sources."""
     import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+GEMM_SOURCES = [os.path.join(ROOT, "paper_2203_08900_amd", "csrc", f)
+                for f in ("gemm_f64.hip", "gemm_tile.h")]
+
+
+def traffic_from_profile(kernel_srcs):
+    """HBM bytes per launch of the large-tile GEMM from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "gemm_f64_128x128_traffic_casida_n4096.txt")
     if not os.path.exists(path):
         return None
@@ -254,8 +266,7 @@ def traffic_from_profile(kernel_src: str):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
-    if kv.get("kernel_source_sha256_16") != h:
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash(kernel_srcs):
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -382,8 +393,7 @@ def main():
         achieved = gm["flops"] / (gm["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK["f64"],
-                "traffic": traffic_from_profile(os.path.join(
-                    ROOT, "paper_2203_08900_amd", "csrc", "gemm_f64.hip")),
+                "traffic": traffic_from_profile(GEMM_SOURCES),
                 "kernel": "gemm_mfma_kernel<double,128,128,4,4>",
                 "launches_per_step": gm["launches"] / args.steps,
                 "avg_launch_ms": gm["ms"] / gm["launches"],
