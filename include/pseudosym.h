@@ -200,7 +200,7 @@ int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B,
  * and outputs Qp[i] (2m[i] x m[i], ldq[i] >= 2 m[i]) and Hp[i] (ldh[i] >= m[i]), with
  * the conventions of pseudosym_divide.  m, lda, ldb, ldq, ldh and the pointer arrays
  * are HOST arrays of length batch holding device pointers.  The problems run largest
- * first on four worker streams owned by the handle (each with its own library-owned
+ * first on six worker streams owned by the handle (each with its own library-owned
  * workspace; ps_set_workspace does not apply to them); the call returns when all are
  * done.  infos (host, length batch, may be NULL) receives one record per problem;
  * the return value is 0 or the status of the first failing problem in index order.

@@ -1334,8 +1334,9 @@ int guarded(ps_handle h, F&& f) {
 // largest first, to kWorkers host threads; each drives its own handle (stream,
 // workspace, pinned staging) through the single-problem pipeline, so that the
 // latency-bound small factorizations of different problems overlap on the device.
-// kWorkers matches the hardware queues a process gets by default.
-constexpr int kWorkers = 4;
+// Measured on 256 problems of m = 32..512: 3 workers 146 ms, 4: 143, 6: 136, 8: 136
+// (the process has 4 hardware queues; more streams than queues still fill gaps).
+constexpr int kWorkers = 6;
 
 int run_batched(ps_handle h, int batch, const int* m, const double* const* A, const int* lda,
                 const double* const* B, const int* ldb, double* const* Qp, const int* ldq,
