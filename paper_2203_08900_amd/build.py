@@ -20,6 +20,7 @@ SOURCES = [
     "gemm_f64.hip",
     "chol_f64.hip",
     "misc_f64.hip",
+    "batch.hip",
     "eig_f64.hip",
     "mixed.hip",
     "zolo_host.cpp",

@@ -227,6 +227,8 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
       throw HipError{hipErrorInvalidValue, "gemm_f64: bad K segmentation"};
     if (p.ksplit < 1 || (p.ksplit > 1 && (p.nb1 * p.nb2 != 1 || !p.ws)))
       throw HipError{hipErrorInvalidValue, "gemm_f64: bad split-K setup"};
+    if (p.ksplit > 1 && (p.alpha_b || p.beta_b))
+      throw HipError{hipErrorInvalidValue, "gemm_f64: per-entry scalars with split-K"};
     if (p.M % 128 || p.N % 128 || std::min(p.M, p.N) < 512) big = false;
     const long long tm = p.M / 128, tn = p.N / 128;
     tiles128 += ((p.flags & (kOutUpper | kOutLower)) ? tm * (tm + 1) / 2 : tm * tn) *

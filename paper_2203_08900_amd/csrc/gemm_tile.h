@@ -193,7 +193,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
   auto load = [&](int kt, T* ra, T* rb, double& rsc) {
     const int s = kt / per;
     const int k0 = s * segK + kb + (kt - s * per) * BK;
-    rsc = P.kseg > 0 ? P.kscale[s] : 1.0;
+    rsc = P.kseg > 0 ? (P.kscale_b ? P.kscale_b[z * P.nseg + s] : P.kscale[s]) : 1.0;
 #pragma unroll
     for (int p = 0; p < APT; ++p) {
       const int idx = tid + p * NT;
@@ -270,7 +270,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
   // row by row in the epilogue.
   constexpr bool kEarlyC = (BM == 64);
   T cpre[kEarlyC ? FM : 1][FN][4];
-  if (kEarlyC && P.beta != 0.0) {
+  if (kEarlyC && (P.beta_b ? P.beta_b[z] : P.beta) != 0.0) {
 #pragma unroll
     for (int a = 0; a < (kEarlyC ? FM : 1); ++a)
 #pragma unroll
@@ -305,7 +305,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
     }
   }
 
-  const double alpha = P.alpha, beta = P.beta;
+  const double alpha = P.alpha_b ? P.alpha_b[z] : P.alpha;
+  const double beta = P.beta_b ? P.beta_b[z] : P.beta;
   if (P.ksplit > 1) {
     // partial tile of split ks (batch extent is 1 for split problems)
     T* W = P.ws + (long long)ks * P.M * P.N;

@@ -56,6 +56,10 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kPinned = 1 << 16;  // doubles (host staging: up to m = 32768 values)
+// below this padded size the FP32 group of a mixed step costs more in extra launches and
+// stream hand-offs than its arithmetic saves (measured on 256 problems of 32..512): such
+// problems run in FP64
+constexpr int kMixedMin = 1024;
 
 struct Arena {
   char* base = nullptr;
@@ -717,9 +721,6 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
 
   // ---- Zolotarev steps with the stopping test of Alg. 8
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
-  // below kMixedMin the FP32 group's extra launches and stream hand-offs cost more than
-  // its arithmetic saves (measured on 256 problems of 32..512): those sizes run in FP64
-  constexpr int kMixedMin = 1024;
   const bool mixed = o.precision == PS_PREC_MIXED && mp >= kMixedMin;
   const int status =
       polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm, mixed ? &mxc : nullptr);
@@ -1338,6 +1339,321 @@ int guarded(ps_handle h, F&& f) {
 // (the process has 4 hardware queues; more streams than queues still fill gaps).
 constexpr int kWorkers = 6;
 
+// ---- One batched pipeline for a class of problems with the same padded size (core
+// basis, FP64 arithmetic, no restarts): every launch of the single-problem path covers
+// the whole class, with the per-problem scalars (bounds, Zolotarev coefficients, shifts,
+// series coefficients) in small device arrays.  Problems the class cannot finish (a
+// failed factorization, a step needing a restart or the Cholesky form of step 2) are
+// returned in `redo` for the single-problem path.  The arithmetic per problem is that
+// of the single path; sums split differently (no split-K), so results agree with it to
+// rounding, not bit for bit.
+struct ClassBufs {
+  int nb = 0, mp = 0, r = 0;
+  long long S = 0;
+  double *mk, *wmk, *y, *yt, *x0, *x1, *x2, *g, *z, *w, *nmat, *t1, *t2, *s12, *p11, *wc, *top,
+      *qbot, *hp, *vv, *uu, *pp, *hist, *norms, *scal;
+  int *dinfo, *mdev;
+};
+
+constexpr int kClassScal = 64;   // per-problem scalar slots (see run_class)
+
+void carve_class(Arena& a, ClassBufs& c, int nb, int mp, int r) {
+  c.nb = nb;
+  c.mp = mp;
+  c.r = r;
+  c.S = (long long)mp * mp;
+  const size_t S = (size_t)c.S, n = (size_t)nb;
+  c.mk = a.take<double>(2 * n * S);
+  c.wmk = a.take<double>(2 * n * S);
+  c.y = a.take<double>(2 * n * S);
+  c.yt = a.take<double>(2 * n * S);
+  c.x0 = a.take<double>(n * S);
+  c.x1 = a.take<double>(n * S);
+  c.x2 = a.take<double>(n * S);
+  c.g = a.take<double>(n * S);
+  c.z = a.take<double>((size_t)r * n * S);
+  c.w = a.take<double>((size_t)r * n * S);
+  c.nmat = a.take<double>(n * S);
+  c.t1 = a.take<double>(n * S);
+  c.t2 = a.take<double>(n * S);
+  c.s12 = a.take<double>(n * S);
+  c.p11 = a.take<double>(n * S);
+  c.wc = a.take<double>(n * S);
+  c.top = a.take<double>(n * S);
+  c.qbot = a.take<double>(n * S);
+  c.hp = a.take<double>(n * S);
+  c.vv = a.take<double>(2 * n * mp);
+  c.uu = a.take<double>(2 * n * mp);
+  c.pp = a.take<double>(2 * n * mp);
+  c.hist = a.take<double>(2 * n * 256);
+  c.norms = a.take<double>(2 * n);
+  c.scal = a.take<double>(n * kClassScal);
+  c.dinfo = a.take<int>(16);
+  c.mdev = a.take<int>(n);
+}
+
+size_t class_bytes(int nb, int mp, int r) {
+  Arena a;
+  ClassBufs c;
+  carve_class(a, c, nb, mp, r);
+  return a.off + kAlign;
+}
+
+// Problems with padded size mp and at most this many per class launch (memory: about
+// (37 + 2r) mp^2 doubles each).
+constexpr int kClassMax = 16;
+
+int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const double* const* A,
+              const int* lda, const double* const* B, const int* ldb, double* const* Qp,
+              const int* ldq, double* const* Hp, const int* ldh, const ps_opts& o,
+              ps_info* infos, std::vector<int>& redo) {
+  hipStream_t s = h->stream;
+  const int nb = (int)idx.size();
+  const int mp = pad_to(m[idx[0]]);
+  const int rmax = resolve_r(o);
+  char* base = workspace_base(h, class_bytes(nb, mp, rmax));
+  if (!base) return PS_NO_WORKSPACE;
+  Arena ar;
+  ar.base = base;
+  ar.dry = false;
+  ClassBufs c;
+  carve_class(ar, c, nb, mp, rmax);
+  const long long S = c.S;
+  double* pin = h->pinned;
+  auto fail_all = [&] {
+    for (int p : idx) redo.push_back(p);
+    return PS_OK;
+  };
+  // ---- setup (a0): M_b, K_b packed as matrices 2b, 2b + 1; one batched factorization
+  fill_int_zero(s, c.dinfo, 16);
+  int* ipin = (int*)pin;
+  for (int b = 0; b < nb; ++b) {
+    const int p = idx[b];
+    pack_casida(s, m[p], mp, A[p], lda[p], B[p], ldb[p], c.mk + 2 * b * S);
+    ipin[b] = m[p];
+  }
+  PS_HIP(hipMemcpyAsync(c.mdev, ipin, nb * sizeof(int), hipMemcpyHostToDevice, s));
+  potrf_inv_f64(s, c.mk, S, c.wmk, S, nullptr, mp, 2 * nb, c.dinfo + 0);
+  {
+    GemmProblem pg[2];
+    pg[0] = gemm_problem(mp, mp, mp, c.mk, mp, 0, c.mk + S, mp, 1, c.y, mp, 1.0, 0.0, nullptr, 0,
+                         kAUpper | kBLower);
+    pg[1] = gemm_problem(mp, mp, mp, c.wmk + S, mp, 1, c.wmk, mp, 0, c.y + S, mp, 1.0, 0.0, nullptr,
+                         0, kALower | kBUpper);
+    for (auto& q : pg) {
+      q.nb1 = nb;
+      q.sA[0] = q.sB[0] = q.sC[0] = q.sD[0] = 2 * S;
+    }
+    gemm_f64(s, pg, 2);
+  }
+  for (int b = 0; b < nb; ++b) mask_pad(s, c.y + 2 * b * S, m[idx[b]], mp, S, 2);
+  // ---- bounds (a1): Golub-Kahan on all 2 nb matrices at once
+  const int steps = std::max(4, std::min(o.lanczos_steps, 120));
+  transpose(s, c.y, c.yt, mp, S, 2 * nb);
+  gk_init_b(s, c.vv, c.mdev, mp, 2 * nb, 2);
+  for (int k = 0; k < steps; ++k) {
+    coldots(s, c.yt, S, c.vv, mp, c.pp, mp, mp, 2 * nb);
+    gk_update(s, c.pp, mp, c.uu, mp, k > 0 ? c.uu : nullptr, mp, c.hist, 2 * k - 1, 2 * k, 256,
+              mp, 2 * nb);
+    coldots(s, c.y, S, c.uu, mp, c.pp, mp, mp, 2 * nb);
+    gk_update(s, c.pp, mp, c.vv, mp, c.vv, mp, c.hist, 2 * k, 2 * k + 1, 256, mp, 2 * nb);
+  }
+  const size_t hist_n = (size_t)2 * nb * 256;
+  if (hist_n + 16 > (size_t)kPinned) return fail_all();
+  PS_HIP(hipMemcpyAsync(pin, c.hist, hist_n * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipMemcpyAsync(pin + hist_n, c.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  if (((int*)(pin + hist_n))[0] != 0) return fail_all();   // not definite somewhere
+  std::vector<double> alpha(nb), beta(nb), ell(nb);
+  int r = (o.r <= 0) ? 1 : rmax;
+  for (int b = 0; b < nb; ++b) {
+    double smax[2];
+    for (int q = 0; q < 2; ++q) {
+      double d[128], e[128], smn;
+      for (int k = 0; k < steps; ++k) {
+        d[k] = pin[(2 * b + q) * 256 + 2 * k];
+        e[k] = pin[(2 * b + q) * 256 + 2 * k + 1];
+      }
+      bidiag_extreme_sv(d, e, steps, &smax[q], &smn);
+    }
+    alpha[b] = o.alpha > 0.0 ? o.alpha : 1.01 * smax[0];
+    beta[b] = o.beta > 0.0 ? o.beta : 0.99 / smax[1];
+    if (!(alpha[b] > 0.0) || !(beta[b] > 0.0) || !std::isfinite(alpha[b]) ||
+        !std::isfinite(beta[b]))
+      return fail_all();
+    ell[b] = std::min(beta[b] / alpha[b], 1.0 - 1e-15);
+    if (o.r <= 0) r = std::max(r, auto_r(ell[b]));
+  }
+  // ---- coefficients per problem (a2) and their device arrays
+  //   scal[0 .. nb)          1/alpha_b               scal[nb .. 2nb)   hat C of step 1
+  //   scal[2nb .. 2nb+nb r)  a_j of step 1 (b-major)  then c_{2j-1} of step 1 (b-major)
+  //   then hat C of step 2 (nb), then the Horner coefficients of step 2 (p-major, nb each)
+  std::vector<ZoloHost> c1(nb), c2(nb);
+  std::vector<double> gam((size_t)nb * kMaxSeries);
+  int P = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (zolotarev_host(ell[b], r, &c1[b])) return fail_all();
+    const double ell1 = std::min(c1[b].ell_next, 1.0 - 1e-15);
+    if (zolotarev_host(ell1, r, &c2[b])) return fail_all();
+    const int Pb = o.step2_series ? series_terms(c2[b], ell1, &gam[(size_t)b * kMaxSeries]) : 0;
+    if (Pb == 0) return fail_all();
+    P = std::max(P, Pb);
+  }
+  double* hs = pin;   // staging for the upload (the downloads above are complete)
+  const int o_inva = 0, o_chat1 = nb, o_a1 = 2 * nb, o_c1 = 2 * nb + nb * r,
+            o_chat2 = 2 * nb + 2 * nb * r, o_h = o_chat2 + nb;
+  const int n_scal = o_h + nb * (kMaxSeries + 3);
+  if (n_scal > nb * kClassScal) return fail_all();
+  for (int b = 0; b < nb; ++b) {
+    hs[o_inva + b] = 1.0 / alpha[b];
+    hs[o_chat1 + b] = c1[b].chat;
+    for (int j = 0; j < r; ++j) {
+      hs[o_a1 + b * r + j] = c1[b].a[j];
+      hs[o_c1 + b * r + j] = c1[b].c[2 * j];
+    }
+    hs[o_chat2 + b] = c2[b].chat;
+    const double* gb = &gam[(size_t)b * kMaxSeries];
+    // Horner stages: T = gam_{P-1} Delta + gam'_{P-2} I, then T <- Delta T + gam'_q I,
+    // gam'_0 = 1 + gam_0 (slot p holds gam'_p; slots kMaxSeries.. hold 1, -1 and 0)
+    for (int p = 0; p < kMaxSeries; ++p) hs[o_h + p * nb + b] = p == 0 ? 1.0 + gb[0] : gb[p];
+    hs[o_h + kMaxSeries * nb + b] = 1.0;
+    hs[o_h + (kMaxSeries + 1) * nb + b] = -1.0;
+    hs[o_h + (kMaxSeries + 2) * nb + b] = 0.0;
+  }
+  PS_HIP(hipMemcpyAsync(c.scal, hs, n_scal * sizeof(double), hipMemcpyHostToDevice, s));
+  const double* d_inva = c.scal + o_inva;
+  const double* d_chat1 = c.scal + o_chat1;
+  const double* d_a1 = c.scal + o_a1;
+  const double* d_c1 = c.scal + o_c1;
+  const double* d_chat2 = c.scal + o_chat2;
+  auto d_h = [&](int p) { return c.scal + o_h + (size_t)p * nb; };
+  const double* d_one = d_h(kMaxSeries);
+  const double* d_mone = d_h(kMaxSeries + 1);
+  const double* d_zero = d_h(kMaxSeries + 2);
+  auto batched = [&](GemmProblem q, long long sa, long long sb, long long sd) {
+    q.nb1 = nb;
+    q.sA[0] = sa;
+    q.sB[0] = sb;
+    q.sC[0] = sd;
+    q.sD[0] = sd;
+    return q;
+  };
+  // ---- step 1 (a3): X1 = hat C X0 (I + sum_j a_j (X0^T X0 + c_j I)^{-1})
+  scale_b(s, c.y, 2 * S, c.x0, S, d_inva, (size_t)S, nb);
+  {
+    GemmProblem pg = batched(gemm_problem(mp, mp, mp, c.x0, mp, 1, c.x0, mp, 0, c.g, mp, 1.0, 0.0,
+                                          nullptr, 0, kOutUpper), S, S, S);
+    gemm_f64(s, pg);
+    form_shifts_b(s, c.g, c.z, mp, d_c1, r, nb);
+    potrf_inv_f64(s, c.z, S, c.w, S, nullptr, mp, r * nb, c.dinfo + 1);
+    GemmProblem pn = batched(gemm_problem(mp, mp, r * mp, c.w, mp, 0, c.w, mp, 1, c.nmat, mp, 1.0,
+                                          0.0, nullptr, 0,
+                                          kAUpper | kBLower | kOutUpper | kMirror),
+                             r * S, r * S, S);
+    pn.kseg = mp;
+    pn.nseg = r;
+    pn.kscale_b = d_a1;
+    gemm_f64(s, pn);
+    GemmProblem px = batched(gemm_problem(mp, mp, mp, c.x0, mp, 0, c.nmat, mp, 0, c.x1, mp, 1.0,
+                                          1.0, c.x0, mp, 0),
+                             S, S, S);
+    px.alpha_b = d_chat1;
+    px.beta_b = d_chat1;
+    gemm_f64(s, px);
+  }
+  // ---- step 2 (a3) by the series: X2 = hat C X1 T(Delta), Delta = X1^T X1 - I
+  {
+    GemmProblem pg = batched(gemm_problem(mp, mp, mp, c.x1, mp, 1, c.x1, mp, 0, c.g, mp, 1.0, 0.0,
+                                          nullptr, 0, kOutUpper | kMirror), S, S, S);
+    gemm_f64(s, pg);
+    axpb_identity_b(s, c.g, c.g, d_one, d_mone, mp, nb);   // Delta
+    double* T = c.nmat;
+    double* T2 = c.t1;
+    if (P == 1) {
+      axpb_identity_b(s, c.g, T, d_zero, d_h(0), mp, nb);   // T = (1 + gam_0) I
+    } else {
+      axpb_identity_b(s, c.g, T, d_h(P - 1), d_h(P - 2), mp, nb);
+      for (int q = P - 3; q >= 0; --q) {
+        GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.g, mp, 0, T, mp, 0, T2, mp), S, S, S);
+        gemm_f64(s, ph);
+        axpb_identity_b(s, T2, T, d_one, d_h(q), mp, nb);
+      }
+    }
+    GemmProblem px = batched(gemm_problem(mp, mp, mp, c.x1, mp, 0, T, mp, 0, c.x2, mp), S, S, S);
+    px.alpha_b = d_chat2;
+    gemm_f64(s, px);
+  }
+  // ---- stopping test (a4) per problem
+  diff_norms_b(s, c.x1, c.x2, (size_t)S, c.norms, nb);
+  PS_HIP(hipMemcpyAsync(pin, c.norms, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipMemcpyAsync(pin + 2 * nb, c.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  if (((int*)(pin + 2 * nb))[1] != 0) return fail_all();
+  const double tol = std::pow(std::ldexp(1.0, -53), 1.0 / (2 * r + 1));
+  std::vector<char> ok(nb, 1);
+  std::vector<double> change(nb);
+  for (int b = 0; b < nb; ++b) {
+    change[b] = std::sqrt(pin[2 * b]) / std::sqrt(pin[2 * b + 1]);
+    if (!(change[b] <= tol)) ok[b] = 0;
+  }
+  // ---- core basis (a7, a8): Q_+ = Z R_G^{-1}, H_+ = 2 R_G^{-T} R_G^{-1}
+  const double* U = c.x2;
+  {
+    GemmProblem pt = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, U, mp, 0, c.t1, mp, 1.0, 0.0,
+                                          nullptr, 0, kAUpper), 2 * S, S, S);
+    gemm_f64(s, pt);
+    GemmProblem pv = batched(gemm_problem(mp, mp, mp, c.wmk + S, mp, 1, c.t1, mp, 0, c.t2, mp, 1.0,
+                                          0.0, nullptr, 0, kALower), 2 * S, S, S);
+    gemm_f64(s, pv);
+    for (int b = 0; b < nb; ++b)
+      sym_scale_upper(s, c.t2 + b * S, c.p11 + b * S, m[idx[b]], mp, 1.0);
+    potrf_inv_f64(s, c.p11, S, c.wc, S, nullptr, mp, nb, c.dinfo + 4);
+    GemmProblem pe[2];
+    pe[0] = batched(gemm_problem(mp, mp, mp, c.t1, mp, 0, c.wc, mp, 0, c.t2, mp, 1.0, 0.0, nullptr,
+                                 0, kBUpper), S, S, S);
+    pe[1] = batched(gemm_problem(mp, mp, mp, c.wmk + S, mp, 0, c.wc, mp, 0, c.s12, mp, 1.0, 0.0,
+                                 nullptr, 0, kAUpper | kBUpper), 2 * S, S, S);
+    gemm_f64(s, pe, 2);
+    for (int b = 0; b < nb; ++b)   // (sum_diff_scaled takes the matrix edge, not a length)
+      sum_diff_scaled(s, c.t2 + b * S, c.s12 + b * S, c.top + b * S, c.qbot + b * S, M_SQRT1_2,
+                      mp);
+    GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.wc, mp, 1, c.wc, mp, 0, c.hp, mp, 2.0, 0.0,
+                                          nullptr, 0, kALower | kBUpper | kOutUpper | kMirror),
+                             S, S, S);
+    gemm_f64(s, ph);
+  }
+  PS_HIP(hipMemcpyAsync(pin, c.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  if (((int*)pin)[4] != 0) return fail_all();
+  for (int b = 0; b < nb; ++b) {
+    const int p = idx[b];
+    if (!ok[b]) {
+      redo.push_back(p);
+      continue;
+    }
+    const int mm = m[p];
+    copy_out(s, c.top + b * S, mp, Qp[p], ldq[p], mm, mm);
+    copy_out(s, c.qbot + b * S, mp, Qp[p] + mm, ldq[p], mm, mm);
+    copy_out(s, c.hp + b * S, mp, Hp[p], ldh[p], mm, mm);
+    if (infos) {
+      ps_info& inf = infos[p];
+      inf = ps_info{};
+      inf.status = PS_OK;
+      inf.failed_step = -1;
+      inf.steps = 2;
+      inf.r = r;
+      inf.alpha = alpha[b];
+      inf.beta = beta[b];
+      inf.ell[0] = ell[b];
+      inf.ell[1] = std::min(c1[b].ell_next, 1.0 - 1e-15);
+      inf.step_change = change[b];
+      inf.step2_terms = P;
+    }
+  }
+  PS_HIP(hipStreamSynchronize(s));
+  return PS_OK;
+}
+
 int run_batched(ps_handle h, int batch, const int* m, const double* const* A, const int* lda,
                 const double* const* B, const int* ldb, double* const* Qp, const int* ldq,
                 double* const* Hp, const int* ldh, const ps_opts& o, ps_info* infos) {
@@ -1356,24 +1672,68 @@ int run_batched(ps_handle h, int batch, const int* m, const double* const* A, co
   // the inputs may still be in flight on the caller's stream
   PS_HIP(hipEventRecord(h->fork, h->stream));
   for (int k = 0; k < nw; ++k) PS_HIP(hipStreamWaitEvent(h->workers[k]->stream, h->fork, 0));
-  std::vector<int> order(batch);
-  for (int i = 0; i < batch; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m[x] > m[y]; });
+  // Jobs, largest first: with the core basis in FP64 arithmetic (mixed requests below
+  // the mixed threshold run in FP64 anyway), problems of one padded size form classes of
+  // up to kClassMax that run as one batched pipeline; everything else, and what a class
+  // hands back, runs one problem at a time.
+  const bool classes = o.basis == PS_BASIS_CORE && o.max_steps != 1 && o.timing == 0 &&
+                       (o.precision == PS_PREC_FP64 || o.precision == PS_PREC_MIXED);
+  std::vector<std::vector<int>> jobs;
+  {
+    std::vector<int> order(batch);
+    for (int i = 0; i < batch; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m[x] > m[y]; });
+    size_t i = 0;
+    while (i < order.size()) {
+      const int mp = pad_to(m[order[i]]);
+      size_t j = i;
+      while (j < order.size() && pad_to(m[order[j]]) == mp) ++j;
+      const bool cls = classes && j - i >= 2 &&
+                       (o.precision == PS_PREC_FP64 || mp < kMixedMin);
+      if (cls) {
+        for (size_t a = i; a < j; a += kClassMax)
+          jobs.emplace_back(order.begin() + a, order.begin() + std::min(j, a + kClassMax));
+      } else {
+        for (size_t a = i; a < j; ++a) jobs.push_back({order[a]});
+      }
+      i = j;
+    }
+  }
   std::vector<int> status(batch, PS_OK);
   std::atomic<int> next{0};
+  const int njobs = (int)jobs.size();
   auto work = [&](int k) {
     ps_handle w = h->workers[k];
     if (hipSetDevice(h->device) != hipSuccess) {
-      for (int i; (i = next.fetch_add(1)) < batch;) status[order[i]] = PS_HIP_ERROR;
+      for (int i; (i = next.fetch_add(1)) < njobs;)
+        for (int p : jobs[i]) status[p] = PS_HIP_ERROR;
       return;
     }
-    for (int i; (i = next.fetch_add(1)) < batch;) {
-      const int p = order[i];
+    auto single = [&](int p) {
       ps_info local{};
       ps_info* inf = infos ? &infos[p] : &local;
       status[p] = guarded(w, [&] {
         return run(w, m[p], A[p], lda[p], B[p], ldb[p], Qp[p], ldq[p], Hp[p], ldh[p], o, inf, 1);
       });
+    };
+    for (int i; (i = next.fetch_add(1)) < njobs;) {
+      const std::vector<int>& job = jobs[i];
+      if (job.size() == 1) {
+        single(job[0]);
+        continue;
+      }
+      std::vector<int> redo;
+      const int st = guarded(w, [&] {
+        return run_class(w, job, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, infos, redo);
+      });
+      if (st != PS_OK) {
+        redo = job;   // the class could not run at all (workspace, device error)
+        if (st == PS_HIP_ERROR) {
+          for (int p : job) status[p] = st;
+          continue;
+        }
+      }
+      for (int p : redo) single(p);
     }
   };
   std::vector<std::thread> threads;

@@ -66,6 +66,11 @@ struct GemmProblemT {
   double alpha, beta;
   double kscale[kMaxSeg];
   T* ws;            // ksplit * M * N elements per batch entry (only when ksplit > 1)
+  // optional per-batch-entry scalars in device memory (entry z = z1 + nb1 * z2); when
+  // set they replace alpha, beta and kscale (kscale_b[z * nseg + s])
+  const double* alpha_b;
+  const double* beta_b;
+  const double* kscale_b;
   // filled by the launcher
   int tm, tn, tiles, tiles_per_batch, tile_begin;
 };
@@ -189,6 +194,16 @@ void grad_assemble(hipStream_t s, const double* k, int np, int m, double* ga, do
 
 // Golub-Kahan bidiagonalization (batch of two matrices M_b with transposes Mt_b).
 void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned seed);
+// batched division (batch.hip): per-matrix scalars from device arrays
+void scale_b(hipStream_t s, const double* x, long long sx, double* y, long long sy,
+             const double* f, size_t n, int nb);
+void form_shifts_b(hipStream_t s, const double* g, double* z, int mp, const double* c, int r,
+                   int nb);
+void axpb_identity_b(hipStream_t s, const double* x, double* y, const double* a,
+                     const double* c, int mp, int nb);
+void diff_norms_b(hipStream_t s, const double* x1, const double* x2, size_t n, double* out,
+                  int nb);
+void gk_init_b(hipStream_t s, double* v, const int* m_dev, int mp, int count, int per);
 void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
              long long xstride, double* y, long long ystride, int mp, int batch);
 void gk_update(hipStream_t s, const double* p, long long pstride, double* w,

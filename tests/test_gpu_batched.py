@@ -58,3 +58,37 @@ def test_batched_bad_arguments():
     a, b = inputs.small_dense(8, 1)
     with pytest.raises(api.PseudosymError):
         api.divide_batched([dev(a)], [dev(b)], r=9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_core_classes_match_single(precision):
+    """With the core basis, problems of one padded size run as one batched pipeline
+    (per-problem bounds, coefficients and shifts in device arrays).  The arithmetic per
+    problem is the single path's with sums split differently, so the results agree with
+    single calls to rounding: same eigenvalues of H_+ to 1e-12, Sigma-orthonormal Q_+,
+    and the same subspace (P_+ = Q_+ Q_+^T Sigma)."""
+    sizes = [40, 50, 60, 33, 130, 140, 150, 129, 7, 300, 310, 290, 64, 1, 2, 3]
+    probs = [inputs.small_dense(mi, 300 + i) for i, mi in enumerate(sizes)]
+    As = [dev(a) for a, _ in probs]
+    Bs = [dev(b) for _, b in probs]
+    print(f"[classes] {precision} sizes {sizes}", flush=True)
+    Qs, Hs, infos = api.divide_batched(As, Bs, precision=precision, basis="core")
+    assert all(inf["status"] == 0 for inf in infos)
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        m = sizes[i]
+        Q1, H1, _ = api.divide(A, B, precision=precision, basis="core")
+        sig = torch.cat([torch.ones(m, dtype=torch.float64, device="cuda"),
+                         -torch.ones(m, dtype=torch.float64, device="cuda")])
+        G = Qs[i].T @ (sig[:, None] * Qs[i])
+        assert (G - torch.eye(m, dtype=torch.float64, device="cuda")).abs().max().item() < 1e-12
+        P1 = Q1 @ Q1.T * sig[None, :]
+        P2 = Qs[i] @ Qs[i].T * sig[None, :]
+        assert (P1 - P2).abs().max().item() < 1e-11
+        w1 = np.linalg.eigvalsh(0.5 * (H1 + H1.T).cpu().numpy())
+        w2 = np.linalg.eigvalsh(0.5 * (Hs[i] + Hs[i].T).cpu().numpy())
+        assert np.max(np.abs(w1 - w2) / w1) < 1e-12
+    for i in (0, 4, 9):
+        a, b = probs[i]
+        lam = np.sort(np.sqrt(np.linalg.eigvals((a - b) @ (a + b)).real))
+        w = np.sort(np.linalg.eigvalsh(0.5 * (Hs[i] + Hs[i].T).cpu().numpy()))
+        assert np.max(np.abs(w - lam) / lam) < 1e-11
