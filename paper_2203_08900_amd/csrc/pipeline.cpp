@@ -1399,9 +1399,17 @@ size_t class_bytes(int nb, int mp, int r) {
   return a.off + kAlign;
 }
 
-// Problems with padded size mp and at most this many per class launch (memory: about
-// (37 + 2r) mp^2 doubles each).
-constexpr int kClassMax = 16;
+// At most this many problems per class, and at most kClassBytes of workspace for one
+// (about (37 + 2r) mp^2 doubles per problem).  Measured on 256 problems of m = 32..512
+// (about 32 per padded size): classes of 8, 16, 32, 64: 41, 36, 33, 32 ms.
+constexpr int kClassMax = 32;
+constexpr size_t kClassBytes = (size_t)3 << 30;
+
+int class_limit(int mp, int r) {
+  const size_t one = class_bytes(1, mp, r);
+  const size_t fit = kClassBytes / (one ? one : 1);
+  return (int)std::min<size_t>(kClassMax, fit);
+}
 
 int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const double* const* A,
               const int* lda, const double* const* B, const int* ldb, double* const* Qp,
@@ -1688,11 +1696,12 @@ int run_batched(ps_handle h, int batch, const int* m, const double* const* A, co
       const int mp = pad_to(m[order[i]]);
       size_t j = i;
       while (j < order.size() && pad_to(m[order[j]]) == mp) ++j;
-      const bool cls = classes && j - i >= 2 &&
+      const int lim = class_limit(mp, resolve_r(o));
+      const bool cls = classes && j - i >= 2 && lim >= 2 &&
                        (o.precision == PS_PREC_FP64 || mp < kMixedMin);
       if (cls) {
-        for (size_t a = i; a < j; a += kClassMax)
-          jobs.emplace_back(order.begin() + a, order.begin() + std::min(j, a + kClassMax));
+        for (size_t a = i; a < j; a += lim)
+          jobs.emplace_back(order.begin() + a, order.begin() + std::min(j, a + (size_t)lim));
       } else {
         for (size_t a = i; a < j; ++a) jobs.push_back({order[a]});
       }
