@@ -158,8 +158,8 @@ __device__ inline void chol4(T d[4][4], T w[4][4], bool& bad) {
 // the caller may reuse the staging area at once.  Every thread of the workgroup must
 // call this (at least 256).
 template <class T>
-__device__ void factor_invert_block(T* lds, T* Z, T* W, long long ld, int* info, int bit,
-                                    bool store) {
+__device__ __forceinline__ void factor_invert_block(T* lds, T* Z, T* W, long long ld, int* info,
+                                                    int bit, bool store) {
   auto panels = reinterpret_cast<T(*)[4][kB]>(lds + kPanel);
   auto wd = reinterpret_cast<T(*)[4][4]>(lds + kWd);
   T* stage = lds + kStage;

@@ -2,11 +2,10 @@
 // or FP32 (one template).
 //
 // Blocked right-looking algorithm over 64 x 64 diagonal blocks with a look-ahead of one
-// block row.  Per block step k:
-//   1. a small GEMM applies panel k to block row k+1;
-//   2. one launch factors and inverts diagonal block k+1 and forms its panel
-//      R(k+1, k+2:) = R^{-T} Z(k+1, k+2:) (each panel tile's workgroup factors the block
-//      itself) while its other workgroups apply panel k to the rows below block row k+1.
+// block row.  Per block step k, one launch applies panel k to block row k+1, factors and
+// inverts diagonal block k+1 and forms its panel R(k+1, k+2:) = R^{-T} Z(k+1, k+2:) (each
+// panel tile's workgroup updates and factors the block itself, and updates its own tile)
+// while its other workgroups apply panel k to the rows below block row k+1.
 // The full inverse factor W = R^{-1} is then assembled from the inverted diagonal
 // blocks by recursive doubling, one pair of GEMM launches per level.  The batch index
 // runs over independent matrices (the r shifted Gram matrices of a Zolotarev step, or
@@ -20,40 +19,134 @@ namespace ps {
 namespace {
 constexpr int NB = kNb;
 constexpr int NTD = 256;
+constexpr int kWideBatch = 2;
 }
 
-// One step of the blocked factorization, diagonal block and panel together.  Every
-// workgroup (ntiles per matrix) factors and inverts the 64 x 64 diagonal block at k0 in
-// LDS (the same arithmetic in each, so all agree; tile 0 stores R_kk^{-1} and R_kk) and
-// then forms its 64-column tile of the panel R(k, k+1:) = R_kk^{-T} Z(k, k+1:) on the
-// matrix cores, in place.  The redundant factorizations run side by side on otherwise
-// idle compute units; what they save is a dependent launch per step.
+// LDS of a step in the wide variant: the block layout, then R(k-1, tile) and the panel
+// tile (row-major [64][65] each).  The narrow variant uses the block layout alone.
+constexpr int kQt = blk::kLdsElems;
+constexpr int kUt = kQt + NB * blk::kLdS;
+constexpr int kWideElems = kUt + NB * blk::kLdS;
+
+// Load the 64 x 64 block at g (column-major, leading dimension ld) into registers, and
+// store such values row-major into LDS at l (leading dimension 65).
 template <class T>
-__device__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long sw, int ld, int k0,
+__device__ inline void load_block(const T* g, long long ld, T (&val)[NB * NB / NTD]) {
+#pragma unroll
+  for (int q = 0; q < NB * NB / NTD; ++q) {
+    const int e = threadIdx.x + q * NTD;
+    val[q] = g[e % NB + (long long)(e / NB) * ld];
+  }
+}
+template <class T>
+__device__ inline void stage_block(T* l, const T (&val)[NB * NB / NTD]) {
+#pragma unroll
+  for (int q = 0; q < NB * NB / NTD; ++q) {
+    const int e = threadIdx.x + q * NTD;
+    l[(e % NB) * blk::kLdS + e / NB] = val[q];
+  }
+}
+
+// D -= P^T Q for the 16 x 16 tile (ti, tj) of row-major LDS blocks (wave-wide).
+template <class T>
+__device__ inline void sub_ptq(T* D, const T* P, const T* Q, int ti, int tj) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  const auto acc = blk::tile_mm_ta(P + 16 * ti, blk::kLdS, Q + 16 * tj, blk::kLdS, NB);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    T* d = D + (16 * ti + blk::BlkMfma<T>::row(lk, v)) * blk::kLdS + 16 * tj + li;
+    *d -= acc[v];
+  }
+}
+
+// One step of the blocked factorization: the update of block row k by panel k-1, the
+// diagonal block and the panel together.  Every workgroup (ntiles per matrix) applies
+// the update to the diagonal block, factors and inverts it in LDS (the same arithmetic
+// in each, so all agree; tile 0 stores R_kk^{-1} and R_kk), applies the update to its
+// own 64-column tile of block row k and forms that tile of the panel
+// R(k, k+1:) = R_kk^{-T} Z(k, k+1:) on the matrix cores, in place.  The redundant work
+// runs side by side on otherwise idle compute units; what it saves is a dependent
+// launch per step.
+//
+// Two variants of the LDS use.  Wide: R(k-1, tile) and the panel tile are staged in
+// LDS as well (about 144 KB in FP64, one workgroup per compute unit), which gives the
+// shortest diagonal chain when a step has few matrices.  Narrow: R(k-1, tile) is read
+// from memory as the matrix-core operand and the panel tile stays in registers until
+// the panel product (the block layout alone, two FP64 workgroups per compute unit), so
+// that the trailing-update tiles of many matrices run at twice the occupancy.
+template <class T, bool kWide>
+__device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long sw, int ld, int k0,
                            int rest, int ntiles, int* info) {
+  using Acc = typename blk::BlkMfma<T>::acc_t;
   const int b = bid / ntiles, t = bid - b * ntiles;
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
+  T* Zt = Z + (long long)(NB + NB * t) * ld;   // panel tile t: columns k0 + 64 + 64t..
+  const bool upd = k0 > 0;                     // block row k still owes panel k-1's update
+  const bool tile = rest > 0;
+  T* const stage = lds + blk::kStage;
+  T* const Pl = lds + blk::kWl;   // R(k-1, k) until the factorization takes the area
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  // all loads in flight at once (lower triangles are staged too and ignored where they
+  // do not matter); narrow: wave w's row of 16 x 16 tiles of the panel tile goes straight
+  // into the accumulator layout
   constexpr int Q = NB * NB / NTD;
-  // all loads in flight at once, then into LDS (the lower triangle is staged too and
-  // ignored)
-  T val[Q];
+  T vz[Q], vp[Q];
+  load_block(Z, ld, vz);
+  if (upd) load_block(Z - NB, ld, vp);
+  Acc u[4];
+  if constexpr (kWide) {
+    T vt[Q], vq[Q];
+    if (tile) load_block(Zt, ld, vt);
+    if (upd && tile) load_block(Zt - NB, ld, vq);
+    if (tile) stage_block(lds + kUt, vt);
+    if (upd && tile) stage_block(lds + kQt, vq);
+  } else {
+    if (tile) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + q * NTD;
-    val[q] = Z[e % NB + (long long)(e / NB) * ld];
-  }
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + q * NTD;
-    lds[blk::kStage + (e % NB) * blk::kLdS + e / NB] = val[q];
+        for (int v = 0; v < 4; ++v)
+          u[c][v] = Zt[(16 * wave + blk::BlkMfma<T>::row(lk, v)) + (long long)(16 * c + li) * ld];
+    }
   }
+  stage_block(stage, vz);
+  if (upd) stage_block(Pl, vp);
   __syncthreads();
+  if (upd) {
+    // Z_kk -= P^T P with P = R(k-1, k) (the ten tiles on and above the diagonal, dealt
+    // round-robin over the four waves; every LDS element is updated by one lane) and
+    // Z(k, tile) -= P^T R(k-1, tile)
+    int n = 0;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = ti; tj < 4; ++tj, ++n)
+        if ((n & 3) == wave) sub_ptq(stage, Pl, Pl, ti, tj);
+    if (tile) {
+      if constexpr (kWide) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sub_ptq(lds + kUt, Pl, lds + kQt, wave, c);
+      } else {
+        const T* Qg = Zt - NB;   // R(k-1, tile) from memory as the B operand
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          Acc acc = {0, 0, 0, 0};
+          const T* Qc = Qg + (long long)(16 * c + li) * ld + lk;
+#pragma unroll
+          for (int k = 0; k < NB; k += 4)
+            acc = blk::BlkMfma<T>::step(Pl[(k + lk) * blk::kLdS + 16 * wave + li], Qc[k], acc);
+          u[c] -= acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
   // The other workgroups of this matrix may still be reading the diagonal block, so
   // tile 0 leaves it untouched: R_kk goes to the (unused, zero) block below W_kk and
   // moves into place in the next step's launch, which also clears that block; the last
   // step (a single workgroup) writes it directly.
-  if (t == 0 && k0 > 0) {
+  if (t == 0 && upd) {
     T* src = W - (long long)NB * ld;              // block (k, k-1) of W
     T* dst = Z - NB - (long long)NB * ld;         // block (k-1, k-1) of Z
     for (int e = threadIdx.x; e < NB * NB; e += NTD) {
@@ -62,25 +155,22 @@ __device__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long 
       src[o] = T(0);
     }
   }
-  blk::factor_invert_block(lds, rest > 0 ? W + NB : Z, W, ld, info, b < 30 ? b : 30, t == 0);
-  if (rest <= 0) return;
-  // panel tile t: rows k0.., columns k0 + 64 + 64t.., staged where R was
-  T* Zt = Z + (long long)(NB + NB * t) * ld;
+  blk::factor_invert_block(lds, tile ? W + NB : Z, W, ld, info, b < 30 ? b : 30, t == 0);
+  if (!tile) return;
+  // wave w forms rows 16w.. of R_kk^{-T} Z(k, tile), four 16-column tiles (narrow: the
+  // updated panel tile first goes into the staging area, free again)
+  const T* St = stage;
+  if constexpr (kWide) {
+    St = lds + kUt;
+  } else {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + q * NTD;
-    val[q] = Zt[e % NB + (long long)(e / NB) * ld];
-  }
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + q * NTD;
-    lds[blk::kStage + (e % NB) * blk::kLdS + e / NB] = val[q];
+      for (int v = 0; v < 4; ++v)
+        stage[(16 * wave + blk::BlkMfma<T>::row(lk, v)) * blk::kLdS + 16 * c + li] = u[c][v];
+    __syncthreads();
   }
-  __syncthreads();
-  // wave w: rows 16w.. of the tile, four 16-column tiles, P = W_kk^T Z_tile
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
   const T* Wl = lds + blk::kWl;
-  const T* St = lds + blk::kStage;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const auto acc = blk::tile_mm_ta(Wl + 16 * wave, blk::kLdS, St + 16 * c, blk::kLdS, NB);
@@ -92,17 +182,25 @@ __device__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long 
 
 // One launch of the factorization: workgroups below ndiag run diag_panel for the block
 // at k0; the others are tiles of the trailing update `tp` that the step before k0 still
-// owes to the rows below block row k0 (look-ahead: the row block at k0 was updated
-// first, by a launch of its own, so its diagonal block and panel need not wait for the
-// whole trailing update).  The two roles touch disjoint parts of Z.
-template <class T>
-__global__ __launch_bounds__(NTD) void chol_step_kernel(T* z, long long sz, T* w, long long sw,
+// owes to the rows below block row k0 (look-ahead: block row k0 takes that update
+// inside diag_panel, so its diagonal block and panel need not wait for the whole
+// trailing update).  The two roles touch disjoint parts of Z.
+// Waves per SIMD the LDS of a variant allows (the register budget follows from it).
+template <class T, bool kWide>
+constexpr int step_waves() {
+  return sizeof(T) == 8 ? (kWide ? 1 : 2) : (kWide ? 2 : 3);
+}
+
+template <class T, bool kWide>
+__global__ __launch_bounds__(NTD)
+__attribute__((amdgpu_waves_per_eu(step_waves<T, kWide>()))) void chol_step_kernel(T* z, long long sz, T* w, long long sw,
                                                         int ld, int k0, int rest, int ntiles,
                                                         int* info, GemmProblemT<T> tp, int ndiag) {
   constexpr int kAB = 2 * GemmLds<64, 64>::ASZ + 2 * GemmLds<64, 64>::BSZ;
-  __shared__ T lds[blk::kLdsElems > kAB ? blk::kLdsElems : kAB];
+  constexpr int kElems = kWide ? kWideElems : blk::kLdsElems;
+  __shared__ T lds[kElems > kAB ? kElems : kAB];
   if ((int)blockIdx.x < ndiag)
-    diag_panel(lds, blockIdx.x, z, sz, w, sw, ld, k0, rest, ntiles, info);
+    diag_panel<T, kWide>(lds, blockIdx.x, z, sz, w, sw, ld, k0, rest, ntiles, info);
   else
     gemm_tile<T, 64, 64, 2, 2, 1, 0>(tp, blockIdx.x - ndiag, lds);
 }
@@ -112,17 +210,28 @@ inline void gemm_t(hipStream_t s, const GemmProblemF* p, int n) { gemm_f32(s, p,
 
 template <class T>
 void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, int batch,
-                 int* info, bool inverse = true) {
-  zero_lower(s, w, mp, sw, batch);  // the diagonal blocks and W12 blocks cover the rest
+                 int* info, bool inverse, LaunchList* defer) {
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
+  // every launch goes through issue (closures own copies of their arguments)
+  auto issue = [defer](std::function<void()> f) {
+    if (defer)
+      defer->push_back(std::move(f));
+    else
+      f();
+  };
+  // the diagonal blocks and W12 blocks cover the rest
+  issue([=] { zero_lower(s, w, mp, sw, batch); });
+  // one or two matrices: the chain of diagonal blocks bounds the time (wide step
+  // kernel); more: the trailing updates do (narrow, twice the occupancy)
+  const bool wide = batch <= kWideBatch;
   const int nbk = mp / NB;
   // ---- blocked right-looking Cholesky with a look-ahead of one block row:
   //   C_0 = diagonal block and panel of block row 0;
-  //   for k = 0, 1, ...:  A_k = update of block row k+1 by panel k (one small GEMM);
-  //                       C_{k+1} = diagonal block and panel of block row k+1, together
-  //                       with the update by panel k of the rows below block row k+1.
-  // Per step the chain waits for A_k and C_{k+1}; the bulk of the trailing update runs
-  // beside the next diagonal factorization instead of before it.
+  //   for k = 0, 1, ...:  C_{k+1} = update of block row k+1 by panel k, its diagonal
+  //                       block and panel (in the diagonal workgroups), together with
+  //                       the update by panel k of the rows below block row k+1.
+  // One launch per step; the bulk of the trailing update runs beside the next diagonal
+  // factorization instead of before it.
   auto step = [&](int k0, const GemmProblemT<T>* tp) {
     const int rest = mp - k0 - NB;
     const int nt = rest > 0 ? rest / NB : 1;
@@ -138,9 +247,15 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
       t.tile_begin = 0;
       ntrail = t.tiles * batch;
     }
-    hipLaunchKernelGGL(chol_step_kernel<T>, dim3(ndiag + ntrail), dim3(NTD), 0, s, z, sz, w, sw,
-                       mp, k0, rest, nt, info, t, ndiag);
-    PS_HIP(hipGetLastError());
+    issue([=] {
+      if (wide)
+        hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(ndiag + ntrail), dim3(NTD), 0, s, z,
+                           sz, w, sw, mp, k0, rest, nt, info, t, ndiag);
+      else
+        hipLaunchKernelGGL((chol_step_kernel<T, false>), dim3(ndiag + ntrail), dim3(NTD), 0, s,
+                           z, sz, w, sw, mp, k0, rest, nt, info, t, ndiag);
+      PS_HIP(hipGetLastError());
+    });
   };
   step(0, nullptr);
   for (int k = 0; k + 1 < nbk; ++k) {
@@ -148,14 +263,6 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     const int rest = mp - k0 - NB;   // > 0
     T* zr = z + k0 + (long long)(k0 + NB) * mp;          // R(k, k+1:)
     T* zn = z + (k0 + NB) + (long long)(k0 + NB) * mp;   // Z(k+1, k+1:)
-    // A_k: Z(k+1, k+1:) -= R(k, k+1)^T R(k, k+1:)
-    GemmProblemT<T> pa = gemm_problem(NB, rest, NB, zr, mp, 1, zr, mp, 0, zn, mp, -1.0, 1.0, zn, mp, 0);
-    pa.nb1 = batch;
-    pa.sA[0] = sz;
-    pa.sB[0] = sz;
-    pa.sC[0] = sz;
-    pa.sD[0] = sz;
-    gemm_t(s, &pa, 1);
     // C_{k+1} with the rest of the trailing update of step k:
     // Z(k+2:, k+2:) -= R(k, k+2:)^T R(k, k+2:)  (upper triangle)
     if (rest > NB) {
@@ -212,23 +319,35 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     if (full > 0) add_pair(0, S, full);
     if (rem > S) add_pair((long long)full * pstride, rem - S, 1);
     if (n1) {
-      gemm_t(s, t1, n1);
-      gemm_t(s, t2, n1);
-      for (int q = 0; q < n1; ++q)
-        zero_block(s, const_cast<T*>(t2[q].B), t2[q].N, t2[q].K, mp, batch, sw, t2[q].nb2,
-                   pstride);
+      issue([=] { gemm_t(s, t1, n1); });
+      issue([=] { gemm_t(s, t2, n1); });
+      for (int q = 0; q < n1; ++q) {
+        const GemmProblemT<T> u = t2[q];
+        issue([=] { zero_block(s, const_cast<T*>(u.B), u.N, u.K, mp, batch, sw, u.nb2, pstride); });
+      }
     }
   }
 }
 
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
-                   double* /*tmp*/, int mp, int batch, int* info, bool inverse) {
-  potrf_inv_t(s, z, sz, w, sw, mp, batch, info, inverse);
+                   double* /*tmp*/, int mp, int batch, int* info, bool inverse,
+                   LaunchList* defer) {
+  potrf_inv_t(s, z, sz, w, sw, mp, batch, info, inverse, defer);
 }
 
 void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,
-                   int batch, int* info) {
-  potrf_inv_t(s, z, sz, w, sw, mp, batch, info);
+                   int batch, int* info, LaunchList* defer) {
+  potrf_inv_t(s, z, sz, w, sw, mp, batch, info, true, defer);
+}
+
+void issue_interleaved(LaunchList& a, LaunchList& b) {
+  const size_t n = std::max(a.size(), b.size());
+  for (size_t i = 0; i < n; ++i) {
+    if (i < a.size()) a[i]();
+    if (i < b.size()) b[i]();
+  }
+  a.clear();
+  b.clear();
 }
 
 }  // namespace ps

@@ -393,18 +393,36 @@ void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned) {
   PS_HIP(hipGetLastError());
 }
 
-// y_b[j] = sum_i M_b(i, j) x_b[i]: one wave per column
+// y_b[j] = sum_i M_b(i, j) x_b[i]: one wave per column.  Each lane takes 16-byte pairs
+// of the column and of x, eight pairs per round with all sixteen loads issued before
+// the first multiply, so a wave keeps 8 KB of the column in flight instead of one
+// dependent load per iteration (mp is a multiple of 64, the buffers 16-byte aligned).
 __global__ void coldots_kernel(const double* mat, long long mstride, const double* x,
                                long long xstride, double* y, long long ystride, int mp) {
+  constexpr int U = 8;
   const int b = blockIdx.y;
   const int col = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (col >= mp) return;
-  const double* Mc = mat + b * mstride + (size_t)col * mp;
-  const double* X = x + b * xstride;
-  double acc = 0.0;
-  for (int i = lane; i < mp; i += 64) acc += Mc[i] * X[i];
-  acc = warp_sum(acc);
+  const double2* Mc = reinterpret_cast<const double2*>(mat + b * mstride + (size_t)col * mp);
+  const double2* X = reinterpret_cast<const double2*>(x + b * xstride);
+  const int n2 = mp / 2;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int base = 0; base < n2; base += 64 * U) {
+    double2 a[U], v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + lane + 64 * u;
+      a[u] = i < n2 ? Mc[i] : double2{0.0, 0.0};
+      v[u] = i < n2 ? X[i] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc0 += a[u].x * v[u].x;
+      acc1 += a[u].y * v[u].y;
+    }
+  }
+  const double acc = warp_sum(acc0 + acc1);
   if (lane == 0) y[b * ystride + col] = acc;
 }
 

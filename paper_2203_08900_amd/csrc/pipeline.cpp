@@ -431,12 +431,22 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
     }
   }
   *n64_out = n64;
+  // the two groups' factorizations are latency-bound chains of launches: record both and
+  // issue them alternately, so that neither waits for the host to enqueue the other
+  LaunchList chain32, chain64;
+  hipStream_t s2 = mx.side;
   if (n32 > 0) {
     PS_HIP(hipEventRecord(mx.fork, s));
-    PS_HIP(hipStreamWaitEvent(mx.side, mx.fork, 0));
-    hipStream_t s2 = mx.side;
+    PS_HIP(hipStreamWaitEvent(s2, mx.fork, 0));
     form_shifts_f32(s2, b.g, b.z32, mp, c32, n32);
-    potrf_inv_f32(s2, b.z32, S, b.w32, S, mp, n32, dinfo32);
+    potrf_inv_f32(s2, b.z32, S, b.w32, S, mp, n32, dinfo32, &chain32);
+  }
+  if (n64 > 0) {
+    form_shifts_v(s, b.g, b.z, mp, c64, n64);
+    potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, n64, dinfo64, true, &chain64);
+  }
+  issue_interleaved(chain32, chain64);
+  if (n32 > 0) {
     GemmProblemF pn = gemm_problem(mp, mp, n32 * mp, b.w32, mp, 0, b.w32, mp, 1, b.n32, mp, 1.0,
                                    0.0, nullptr, 0, kAUpper | kBLower | kOutUpper | kMirror);
     pn.kseg = mp;
@@ -450,8 +460,6 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
     PS_HIP(hipEventRecord(mx.join, s2));
   }
   if (n64 > 0) {
-    form_shifts_v(s, b.g, b.z, mp, c64, n64);
-    potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, n64, dinfo64);
     GemmProblem pn = gemm_problem(mp, mp, n64 * mp, b.w, mp, 0, b.w, mp, 1, b.nmat, mp, 1.0, 0.0,
                                   nullptr, 0, kAUpper | kBLower | kOutUpper | kMirror);
     pn.kseg = mp;

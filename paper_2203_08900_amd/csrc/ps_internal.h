@@ -13,7 +13,9 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "zolo_host.h"
 
@@ -108,16 +110,24 @@ void gemm_f32(hipStream_t s, const GemmProblemF* probs, int count);
 inline void gemm_f32(hipStream_t s, const GemmProblemF& p) { gemm_f32(s, &p, 1); }
 
 // ----------------------------------------------------------------- Cholesky
+// Kernel launches recorded for later issue (each closure enqueues on its own stream).
+using LaunchList = std::vector<std::function<void()>>;
+// Issue two recorded launch sequences alternately, one launch of each in turn, so that
+// two independent chains on different streams both start at once whatever the host's
+// launch rate.
+void issue_interleaved(LaunchList& a, LaunchList& b);
+
 // In-place upper Cholesky Z = R^T R of `batch` SPD matrices (mp x mp, ld = mp,
 // matrix stride sz) with the strictly lower part zero on entry, producing the
-// inverse factor W = R^{-1} (upper) in `w` (stride sw).  `tmp` holds
-// batch * mp * kNb doubles.  A non-positive pivot in matrix b sets bit min(b, 30) of
-// the device int *info.
+// inverse factor W = R^{-1} (upper) in `w` (stride sw).  `tmp` is unused.  A
+// non-positive pivot in matrix b sets bit min(b, 30) of the device int *info.  With
+// `defer`, the launches are appended there instead of issued.
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
-                   double* tmp, int mp, int batch, int* info, bool inverse = true);
+                   double* tmp, int mp, int batch, int* info, bool inverse = true,
+                   LaunchList* defer = nullptr);
 // the same in FP32 (pivots taken and inverted through FP64 square roots)
 void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,
-                   int batch, int* info);
+                   int batch, int* info, LaunchList* defer = nullptr);
 
 // ----------------------------------------------------------------- elementwise
 void pack_casida(hipStream_t s, int m, int mp, const double* A, int lda, const double* B,
