@@ -20,6 +20,8 @@ namespace {
 constexpr int NB = kNb;
 constexpr int NTD = 256;
 constexpr int kWideBatch = 2;
+constexpr int kOuter = 512;      // outer block of the large factorizations
+constexpr int kOuterMin = 4096;  // padded sizes from which they are used
 }
 
 // LDS of a step in the wide variant: the block layout, then R(k-1, tile) and the panel
@@ -75,14 +77,15 @@ __device__ inline void sub_ptq(T* D, const T* P, const T* Q, int ti, int tj) {
 // the panel product (the block layout alone, two FP64 workgroups per compute unit), so
 // that the trailing-update tiles of many matrices run at twice the occupancy.
 template <class T, bool kWide>
-__device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long sw, int ld, int k0,
-                           int rest, int ntiles, int* info) {
+__device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, T* w, long long sw,
+                                           int ld, int k0, int rest, int ntiles, int fold,
+                                           int* info) {
   using Acc = typename blk::BlkMfma<T>::acc_t;
   const int b = bid / ntiles, t = bid - b * ntiles;
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
   T* Zt = Z + (long long)(NB + NB * t) * ld;   // panel tile t: columns k0 + 64 + 64t..
-  const bool upd = k0 > 0;                     // block row k still owes panel k-1's update
+  const bool upd = fold != 0;                  // block row k still owes panel k-1's update
   const bool tile = rest > 0;
   T* const stage = lds + blk::kStage;
   T* const Pl = lds + blk::kWl;   // R(k-1, k) until the factorization takes the area
@@ -146,7 +149,7 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
   // tile 0 leaves it untouched: R_kk goes to the (unused, zero) block below W_kk and
   // moves into place in the next step's launch, which also clears that block; the last
   // step (a single workgroup) writes it directly.
-  if (t == 0 && upd) {
+  if (t == 0 && k0 > 0) {
     T* src = W - (long long)NB * ld;              // block (k, k-1) of W
     T* dst = Z - NB - (long long)NB * ld;         // block (k-1, k-1) of Z
     for (int e = threadIdx.x; e < NB * NB; e += NTD) {
@@ -181,10 +184,11 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
 }
 
 // One launch of the factorization: workgroups below ndiag run diag_panel for the block
-// at k0; the others are tiles of the trailing update `tp` that the step before k0 still
-// owes to the rows below block row k0 (look-ahead: block row k0 takes that update
-// inside diag_panel, so its diagonal block and panel need not wait for the whole
-// trailing update).  The two roles touch disjoint parts of Z.
+// at k0 (with the previous panel's update of block row k0 when fold is set); the others
+// are tiles of the trailing update, `tp` then `tq` (np tiles of tp), that the step
+// before k0 still owes to the rows below block row k0 (look-ahead: block row k0 takes
+// that update inside diag_panel, so its diagonal block and panel need not wait for the
+// whole trailing update).  The two roles touch disjoint parts of Z.
 // Waves per SIMD the LDS of a variant allows (the register budget follows from it).
 template <class T, bool kWide>
 constexpr int step_waves() {
@@ -193,16 +197,19 @@ constexpr int step_waves() {
 
 template <class T, bool kWide>
 __global__ __launch_bounds__(NTD)
-__attribute__((amdgpu_waves_per_eu(step_waves<T, kWide>()))) void chol_step_kernel(T* z, long long sz, T* w, long long sw,
-                                                        int ld, int k0, int rest, int ntiles,
-                                                        int* info, GemmProblemT<T> tp, int ndiag) {
+__attribute__((amdgpu_waves_per_eu(step_waves<T, kWide>()))) void chol_step_kernel(
+    T* z, long long sz, T* w, long long sw, int ld, int k0, int rest, int ntiles, int fold,
+    int* info, GemmProblemT<T> tp, GemmProblemT<T> tq, int ndiag, int np) {
   constexpr int kAB = 2 * GemmLds<64, 64>::ASZ + 2 * GemmLds<64, 64>::BSZ;
   constexpr int kElems = kWide ? kWideElems : blk::kLdsElems;
   __shared__ T lds[kElems > kAB ? kElems : kAB];
-  if ((int)blockIdx.x < ndiag)
-    diag_panel<T, kWide>(lds, blockIdx.x, z, sz, w, sw, ld, k0, rest, ntiles, info);
+  const int bid = blockIdx.x;
+  if (bid < ndiag)
+    diag_panel<T, kWide>(lds, bid, z, sz, w, sw, ld, k0, rest, ntiles, fold, info);
+  else if (bid < ndiag + np)
+    gemm_tile<T, 64, 64, 2, 2, 1, 0>(tp, bid - ndiag, lds);
   else
-    gemm_tile<T, 64, 64, 2, 2, 1, 0>(tp, blockIdx.x - ndiag, lds);
+    gemm_tile<T, 64, 64, 2, 2, 1, 0>(tq, bid - ndiag - np, lds);
 }
 
 inline void gemm_t(hipStream_t s, const GemmProblem* p, int n) { gemm_f64(s, p, n); }
@@ -224,7 +231,6 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   // one or two matrices: the chain of diagonal blocks bounds the time (wide step
   // kernel); more: the trailing updates do (narrow, twice the occupancy)
   const bool wide = batch <= kWideBatch;
-  const int nbk = mp / NB;
   // ---- blocked right-looking Cholesky with a look-ahead of one block row:
   //   C_0 = diagonal block and panel of block row 0;
   //   for k = 0, 1, ...:  C_{k+1} = update of block row k+1 by panel k, its diagonal
@@ -232,52 +238,77 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   //                       the update by panel k of the rows below block row k+1.
   // One launch per step; the bulk of the trailing update runs beside the next diagonal
   // factorization instead of before it.
-  auto step = [&](int k0, const GemmProblemT<T>* tp) {
+  // Large matrices (mp >= kOuterMin) go by outer blocks of kOuter rows: the steps above
+  // run inside an outer block only (their trailing updates stop at its last row), and
+  // the rows below it then take the update by all of its panels at once, one GEMM with
+  // K = kOuter on the large tiles instead of kOuter / 64 memory-bound updates with K = 64.
+  const int outer = mp >= kOuterMin ? kOuter : mp;
+  // trailing problem of one launch: panel row `pr` applied to rows and columns
+  // [r0, r1) (upper triangle) and to rows [r0, r1) x columns [r1, mp)
+  auto trailing = [&](int pr, int r0, int r1, GemmProblemT<T>* out) {
+    int n = 0;
+    if (r1 <= r0) return n;
+    const T* a = z + pr + (long long)r0 * mp;   // R(pr, r0:)
+    GemmProblemT<T> q = gemm_problem(r1 - r0, r1 - r0, NB, a, mp, 1, a, mp, 0,
+                                     z + r0 + (long long)r0 * mp, mp, -1.0, 1.0,
+                                     z + r0 + (long long)r0 * mp, mp, kOutUpper);
+    out[n++] = q;
+    if (r1 < mp) {
+      const T* bq = z + pr + (long long)r1 * mp;   // R(pr, r1:)
+      out[n++] = gemm_problem(r1 - r0, mp - r1, NB, a, mp, 1, bq, mp, 0,
+                              z + r0 + (long long)r1 * mp, mp, -1.0, 1.0,
+                              z + r0 + (long long)r1 * mp, mp, 0);
+    }
+    return n;
+  };
+  auto step = [&](int k0, int fold, const GemmProblemT<T>* tp, int ntp) {
     const int rest = mp - k0 - NB;
     const int nt = rest > 0 ? rest / NB : 1;
     const int ndiag = batch * nt;
-    GemmProblemT<T> t{};
-    int ntrail = 0;
-    if (tp) {
-      t = *tp;
-      t.tm = t.M / 64;
-      t.tn = t.N / 64;
-      t.tiles = t.tm * (t.tm + 1) / 2;   // upper-triangular output
-      t.tiles_per_batch = t.tiles;
-      t.tile_begin = 0;
-      ntrail = t.tiles * batch;
+    GemmProblemT<T> t[2] = {};
+    int cnt[2] = {0, 0};
+    for (int q = 0; q < ntp; ++q) {
+      t[q] = tp[q];
+      t[q].nb1 = batch;
+      t[q].sA[0] = t[q].sB[0] = t[q].sC[0] = t[q].sD[0] = sz;
+      t[q].tm = t[q].M / 64;
+      t[q].tn = t[q].N / 64;
+      t[q].tiles = (t[q].flags & kOutUpper) ? t[q].tm * (t[q].tm + 1) / 2 : t[q].tm * t[q].tn;
+      t[q].tiles_per_batch = t[q].tiles;
+      t[q].tile_begin = 0;
+      cnt[q] = t[q].tiles * batch;
     }
+    const GemmProblemT<T> t0 = t[0], t1 = t[1];
+    const int np = cnt[0], grid = ndiag + cnt[0] + cnt[1];
     issue([=] {
       if (wide)
-        hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(ndiag + ntrail), dim3(NTD), 0, s, z,
-                           sz, w, sw, mp, k0, rest, nt, info, t, ndiag);
+        hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(grid), dim3(NTD), 0, s, z, sz, w, sw,
+                           mp, k0, rest, nt, fold, info, t0, t1, ndiag, np);
       else
-        hipLaunchKernelGGL((chol_step_kernel<T, false>), dim3(ndiag + ntrail), dim3(NTD), 0, s,
-                           z, sz, w, sw, mp, k0, rest, nt, info, t, ndiag);
+        hipLaunchKernelGGL((chol_step_kernel<T, false>), dim3(grid), dim3(NTD), 0, s, z, sz, w,
+                           sw, mp, k0, rest, nt, fold, info, t0, t1, ndiag, np);
       PS_HIP(hipGetLastError());
     });
   };
-  step(0, nullptr);
-  for (int k = 0; k + 1 < nbk; ++k) {
-    const int k0 = k * NB;
-    const int rest = mp - k0 - NB;   // > 0
-    T* zr = z + k0 + (long long)(k0 + NB) * mp;          // R(k, k+1:)
-    T* zn = z + (k0 + NB) + (long long)(k0 + NB) * mp;   // Z(k+1, k+1:)
-    // C_{k+1} with the rest of the trailing update of step k:
-    // Z(k+2:, k+2:) -= R(k, k+2:)^T R(k, k+2:)  (upper triangle)
-    if (rest > NB) {
-      T* zr2 = zr + (long long)NB * mp;
-      T* zt2 = zn + NB + (long long)NB * mp;
-      GemmProblemT<T> pt = gemm_problem(rest - NB, rest - NB, NB, zr2, mp, 1, zr2, mp, 0, zt2, mp,
-                                        -1.0, 1.0, zt2, mp, kOutUpper);
-      pt.nb1 = batch;
-      pt.sA[0] = sz;
-      pt.sB[0] = sz;
-      pt.sC[0] = sz;
-      pt.sD[0] = sz;
-      step(k0 + NB, &pt);
-    } else {
-      step(k0 + NB, nullptr);
+  for (int ob = 0; ob < mp; ob += outer) {
+    const int obe = std::min(mp, ob + outer);
+    for (int k0 = ob; k0 < obe; k0 += NB) {
+      // the launch for block k0 carries the previous panel's update of the rows below
+      // block row k0 + 1 within this outer block (none for the outer block's first
+      // block: its rows took every earlier panel in the outer update)
+      GemmProblemT<T> tp[2];
+      const int ntp = k0 > ob ? trailing(k0 - NB, k0 + NB, obe, tp) : 0;
+      step(k0, k0 > ob ? 1 : 0, tp, ntp);
+    }
+    if (obe < mp) {
+      // rows and columns [obe, mp) -= R(ob:obe, obe:)^T R(ob:obe, obe:)  (upper triangle)
+      const T* a = z + ob + (long long)obe * mp;
+      GemmProblemT<T> pu = gemm_problem(mp - obe, mp - obe, obe - ob, a, mp, 1, a, mp, 0,
+                                        z + obe + (long long)obe * mp, mp, -1.0, 1.0,
+                                        z + obe + (long long)obe * mp, mp, kOutUpper);
+      pu.nb1 = batch;
+      pu.sA[0] = pu.sB[0] = pu.sC[0] = pu.sD[0] = sz;
+      issue([=] { gemm_t(s, &pu, 1); });
     }
   }
   if (!inverse) return;   // W then holds only the inverted diagonal blocks
