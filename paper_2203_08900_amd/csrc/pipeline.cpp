@@ -382,8 +382,9 @@ void zolo_step_series(hipStream_t s, Buffers& b, const double* x, double* xn, co
   } else {
     axpb_identity(s, b.g, T, gam[P - 1], (P - 2 == 0 ? 1.0 + gam[0] : gam[P - 2]), mp);
     for (int q = P - 3; q >= 0; --q) {
+      // Delta and T are symmetric and commute, so Delta T is symmetric: upper tiles only
       GemmProblem ph = gemm_problem(mp, mp, mp, b.g, mp, 0, T, mp, 0, T2, mp, 1.0, 0.0, nullptr,
-                                    0, 0);
+                                    0, kOutUpper | kMirror);
       auto_split(ph, b.splitws);
       gemm_f64(s, ph);
       axpb_identity(s, T2, T, 1.0, q == 0 ? 1.0 + gam[0] : gam[q], mp);
@@ -505,11 +506,13 @@ void zolo_step_series_mixed(hipStream_t s, Buffers& b, const double* x, double* 
   axpb_identity_f32(s, b.d32, inner, P >= 3 ? (float)gam[P - 1] : 0.0f,
                     (float)(P >= 3 ? gam[P - 2] : gam[1]), mp);
   for (int q = P - 3; q >= 1; --q) {
-    GemmProblemF ph = gemm_problem(mp, mp, mp, b.d32, mp, 0, inner, mp, 0, tmp, mp);
+    GemmProblemF ph = gemm_problem(mp, mp, mp, b.d32, mp, 0, inner, mp, 0, tmp, mp, 1.0, 0.0,
+                                   nullptr, 0, kOutUpper | kMirror);   // symmetric, as above
     gemm_f32(s, ph);
     axpb_identity_f32(s, tmp, inner, 1.0f, (float)gam[q], mp);
   }
-  GemmProblemF pt = gemm_problem(mp, mp, mp, b.d32, mp, 0, inner, mp, 0, tmp, mp);
+  GemmProblemF pt = gemm_problem(mp, mp, mp, b.d32, mp, 0, inner, mp, 0, tmp, mp, 1.0, 0.0,
+                                 nullptr, 0, kOutUpper | kMirror);
   gemm_f32(s, pt);
   GemmProblemF py = gemm_problem(mp, mp, mp, b.x32, mp, 0, tmp, mp, 0, b.y32, mp);
   gemm_f32(s, py);
@@ -1590,7 +1593,9 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
     } else {
       axpb_identity_b(s, c.g, T, d_h(P - 1), d_h(P - 2), mp, nb);
       for (int q = P - 3; q >= 0; --q) {
-        GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.g, mp, 0, T, mp, 0, T2, mp), S, S, S);
+        GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.g, mp, 0, T, mp, 0, T2, mp, 1.0, 0.0,
+                                              nullptr, 0, kOutUpper | kMirror),
+                                 S, S, S);   // symmetric (Delta and T commute)
         gemm_f64(s, ph);
         axpb_identity_b(s, T2, T, d_one, d_h(q), mp, nb);
       }
