@@ -235,7 +235,19 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
                 p.ksplit * p.nb1 * p.nb2;
   }
   if (!live) return;
-  if (big && tiles128 >= 256)
+  // triangular operands with a full output: the K extents of the tiles differ by up to
+  // the whole K, and while there are few large tiles per compute unit one with the
+  // longest K bounds the launch; small tiles spread that work four times finer.  Two
+  // triangular operands (K from max(i0, j0), or up to min) skew it most.
+  int skew = 0;
+  for (int q = 0; q < count; ++q) {
+    const int f = probs[q].flags;
+    if (f & (kOutUpper | kOutLower)) continue;
+    const int na = (f & (kAUpper | kALower)) ? 1 : 0, nb = (f & (kBUpper | kBLower)) ? 1 : 0;
+    skew = std::max(skew, na + nb);
+  }
+  const long long skew_max = skew == 2 ? 2048 : (skew == 1 ? 512 : 0);
+  if (big && tiles128 >= 256 && tiles128 >= skew_max)
     launch_group<T, 128, 128, 4, 4>(s, probs, count);
   else
     launch_group<T, 64, 64, 2, 2>(s, probs, count);
