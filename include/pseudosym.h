@@ -202,12 +202,13 @@ int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B,
  * are HOST arrays of length batch holding device pointers.  The problems run largest
  * first on six worker streams owned by the handle (each with its own library-owned
  * workspace; ps_set_workspace does not apply to them); the call returns when all are
- * done.  With the core basis (FP64, or mixed below its size threshold), problems of one
- * padded size (m rounded up to 64) run together, up to 32 per batched pipeline (fewer
- * where their workspace would pass 3 GiB): their
- * results agree with single calls to rounding (the sums are split differently), not bit
- * for bit; other problems run the single-problem pipeline and match it exactly.  infos (host, length batch, may be NULL) receives one record per problem;
- * the return value is 0 or the status of the first failing problem in index order.
+ * done.  In FP64 (or mixed below its size threshold), problems of one padded size (m
+ * rounded up to 64) run together, with either basis, up to 32 per batched pipeline
+ * (fewer where their workspace would pass 3 GiB): their results agree with single calls
+ * to rounding (the sums are split differently), not bit for bit; other problems run the
+ * single-problem pipeline and match it exactly.  infos (host, length batch, may be NULL)
+ * receives one record per problem; the return value is 0 or the status of the first
+ * failing problem in index order.
  * Argument errors: -k as usual (k = 3..11 also when entry i of that array is invalid). */
 int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double* const* A,
                              const int* lda, const double* const* B, const int* ldb,

@@ -158,4 +158,86 @@ void gk_init_b(hipStream_t s, double* v, const int* m_dev, int mp, int count, in
   PS_HIP(hipGetLastError());
 }
 
+// Alg. 6 tail of a class, one launch per kernel over all its problems (stride mp^2; the
+// same element-wise arithmetic as the single-problem kernels).
+// A_s = sym(S21 + S12) / 2, B_s = sym(S21 - S12) / 2
+__global__ void sign_blocks_b_kernel(const double* s12, const double* s21, double* as, double* bs,
+                                     int mp) {
+  const size_t n = (size_t)mp * mp, off = blockIdx.y * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    const size_t et = j + (size_t)i * mp;
+    const double p = 0.5 * (s12[off + e] + s12[off + et]);
+    const double q = 0.5 * (s21[off + e] + s21[off + et]);
+    as[off + e] = 0.5 * (q + p);
+    bs[off + e] = 0.5 * (q - p);
+  }
+}
+
+void sign_blocks_b(hipStream_t s, const double* s12, const double* s21, double* as, double* bs,
+                   int mp, int nb) {
+  hipLaunchKernelGGL(sign_blocks_b_kernel, dim3(blocks_for((size_t)mp * mp), nb), dim3(NT), 0, s,
+                     s12, s21, as, bs, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// p11 = upper((I + A_s) / 2), strictly lower part zero
+__global__ void half_shift_upper_b_kernel(const double* as, double* p11, int mp) {
+  const size_t n = (size_t)mp * mp, off = blockIdx.y * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    p11[off + e] = (i < j) ? 0.5 * as[off + e] : ((i == j) ? 0.5 * (1.0 + as[off + e]) : 0.0);
+  }
+}
+
+void half_shift_upper_b(hipStream_t s, const double* as, double* p11, int mp, int nb) {
+  hipLaunchKernelGGL(half_shift_upper_b_kernel, dim3(blocks_for((size_t)mp * mp), nb), dim3(NT), 0,
+                     s, as, p11, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// top = C^T;  ab_b = [(top + qbot), (top - qbot)] / sqrt 2  (ab stride 2 mp^2)
+__global__ void basis_mix_b_kernel(const double* c, const double* qbot, double* top_out,
+                                   double* ab, int mp) {
+  const size_t n = (size_t)mp * mp, off = blockIdx.y * n;
+  double* AB = ab + 2 * off;
+  const double h = 0.70710678118654752440;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    const double tv = (i >= j) ? c[off + j + (size_t)i * mp] : 0.0;
+    const double bv = qbot[off + e];
+    top_out[off + e] = tv;
+    AB[e] = h * (tv + bv);
+    AB[n + e] = h * (tv - bv);
+  }
+}
+
+void basis_mix_b(hipStream_t s, const double* c, const double* qbot, double* top_out, double* ab,
+                 int mp, int nb) {
+  hipLaunchKernelGGL(basis_mix_b_kernel, dim3(blocks_for((size_t)mp * mp), nb), dim3(NT), 0, s, c,
+                     qbot, top_out, ab, mp);
+  PS_HIP(hipGetLastError());
+}
+
+// zero rows and columns >= m of matrix q (stride mp^2), m = m_dev[q / per]
+__global__ void mask_pad_b_kernel(double* x, const int* m_dev, int mp, int per) {
+  const size_t n = (size_t)mp * mp;
+  const int q = blockIdx.y, m = m_dev[q / per];
+  double* X = x + q * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    if (i >= m || j >= m) X[e] = 0.0;
+  }
+}
+
+void mask_pad_b(hipStream_t s, double* x, const int* m_dev, int mp, int per, int count) {
+  hipLaunchKernelGGL(mask_pad_b_kernel, dim3(blocks_for((size_t)mp * mp), count), dim3(NT), 0, s,
+                     x, m_dev, mp, per);
+  PS_HIP(hipGetLastError());
+}
+
 }  // namespace ps

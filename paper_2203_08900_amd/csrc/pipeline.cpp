@@ -1617,9 +1617,9 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
     change[b] = std::sqrt(pin[2 * b]) / std::sqrt(pin[2 * b + 1]);
     if (!(change[b] <= tol)) ok[b] = 0;
   }
-  // ---- core basis (a7, a8): Q_+ = Z R_G^{-1}, H_+ = 2 R_G^{-T} R_G^{-1}
   const double* U = c.x2;
-  {
+  if (o.basis == PS_BASIS_CORE) {
+    // ---- core basis (a7, a8): Q_+ = Z R_G^{-1}, H_+ = 2 R_G^{-T} R_G^{-1}
     GemmProblem pt = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, U, mp, 0, c.t1, mp, 1.0, 0.0,
                                           nullptr, 0, kAUpper), 2 * S, S, S);
     gemm_f64(s, pt);
@@ -1641,6 +1641,48 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
     GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.wc, mp, 1, c.wc, mp, 0, c.hp, mp, 2.0, 0.0,
                                           nullptr, 0, kALower | kBUpper | kOutUpper | kMirror),
                              S, S, S);
+    gemm_f64(s, ph);
+  } else {
+    // ---- blocks of sign(H) (a6): S12 = W_M U R_K, S21 = R_M^T U W_K^T (S21 in p11 until
+    // the sign blocks are formed; A_s, B_s in the first matrices of z and w, free since
+    // step 1)
+    double* as = c.z;
+    double* bs = c.w;
+    GemmProblem pg[2];
+    pg[0] = batched(gemm_problem(mp, mp, mp, U, mp, 0, c.mk + S, mp, 0, c.t1, mp, 1.0, 0.0,
+                                 nullptr, 0, kBUpper), S, 2 * S, S);
+    pg[1] = batched(gemm_problem(mp, mp, mp, U, mp, 0, c.wmk + S, mp, 1, c.t2, mp, 1.0, 0.0,
+                                 nullptr, 0, kBLower), S, 2 * S, S);
+    gemm_f64(s, pg, 2);
+    pg[0] = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, c.t1, mp, 0, c.s12, mp, 1.0, 0.0,
+                                 nullptr, 0, kAUpper), 2 * S, S, S);
+    pg[1] = batched(gemm_problem(mp, mp, mp, c.mk, mp, 1, c.t2, mp, 0, c.p11, mp, 1.0, 0.0,
+                                 nullptr, 0, kALower), 2 * S, S, S);
+    gemm_f64(s, pg, 2);
+    sign_blocks_b(s, c.s12, c.p11, as, bs, mp, nb);
+    // ---- Alg. 6 (a7): C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
+    half_shift_upper_b(s, as, c.p11, mp, nb);
+    potrf_inv_f64(s, c.p11, S, c.wc, S, nullptr, mp, nb, c.dinfo + 4);
+    GemmProblem pq = batched(gemm_problem(mp, mp, mp, bs, mp, 0, c.wc, mp, 0, c.qbot, mp, -0.5, 0.0,
+                                          nullptr, 0, kBUpper), S, S, S);
+    gemm_f64(s, pq);
+    mask_pad_b(s, c.qbot, c.mdev, mp, 1, nb);
+    double* ab = c.yt;   // [a_b, b_b] per problem (stride 2 S), free since the estimator
+    basis_mix_b(s, c.p11, c.qbot, c.top, ab, mp, nb);
+    mask_pad_b(s, ab, c.mdev, mp, 2, 2 * nb);
+    // ---- decoupling (a8): H_+ = F^T F, F = [R_M a; R_K b] (2 mp x mp, ld 2 mp; in y)
+    double* F = c.y;
+    GemmProblem pf = gemm_problem(mp, mp, mp, c.mk, mp, 0, ab, mp, 0, F, 2 * mp, 1.0, 0.0, nullptr,
+                                  0, kAUpper);
+    pf.nb1 = 2;
+    pf.sA[0] = pf.sB[0] = S;
+    pf.sC[0] = pf.sD[0] = mp;
+    pf.nb2 = nb;
+    pf.sA[1] = pf.sB[1] = pf.sC[1] = pf.sD[1] = 2 * S;
+    gemm_f64(s, pf);
+    GemmProblem ph = batched(gemm_problem(mp, mp, 2 * mp, F, 2 * mp, 1, F, 2 * mp, 0, c.hp, mp,
+                                          1.0, 0.0, nullptr, 0, kOutUpper | kMirror),
+                             2 * S, 2 * S, S);
     gemm_f64(s, ph);
   }
   PS_HIP(hipMemcpyAsync(pin, c.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1693,11 +1735,11 @@ int run_batched(ps_handle h, int batch, const int* m, const double* const* A, co
   // the inputs may still be in flight on the caller's stream
   PS_HIP(hipEventRecord(h->fork, h->stream));
   for (int k = 0; k < nw; ++k) PS_HIP(hipStreamWaitEvent(h->workers[k]->stream, h->fork, 0));
-  // Jobs, largest first: with the core basis in FP64 arithmetic (mixed requests below
-  // the mixed threshold run in FP64 anyway), problems of one padded size form classes of
+  // Jobs, largest first: in FP64 arithmetic (mixed requests below the mixed threshold
+  // run in FP64 anyway), problems of one padded size form classes of
   // up to kClassMax that run as one batched pipeline; everything else, and what a class
   // hands back, runs one problem at a time.
-  const bool classes = o.basis == PS_BASIS_CORE && o.max_steps != 1 && o.timing == 0 &&
+  const bool classes = o.max_steps != 1 && o.timing == 0 &&
                        (o.precision == PS_PREC_FP64 || o.precision == PS_PREC_MIXED);
   std::vector<std::vector<int>> jobs;
   {

@@ -214,6 +214,15 @@ void axpb_identity_b(hipStream_t s, const double* x, double* y, const double* a,
 void diff_norms_b(hipStream_t s, const double* x1, const double* x2, size_t n, double* out,
                   int nb);
 void gk_init_b(hipStream_t s, double* v, const int* m_dev, int mp, int count, int per);
+// the Alg. 6 tail of a class: the single-problem kernels over nb problems (stride mp^2;
+// ab and its halves stride 2 mp^2); mask_pad_b zeroes rows and columns >= m_dev[q / per]
+// of matrix q for q < count
+void sign_blocks_b(hipStream_t s, const double* s12, const double* s21, double* as, double* bs,
+                   int mp, int nb);
+void half_shift_upper_b(hipStream_t s, const double* as, double* p11, int mp, int nb);
+void basis_mix_b(hipStream_t s, const double* c, const double* qbot, double* top_out, double* ab,
+                 int mp, int nb);
+void mask_pad_b(hipStream_t s, double* x, const int* m_dev, int mp, int per, int count);
 void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
              long long xstride, double* y, long long ystride, int mp, int batch);
 void gk_update(hipStream_t s, const double* p, long long pstride, double* w,
