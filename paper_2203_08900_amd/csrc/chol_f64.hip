@@ -20,6 +20,7 @@ namespace {
 constexpr int NB = kNb;
 constexpr int NTD = 256;
 constexpr int kWideBatch = 2;
+constexpr int kPairedBatch = 8;  // from this many matrices, trailing updates by panel pairs
 constexpr int kOuter = 512;      // outer block of the large factorizations
 constexpr int kOuterMin = 4096;  // padded sizes from which they are used
 }
@@ -85,10 +86,11 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
   T* Z = z + b * sz + k0 + (long long)k0 * ld;
   T* W = w + b * sw + k0 + (long long)k0 * ld;
   T* Zt = Z + (long long)(NB + NB * t) * ld;   // panel tile t: columns k0 + 64 + 64t..
-  const bool upd = fold != 0;                  // block row k still owes panel k-1's update
+  // fold: the previous panels (0, 1 or 2, rows k0 - fold 64 .. k0 - 1) that block row k
+  // still owes
   const bool tile = rest > 0;
   T* const stage = lds + blk::kStage;
-  T* const Pl = lds + blk::kWl;   // R(k-1, k) until the factorization takes the area
+  T* const Pl = lds + blk::kWl;   // a previous panel's block until the factorization
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
   // all loads in flight at once (lower triangles are staged too and ignored where they
   // do not matter); narrow: wave w's row of 16 x 16 tiles of the panel tile goes straight
@@ -96,14 +98,14 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
   constexpr int Q = NB * NB / NTD;
   T vz[Q], vp[Q];
   load_block(Z, ld, vz);
-  if (upd) load_block(Z - NB, ld, vp);
+  if (fold) load_block(Z - fold * NB, ld, vp);
   Acc u[4];
   if constexpr (kWide) {
     T vt[Q], vq[Q];
     if (tile) load_block(Zt, ld, vt);
-    if (upd && tile) load_block(Zt - NB, ld, vq);
+    if (fold && tile) load_block(Zt - fold * NB, ld, vq);
     if (tile) stage_block(lds + kUt, vt);
-    if (upd && tile) stage_block(lds + kQt, vq);
+    if (fold && tile) stage_block(lds + kQt, vq);
   } else {
     if (tile) {
 #pragma unroll
@@ -114,12 +116,26 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
     }
   }
   stage_block(stage, vz);
-  if (upd) stage_block(Pl, vp);
+  if (fold) stage_block(Pl, vp);
   __syncthreads();
-  if (upd) {
-    // Z_kk -= P^T P with P = R(k-1, k) (the ten tiles on and above the diagonal, dealt
+  for (int f = 0; f < fold; ++f) {
+    const int off = (fold - f) * NB;   // rows of this panel above k0
+    if (f > 0) {
+      // the next panel's blocks (every read of the previous ones ended at its barrier)
+      load_block(Z - off, ld, vp);
+      if constexpr (kWide) {
+        if (tile) {
+          T vq[Q];
+          load_block(Zt - off, ld, vq);
+          stage_block(lds + kQt, vq);
+        }
+      }
+      stage_block(Pl, vp);
+      __syncthreads();
+    }
+    // Z_kk -= P^T P with P = R(panel, k) (the ten tiles on and above the diagonal, dealt
     // round-robin over the four waves; every LDS element is updated by one lane) and
-    // Z(k, tile) -= P^T R(k-1, tile)
+    // Z(k, tile) -= P^T R(panel, tile)
     int n = 0;
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
@@ -131,7 +147,7 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
 #pragma unroll
         for (int c = 0; c < 4; ++c) sub_ptq(lds + kUt, Pl, lds + kQt, wave, c);
       } else {
-        const T* Qg = Zt - NB;   // R(k-1, tile) from memory as the B operand
+        const T* Qg = Zt - off;   // R(panel, tile) from memory as the B operand
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           Acc acc = {0, 0, 0, 0};
@@ -245,17 +261,19 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   const int outer = mp >= kOuterMin ? kOuter : mp;
   // trailing problem of one launch: panel row `pr` applied to rows and columns
   // [r0, r1) (upper triangle) and to rows [r0, r1) x columns [r1, mp)
-  auto trailing = [&](int pr, int r0, int r1, GemmProblemT<T>* out) {
+  // trailing problem of one launch: panel rows [pr, pr + kk) applied to rows and columns
+  // [r0, r1) (upper triangle) and to rows [r0, r1) x columns [r1, mp)
+  auto trailing = [&](int pr, int kk, int r0, int r1, GemmProblemT<T>* out) {
     int n = 0;
     if (r1 <= r0) return n;
-    const T* a = z + pr + (long long)r0 * mp;   // R(pr, r0:)
-    GemmProblemT<T> q = gemm_problem(r1 - r0, r1 - r0, NB, a, mp, 1, a, mp, 0,
+    const T* a = z + pr + (long long)r0 * mp;   // R(pr:pr+kk, r0:)
+    GemmProblemT<T> q = gemm_problem(r1 - r0, r1 - r0, kk, a, mp, 1, a, mp, 0,
                                      z + r0 + (long long)r0 * mp, mp, -1.0, 1.0,
                                      z + r0 + (long long)r0 * mp, mp, kOutUpper);
     out[n++] = q;
     if (r1 < mp) {
-      const T* bq = z + pr + (long long)r1 * mp;   // R(pr, r1:)
-      out[n++] = gemm_problem(r1 - r0, mp - r1, NB, a, mp, 1, bq, mp, 0,
+      const T* bq = z + pr + (long long)r1 * mp;   // R(pr:pr+kk, r1:)
+      out[n++] = gemm_problem(r1 - r0, mp - r1, kk, a, mp, 1, bq, mp, 0,
                               z + r0 + (long long)r1 * mp, mp, -1.0, 1.0,
                               z + r0 + (long long)r1 * mp, mp, 0);
     }
@@ -290,14 +308,48 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
       PS_HIP(hipGetLastError());
     });
   };
-  for (int ob = 0; ob < mp; ob += outer) {
+  // Eight or more matrices without outer blocks: the trailing updates, bound by their memory
+  // traffic (a 64 x 64 tile with K = 64 reads and writes its C tile for 64 steps of
+  // work), go by pairs of panels (2q, 2q + 1) with K = 128: launch 2q + 2 takes the
+  // pair into block row 2q + 2 (diagonal workgroups) and applies it to the rows
+  // [2q + 3, mid); launch 2q + 3 takes panel 2q + 2 into its block row and applies the
+  // pair to the rows [mid, end).  mid splits the pair's tiles about evenly.
+  const bool paired = batch >= kPairedBatch && outer == mp;
+  const int nbk = mp / NB;
+  int mid = 0;
+  if (paired) {
+    for (int k = 0; k < nbk; ++k) {
+      GemmProblemT<T> tp[2];
+      int ntp = 0, fold = 0;
+      if (k > 0 && k % 2 == 0) {
+        fold = 2;
+        const int n = nbk - (k + 1);   // block rows below block row k
+        if (n > 0) {
+          const long long half = (long long)n * (n + 1) / 4;
+          int top = 1;
+          while (top < n && (long long)top * n - (long long)top * (top - 1) / 2 < half) ++top;
+          mid = (k + 1 + top) * NB;
+          ntp = trailing((k - 2) * NB, 2 * NB, (k + 1) * NB, mid, tp);
+        } else {
+          mid = mp;
+        }
+      } else if (k % 2 == 1) {
+        fold = 1;
+        if (k >= 3) {
+          ntp = trailing((k - 3) * NB, 2 * NB, mid, mp, tp);   // (upper square only)
+        }
+      }
+      step(k * NB, fold, tp, ntp);
+    }
+  }
+  for (int ob = 0; ob < mp && !paired; ob += outer) {
     const int obe = std::min(mp, ob + outer);
     for (int k0 = ob; k0 < obe; k0 += NB) {
       // the launch for block k0 carries the previous panel's update of the rows below
       // block row k0 + 1 within this outer block (none for the outer block's first
       // block: its rows took every earlier panel in the outer update)
       GemmProblemT<T> tp[2];
-      const int ntp = k0 > ob ? trailing(k0 - NB, k0 + NB, obe, tp) : 0;
+      const int ntp = k0 > ob ? trailing(k0 - NB, NB, k0 + NB, obe, tp) : 0;
       step(k0, k0 > ob ? 1 : 0, tp, ntp);
     }
     if (obe < mp) {
