@@ -88,19 +88,32 @@ struct Buffers {
 
 constexpr int kMaxSplit = 8;
 
-// Choose a split-K factor so that a launch has at least ~2 workgroups per CU.
+// Choose a split-K factor for a launch of few tiles: the pieces run in rounds of
+// `slots` resident workgroups (one 16-wave large tile per compute unit, or two small
+// ones), so the factor that fills the last round best wins, less 2 % per extra split
+// for the partial sums' traffic and the shorter K loops (at least 8 steps of 16).
 void auto_split(GemmProblem& p, double* ws, int maxsplit = kMaxSplit) {
   const bool big = p.M % 128 == 0 && p.N % 128 == 0 && std::min(p.M, p.N) >= 512;
   const int T = big ? 128 : 64;
+  const long long slots = big ? 256 : 512;
   long long tiles = (p.flags & (kOutUpper | kOutLower)) ? (long long)(p.M / T) * (p.M / T + 1) / 2
                                                         : (long long)(p.M / T) * (p.N / T);
   tiles *= (long long)p.nb1 * p.nb2;
   if (p.nb1 * p.nb2 != 1 || tiles >= 512) return;
-  int want = (int)((512 + tiles - 1) / tiles);
-  want = std::min(want, maxsplit);
-  while (want > 1 && p.K / 16 / want < 8) --want;
-  if (want > 1) {
-    p.ksplit = want;
+  int best = 1;
+  double best_score = -1.0;
+  for (int ks = 1; ks <= maxsplit; ++ks) {
+    if (ks > 1 && p.K / 16 / ks < 8) break;
+    const long long pieces = tiles * ks;
+    const long long rounds = (pieces + slots - 1) / slots;
+    const double score = (double)pieces / (double)(rounds * slots) - 0.02 * (ks - 1);
+    if (score > best_score + 1e-12) {
+      best_score = score;
+      best = ks;
+    }
+  }
+  if (best > 1) {
+    p.ksplit = best;
     p.ws = ws;
   }
 }
