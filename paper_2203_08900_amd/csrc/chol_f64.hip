@@ -21,6 +21,7 @@ constexpr int NB = kNb;
 constexpr int NTD = 256;
 constexpr int kWideBatch = 2;
 constexpr int kPairedBatch = 8;  // from this many matrices, trailing updates by panel pairs
+constexpr int kPairedMin = 1024; // ... and from this padded size (short chains gain nothing)
 constexpr int kOuter = 512;      // outer block of the large factorizations
 constexpr int kOuterMin = 4096;  // padded sizes from which they are used
 }
@@ -308,13 +309,14 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
       PS_HIP(hipGetLastError());
     });
   };
-  // Eight or more matrices without outer blocks: the trailing updates, bound by their memory
-  // traffic (a 64 x 64 tile with K = 64 reads and writes its C tile for 64 steps of
-  // work), go by pairs of panels (2q, 2q + 1) with K = 128: launch 2q + 2 takes the
+  // Eight or more matrices of padded size 1024 to 4095 (no outer blocks): the trailing
+  // updates, bound by their memory traffic (a 64 x 64 tile with K = 64 reads and writes
+  // its C tile for 64 steps of work), go by pairs of panels (2q, 2q + 1) with K = 128:
+  // launch 2q + 2 takes the
   // pair into block row 2q + 2 (diagonal workgroups) and applies it to the rows
   // [2q + 3, mid); launch 2q + 3 takes panel 2q + 2 into its block row and applies the
   // pair to the rows [mid, end).  mid splits the pair's tiles about evenly.
-  const bool paired = batch >= kPairedBatch && outer == mp;
+  const bool paired = batch >= kPairedBatch && mp >= kPairedMin && outer == mp;
   const int nbk = mp / NB;
   int mid = 0;
   if (paired) {
