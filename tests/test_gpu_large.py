@@ -94,3 +94,32 @@ def test_cholesky_grid_beyond_one_wave_m2560(precision):
     err = np.max(np.abs(w - exact) / exact)
     print(f"[grid] relative eigenvalue error {err:.3e}", flush=True)
     assert err < (1e-11 if precision == "fp64" else 1e-9)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision,basis", [("fp64", "core"), ("mixed", "alg6")])
+def test_outer_blocked_factorization_m4096(precision, basis):
+    """m = 4096 (padded size 4096): the Cholesky factorizations go by outer blocks of 512
+    rows (look-ahead steps inside an outer block, then one K = 512 update of the rows
+    below it).  The smallest size on that path, with the properties of the test above."""
+    m = 4096
+    a, b, mu = inputs.ill_separated(m, 13, mu_lo=1e-4)
+    A = torch.tensor(a, dtype=torch.float64, device="cuda")
+    B = torch.tensor(b, dtype=torch.float64, device="cuda")
+    print(f"[outer] divide m={m} {precision} {basis}", flush=True)
+    Qp, Hp, info = api.divide(A, B, precision=precision, basis=basis, r=8)
+    torch.cuda.synchronize()
+    assert info["status"] == 0
+    sig = torch.cat([torch.ones(m, dtype=torch.float64, device="cuda"),
+                     -torch.ones(m, dtype=torch.float64, device="cuda")])
+    G = Qp.T @ (sig[:, None] * Qp)
+    orth = (G - torch.eye(m, dtype=torch.float64, device="cuda")).abs().max().item()
+    print(f"[outer] Sigma-orthonormality {orth:.3e}", flush=True)
+    assert orth < 1e-10
+    exact = np.sqrt(mu)
+    Hs = 0.5 * (Hp + Hp.T)
+    assert abs(torch.trace(Hs).item() - exact.sum()) / exact.sum() < 1e-11
+    w = np.sort(eigvals_sym(Hs))
+    err = np.max(np.abs(w - exact) / exact)
+    print(f"[outer] relative eigenvalue error {err:.3e}", flush=True)
+    assert err < (1e-11 if precision == "fp64" else 1e-9)
