@@ -18,7 +18,7 @@ struct GemmGroup {
 
 // The operand transposes are per problem, so one launch covers a group of problems
 // with different transposes (each workgroup branches once, uniformly).
-template <class T, int BM, int BN, int WM, int WN>
+template <class T, int BM, int BN, int WM, int WN, bool kUseC>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g) {
   __shared__ T smem[2 * GemmLds<BM, BN>::ASZ + 2 * GemmLds<BM, BN>::BSZ];
   int bid = blockIdx.x;
@@ -33,13 +33,13 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g)
   const GemmProblemT<T>& P = g.p[pi];
   const int v = P.tA * 2 + P.tB;
   if (v == 0)
-    gemm_tile<T, BM, BN, WM, WN, 0, 0>(P, bid, smem);
+    gemm_tile<T, BM, BN, WM, WN, 0, 0, kUseC>(P, bid, smem);
   else if (v == 1)
-    gemm_tile<T, BM, BN, WM, WN, 0, 1>(P, bid, smem);
+    gemm_tile<T, BM, BN, WM, WN, 0, 1, kUseC>(P, bid, smem);
   else if (v == 2)
-    gemm_tile<T, BM, BN, WM, WN, 1, 0>(P, bid, smem);
+    gemm_tile<T, BM, BN, WM, WN, 1, 0, kUseC>(P, bid, smem);
   else
-    gemm_tile<T, BM, BN, WM, WN, 1, 1>(P, bid, smem);
+    gemm_tile<T, BM, BN, WM, WN, 1, 1, kUseC>(P, bid, smem);
 }
 
 // D = sum_s partial_s + beta C with the triangle / mirror conventions of the GEMM
@@ -128,10 +128,19 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
     tri_ops = tri_ops || ((g.p[q].flags & (kAUpper | kALower | kBUpper | kBLower)) &&
                           !(g.p[q].flags & (kOutUpper | kOutLower)));
   g.remap = (!tri_ops && total % 8 == 0 && total >= 64) ? 1 : 0;
+  // without any C operand (beta = 0 everywhere, or split-K partials) the tiles use the
+  // variant that keeps no C registers
+  bool use_c = false;
+  for (int q = 0; q < g.count; ++q)
+    use_c = use_c || (g.p[q].ksplit <= 1 && (g.p[q].beta_b || g.p[q].beta != 0.0));
   const bool rec = BM == 128 && std::is_same<T, double>::value && g_rec && g_rec->n < g_rec->cap;
   if (rec) PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n], s));
-  hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN>), dim3(total), dim3(WM * WN * 64),
-                     0, s, g);
+  if (use_c)
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN, true>), dim3(total),
+                       dim3(WM * WN * 64), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN, false>), dim3(total),
+                       dim3(WM * WN * 64), 0, s, g);
   PS_HIP(hipGetLastError());
   if (rec) {
     PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n + 1], s));

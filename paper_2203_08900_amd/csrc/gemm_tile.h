@@ -78,7 +78,9 @@ struct GemmLds {
 };
 
 // One output tile of problem P (logical tile index bid within the launch).
-template <class T, int BM, int BN, int WM, int WN, int TA, int TB>
+// kUseC = false: the caller guarantees beta = 0 (no C operand), which frees the
+// registers of the C prefetch.
+template <class T, int BM, int BN, int WM, int WN, int TA, int TB, bool kUseC = true>
 __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* smem) {
   auto As = reinterpret_cast<T(*)[GemmLds<BM, BN>::ASZ]>(smem);
   auto Bs = reinterpret_cast<T(*)[GemmLds<BM, BN>::BSZ]>(smem + 2 * GemmLds<BM, BN>::ASZ);
@@ -268,7 +270,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
   // C values before the K loop, so that trip to memory overlaps the loop instead of
   // following it; the large tiles keep their registers for occupancy and prefetch C
   // row by row in the epilogue.
-  constexpr bool kEarlyC = (BM == 64);
+  constexpr bool kEarlyC = (BM == 64) && kUseC;
   T cpre[kEarlyC ? FM : 1][FN][4];
   if (kEarlyC && (P.beta_b ? P.beta_b[z] : P.beta) != 0.0) {
 #pragma unroll
@@ -306,7 +308,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
   }
 
   const double alpha = P.alpha_b ? P.alpha_b[z] : P.alpha;
-  const double beta = P.beta_b ? P.beta_b[z] : P.beta;
+  const double beta = kUseC ? (P.beta_b ? P.beta_b[z] : P.beta) : 0.0;
   if (P.ksplit > 1) {
     // partial tile of split ks (batch extent is 1 for split problems)
     T* W = P.ws + (long long)ks * P.M * P.N;
