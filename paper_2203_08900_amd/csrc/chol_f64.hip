@@ -5,7 +5,10 @@
 // block row.  Per block step k, one launch applies panel k to block row k+1, factors and
 // inverts diagonal block k+1 and forms its panel R(k+1, k+2:) = R^{-T} Z(k+1, k+2:) (each
 // panel tile's workgroup updates and factors the block itself, and updates its own tile)
-// while its other workgroups apply panel k to the rows below block row k+1.
+// while its other workgroups apply panel k to the rows below block row k+1.  Two
+// variants of that schedule move the memory-bound K = 64 trailing updates: eight or more
+// matrices of moderate size apply panels in pairs (K = 128), and large matrices go by
+// outer blocks of 512 rows whose panels reach the rows below in one large GEMM.
 // The full inverse factor W = R^{-1} is then assembled from the inverted diagonal
 // blocks by recursive doubling, one pair of GEMM launches per level.  The batch index
 // runs over independent matrices (the r shifted Gram matrices of a Zolotarev step, or
@@ -260,8 +263,6 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   // the rows below it then take the update by all of its panels at once, one GEMM with
   // K = kOuter on the large tiles instead of kOuter / 64 memory-bound updates with K = 64.
   const int outer = mp >= kOuterMin ? kOuter : mp;
-  // trailing problem of one launch: panel row `pr` applied to rows and columns
-  // [r0, r1) (upper triangle) and to rows [r0, r1) x columns [r1, mp)
   // trailing problem of one launch: panel rows [pr, pr + kk) applied to rows and columns
   // [r0, r1) (upper triangle) and to rows [r0, r1) x columns [r1, mp)
   auto trailing = [&](int pr, int kk, int r0, int r1, GemmProblemT<T>* out) {
@@ -312,10 +313,9 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
   // Eight or more matrices of padded size 1024 to 4095 (no outer blocks): the trailing
   // updates, bound by their memory traffic (a 64 x 64 tile with K = 64 reads and writes
   // its C tile for 64 steps of work), go by pairs of panels (2q, 2q + 1) with K = 128:
-  // launch 2q + 2 takes the
-  // pair into block row 2q + 2 (diagonal workgroups) and applies it to the rows
-  // [2q + 3, mid); launch 2q + 3 takes panel 2q + 2 into its block row and applies the
-  // pair to the rows [mid, end).  mid splits the pair's tiles about evenly.
+  // launch 2q + 2 takes the pair into block row 2q + 2 (diagonal workgroups) and applies
+  // it to the rows [2q + 3, mid); launch 2q + 3 takes panel 2q + 2 into its block row and
+  // applies the pair to the rows [mid, end).  mid splits the pair's tiles about evenly.
   const bool paired = batch >= kPairedBatch && mp >= kPairedMin && outer == mp;
   const int nbk = mp / NB;
   int mid = 0;
