@@ -336,8 +336,8 @@ void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const
   pn.kseg = mp;
   pn.nseg = r;
   for (int j = 0; j < r; ++j) pn.kscale[j] = co.a[j];
-  if (r > 1 && r <= kMaxSplit) {   // one partial per shift term, summed by the reduction
-    pn.ksplit = r;
+  if (r > 1 && r <= kMaxSplit) {   // one partial per shift term (measured faster here
+    pn.ksplit = r;                  // than the round-filling choice of auto_split)
     pn.ws = b.splitws;
   }
   gemm_f64(s, pn);
@@ -479,10 +479,7 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
     pn.kseg = mp;
     pn.nseg = n64;
     for (int j = 0; j < n64; ++j) pn.kscale[j] = a64[j];
-    if (n64 > 1 && n64 <= kMaxSplit) {
-      pn.ksplit = n64;
-      pn.ws = b.splitws;
-    }
+    auto_split(pn, b.splitws);
     gemm_f64(s, pn);
   } else {
     fill_zero(s, b.nmat, b.S);
