@@ -16,14 +16,15 @@ modes      : fp64 / mixed (precision of the Zolotarev steps) x basis (Alg. 6, or
              run) gives `value`.
 value      : TFLOP/s of the primary mode = nominal algorithmic flops of the executed
              variant / measured time (flop convention below).
-roofline   : the large-tile FP64 GEMM kernel (the dominant kernel class), its
-             algorithmic flops per launch over its average launch duration, timed
-             with HIP events around each launch on the library's stream during a
-             separate instrumented pass over the same K steps.
-cpu_baseline: the FP64 CPU oracle (Alg. 8 with LDL^T solves on the full matrix),
-             timed on one shifted solve of Eq:LDLZolo at full size and scaled to the
-             whole divide; the same leg computes the reference eigenvalues used for
-             the relative eigenvalue error.
+roofline   : the kernel class with the largest summed GPU time in the primary mode
+             (a separate instrumented pass over the same K steps brackets every launch
+             of the matrix-core kernels with HIP events on the stream it runs on): its
+             algorithmic flops per launch over its average launch duration, against
+             the matrix-core peak of its precision; "kernels" lists every class.
+cpu_baseline: the FP64 CPU oracle (Alg. 8 with LDL^T solves on the full matrix, Alg. 6
+             bases, the decoupled block), one whole divide timed on the host; the
+             same leg computes the reference eigenvalues used for the relative
+             eigenvalue error.
 """
 from __future__ import annotations
 
@@ -48,7 +49,9 @@ def nominal_flops(m: int, r: int, step2_terms: int, basis: str = "alg6") -> floa
     setup = 2 * (m3 / 3 + m3 / 3) + 2 * (2 * m3 / 3)        # chol+inverse of A+-B, Y0, Y0^-1
     step1 = m3 + r * (m3 / 3 + m3 / 3 + m3 / 3) + 2 * m3     # X^T X, r x (POTRF, TRTRI, W W^T), X(I+N)
     if step2_terms > 0:
-        step2 = m3 + max(step2_terms - 2, 0) * 2 * m3 + 2 * m3   # X^T X, Horner, X T
+        # X^T X (symmetric: m^3), Horner products of commuting symmetric factors (symmetric
+        # results: m^3 each), X T (2 m^3)
+        step2 = m3 + max(step2_terms - 2, 0) * m3 + 2 * m3
     else:
         step2 = step1
     if basis == "core":
@@ -87,13 +90,15 @@ def gpu_leg(args, a, b):
         info = infos[-1]
         flops = nominal_flops(args.m, info["r"], info["step2_terms"], kw["basis"])
         # instrumented pass: per-phase and per-launch kernel times
-        gl, gms, gfl = 0, 0.0, 0.0
+        nk = len(api.KERNEL_CLASSES)
+        kl, kms, kfl = [0] * nk, [0.0] * nk, [0.0] * nk
         phase = [0.0] * 8
         for _ in range(args.steps):
             _, _, ti = api.divide(A, B, timing=2, **kw)
-            gl += ti["gemm_launches"]
-            gms += ti["gemm_ms"]
-            gfl += ti["gemm_flops"]
+            for c in range(nk):
+                kl[c] += ti["kclass_launches"][c]
+                kms[c] += ti["kclass_ms"][c]
+                kfl[c] += ti["kclass_flops"][c]
             phase = [p + q / args.steps for p, q in zip(phase, ti["phase_ms"])]
         torch.cuda.synchronize()
         Hh = Hp.cpu().numpy()
@@ -101,7 +106,7 @@ def gpu_leg(args, a, b):
         out[mode] = {
             "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "flops": flops,
             "info": info, "w": np.sort(w), "phase_ms": phase,
-            "gemm": {"launches": gl, "ms": gms, "flops": gfl},
+            "kclass": {"launches": kl, "ms": kms, "flops": kfl},
         }
     return out
 
@@ -251,14 +256,24 @@ def kernel_source_hash(paths) -> str:
     return h.hexdigest()[:16]
 
 
-GEMM_SOURCES = [os.path.join(ROOT, "paper_2203_08900_amd", "csrc", f)
-                for f in ("gemm_f64.hip", "gemm_tile.h")]
+_CSRC = os.path.join(ROOT, "paper_2203_08900_amd", "csrc")
+# per kernel class: the committed HBM-traffic summary and the sources the kernel is
+# built from (the counters only count while those sources are unchanged)
+TRAFFIC_PROFILES = {
+    0: ("chol_step_wide_f64_traffic_casida_n4096.txt", ["chol_f64.hip", "chol_block.h", "gemm_tile.h"]),
+    3: ("gemm_f64_128x128_traffic_casida_n4096.txt", ["gemm_f64.hip", "gemm_tile.h"]),
+}
+CLASS_DTYPE = ["f64", "f64", "f32", "f64", "f64", "f32"]
 
 
-def traffic_from_profile(kernel_srcs):
-    """HBM bytes per launch of the large-tile GEMM from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "gemm_f64_128x128_traffic_casida_n4096.txt")
+def traffic_from_profile(cls):
+    """HBM bytes per launch of kernel class `cls` from the committed counter summary, or
+    None when there is none or the kernel sources changed since the counters were taken."""
+    if cls not in TRAFFIC_PROFILES:
+        return None
+    name, srcs = TRAFFIC_PROFILES[cls]
+    kernel_srcs = [os.path.join(_CSRC, f) for f in srcs]
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -271,22 +286,38 @@ def traffic_from_profile(kernel_srcs):
     return float(kv["hbm_bytes_per_launch"])
 
 
-def cpu_leg(args, a, b, lam_pos=None):
-    """The oracle: one shifted LDL^T solve of Eq:LDLZolo at full size (the unit that
-    dominates the paper-literal divide), and the reference eigenvalues (the oracle's
-    definition, unless the construction fixes them)."""
-    import numpy as np
-    import scipy.linalg as sla
-
-    from oracle import eig as eg
-    from oracle import sign as sg
-    from oracle import zolotarev as zol
-
+def host_cpu():
+    """CPU model, physical cores and the BLAS thread count of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False)
+    except Exception:  # pragma: no cover
+        phys = None
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
+    return model, phys, threads
+
+
+def cpu_leg(args, a, b, lam_pos=None, whole=True):
+    """The oracle on the host: one whole divide (Alg. 8 with Bunch-Kaufman LDL^T solves on
+    the full 2m x 2m matrix, alpha and beta from the definition, Alg. 6 bases, the
+    decoupled block), timed once, and the reference eigenvalues (the oracle's definition,
+    unless the construction fixes them)."""
+    from oracle import divide as dv
+    from oracle import eig as eg
+
+    model, phys, threads = host_cpu()
     m = a.shape[0]
     t_eig = time.perf_counter()
     if lam_pos is None:
@@ -295,23 +326,18 @@ def cpu_leg(args, a, b, lam_pos=None):
     else:
         lp = lam_pos
     t_eig = time.perf_counter() - t_eig
-    h = sg.casida_matrix(a, b)
-    sigma = sg.casida_sigma(m)
-    alpha, beta = 1.01 * lp.max(), 0.99 * lp.min()
-    x = h / alpha
-    co = zol.coefficients(beta / alpha, args.r)
-    t0 = time.perf_counter()
-    xtsx = x.T @ (sigma[:, None] * x)
-    t_gram = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    z = xtsx + co.c[0] * np.diag(sigma)
-    lu, d, perm = sla.ldl(z, lower=True)
-    w = sg.ldl_solve(lu, d, perm, np.diag(sigma))
-    _ = x @ w
-    t_shift = time.perf_counter() - t0
-    t_total = 2 * (t_gram + args.r * t_shift)
-    return {"t_shift": t_shift, "t_gram": t_gram, "t_total": t_total, "threads": threads,
+    t_total = None
+    if whole:
+        t0 = time.perf_counter()
+        dv.divide_casida(a, b, r=args.r)
+        t_total = time.perf_counter() - t0
+    return {"t_total": t_total, "threads": threads, "model": model, "physical_cores": phys,
             "lam_pos": lp, "t_eig": t_eig}
+
+
+def api_classes():
+    from paper_2203_08900_amd import api
+    return api.KERNEL_CLASSES
 
 
 def main():
@@ -375,29 +401,44 @@ def main():
         for mode, r in g.items():
             rel_err[mode] = float(np.max(np.abs(r["w"] - exact) / exact))
     if not args.no_cpu:
-        c = cpu_leg(args, a, b, exact)
+        c = cpu_leg(args, a, b, exact, whole=args.workload == "casida_n4096")
         for mode, r in g.items():
             rel_err[mode] = float(np.max(np.abs(r["w"] - c["lam_pos"]) / c["lam_pos"]))
-        cpu_tflops = res["flops"] / c["t_total"] / 1e12
-        cpu = {
-            "value": cpu_tflops, "unit": "TFLOP/s", "cores": c["threads"], "kind": "oracle",
-            "sample": (f"one of the 2r = {2 * args.r} shifted LDL^T solves of Eq:LDLZolo on the full "
-                       f"{2 * args.m}x{2 * args.m} matrix ({c['t_shift']:.2f} s) plus one Gram product "
-                       f"({c['t_gram']:.2f} s), scaled to the divide as 2 x (Gram + r solves) = "
-                       f"{c['t_total']:.1f} s; the flop numerator is the GPU variant's nominal count"),
-        }
+        if c["t_total"] is not None:
+            cpu = {
+                "value": res["flops"] / c["t_total"] / 1e12, "unit": "TFLOP/s",
+                "cores": c["threads"], "kind": "oracle",
+                "sample": (f"one whole oracle divide at n = {2 * args.m} (Alg. 8 with Bunch-Kaufman "
+                           f"LDL^T solves on the full matrix, alpha and beta from the definition, "
+                           f"Alg. 6 bases, H_+), {c['t_total']:.1f} s on {c['threads']} BLAS "
+                           f"threads of a {c['model']} ({c['physical_cores']} physical cores); "
+                           f"the flop numerator is the GPU variant's nominal count"),
+                "seconds": c["t_total"], "cpu_model": c["model"],
+                "physical_cores": c["physical_cores"],
+            }
 
-    gm = res["gemm"]
-    roof = None
-    if gm["launches"] > 0 and gm["ms"] > 0:
-        achieved = gm["flops"] / (gm["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK["f64"],
-                "traffic": traffic_from_profile(GEMM_SOURCES),
-                "kernel": "gemm_mfma_kernel<double,128,128,4,4>",
-                "launches_per_step": gm["launches"] / args.steps,
-                "avg_launch_ms": gm["ms"] / gm["launches"],
-                "flops_per_launch": gm["flops"] / gm["launches"]}
+    kc = res["kclass"]
+    roof, kernels = None, []
+    for cls, name in enumerate(api_classes()):
+        if kc["launches"][cls] == 0 or kc["ms"][cls] <= 0:
+            continue
+        ach = kc["flops"][cls] / (kc["ms"][cls] * 1e-3) / 1e12
+        peak = PEAK[CLASS_DTYPE[cls]]
+        kernels.append({"kernel": name, "launches_per_step": kc["launches"][cls] / args.steps,
+                        "ms_per_step": kc["ms"][cls] / args.steps,
+                        "avg_launch_ms": kc["ms"][cls] / kc["launches"][cls],
+                        "achieved": ach, "peak": peak, "frac": ach / peak,
+                        "share_of_step": kc["ms"][cls] / args.steps / res["ms"]})
+    if kernels:
+        top = max(range(len(kernels)), key=lambda i: kernels[i]["ms_per_step"])
+        k = kernels[top]
+        cls = api_classes().index(k["kernel"])
+        roof = {"bound": "mfma", "achieved": k["achieved"], "peak": k["peak"], "unit": "TFLOP/s",
+                "frac": k["frac"], "traffic": traffic_from_profile(cls),
+                "kernel": k["kernel"], "launches_per_step": k["launches_per_step"],
+                "avg_launch_ms": k["avg_launch_ms"],
+                "flops_per_launch": kc["flops"][cls] / kc["launches"][cls],
+                "kernels": kernels}
 
     line = {
         "metric": METRIC,

@@ -28,9 +28,15 @@
  *    the handle being argument 1) is invalid and nothing was launched; a positive
  *    value is one of the PS_* status codes below, in which case the outputs are
  *    undefined and `info` (if given) says where the failure happened.
- *  - Device memory: the library draws its scratch space from a workspace that the
- *    caller can provide with ps_set_workspace(); without one, the handle allocates
- *    (and keeps) what it needs on first use.
+ *  - Device memory: the library never allocates device memory.  Its scratch space is
+ *    the caller's workspace (ps_set_workspace, sized by ps_workspace_size or
+ *    ps_workspace_size_batched); a call whose workspace is missing or too small returns
+ *    PS_NO_WORKSPACE before any launch.
+ *  - Streams: the library creates none.  Work runs on the handle's stream; the caller
+ *    may lend extra streams (ps_set_worker_streams) on which independent work runs
+ *    concurrently: the FP32 shift group of a mixed step, the workers of a batched call
+ *    and the subtrees of the eigen-decomposition.  Without them that work runs in order
+ *    on the handle's stream, with the same results.
  */
 #ifndef PSEUDOSYM_H
 #define PSEUDOSYM_H
@@ -86,8 +92,8 @@ typedef struct {
                        /* of X_1 = hat Z(H/alpha)); only honoured by pseudosym_sign */
   int lanczos_steps;   /* Golub-Kahan steps of the alpha/beta estimator (>= 4)   */
   int timing;          /* 1: fill info->phase_ms with per-phase GPU times;        */
-                       /* 2: also time every launch of the large-tile FP64 GEMM  */
-                       /*    kernel (info->gemm_*)                               */
+                       /* 2: also time every launch of the matrix-core kernels   */
+                       /*    with events on its stream (info->kclass_*, gemm_*)  */
   double alpha;        /* > 0: caller's upper bound of max|lambda(H)| (skips the  */
   double beta;         /* estimator); > 0: caller's lower bound of min|lambda(H)| */
   double mixed_kappa;  /* mixed precision: shifts whose condition number          */
@@ -118,7 +124,7 @@ typedef struct {
                            /* bases, decouple (when opts->timing)                    */
   int step2_terms;         /* 0: second step by factorizations; P > 0: series terms */
   int gemm_launches;       /* timing == 2: launches of the large-tile FP64 GEMM kernel */
-  double gemm_ms;          /*   their summed GPU time                                 */
+  double gemm_ms;          /*   their summed GPU time (split-K reductions included)   */
   double gemm_flops;       /*   their algorithmic flops (zero blocks of triangular    */
                            /*   operands and the unstored triangle not counted)      */
   int eig_splits;          /* pseudosym_eig: splits of the symmetric recursion        */
@@ -126,7 +132,25 @@ typedef struct {
   int eig_sweeps;          /*   largest number of Jacobi sweeps of a leaf             */
   int eig_steps;           /*   Zolotarev steps summed over the splits                */
   int eig_restarts;        /*   restarts summed over the splits                       */
+  int eig_clusters;        /*   blocks found to be a multiple of I within 1e-12 of     */
+                           /*   their magnitude (split without a shift)                */
+  /* timing == 2, per kernel class c (PS_KC_*): launches, summed GPU time of the event
+   * windows (ms) and algorithmic flops.  A Cholesky step launch counts mp^3/3 per matrix
+   * spread evenly over the mp/64 steps of its factorization. */
+  int kclass_launches[8];
+  double kclass_ms[8];
+  double kclass_flops[8];
 } ps_info;
+
+/* kernel classes of ps_info.kclass_* */
+enum {
+  PS_KC_CHOL_WIDE = 0,     /* Cholesky step, FP64, one or two matrices per launch      */
+  PS_KC_CHOL_NARROW = 1,   /* Cholesky step, FP64, more matrices                       */
+  PS_KC_CHOL_FP32 = 2,     /* Cholesky step, FP32                                      */
+  PS_KC_GEMM128 = 3,       /* FP64 GEMM on 128 x 128 tiles                              */
+  PS_KC_GEMM64 = 4,        /* FP64 GEMM on 64 x 64 tiles                                */
+  PS_KC_GEMM_FP32 = 5      /* FP32 GEMM                                                 */
+};
 
 /* Fill *o with the defaults: FP64, r = 8, 2 restarts, full method, 20 Lanczos
  * steps, no timing, estimated alpha/beta, mixed_kappa = 20, step2_series = 1,
@@ -144,9 +168,29 @@ int ps_set_stream(ps_handle h, void* stream);
 size_t ps_workspace_size(int m, const ps_opts* o, int what);
 
 /* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the
- * workspace from now on; NULL reverts to library-owned memory.  The buffer must
- * outlive every call that uses it. */
+ * workspace from now on; NULL clears it (calls then return PS_NO_WORKSPACE).  The
+ * buffer must outlive every call that uses it.  Returns 0, -1 (no handle) or -2
+ * (misaligned pointer). */
 int ps_set_workspace(ps_handle h, void* dptr, size_t bytes);
+
+/* Bytes of workspace for pseudosym_divide_batched on these `batch` half-sizes m[] (host
+ * array) with options o (NULL = defaults): one share per worker (up to six), each
+ * holding the largest single problem and the largest class of equal padded size that
+ * the call batches together (classes are planned within 2 GiB per share).  A smaller
+ * workspace also works as long as one share holds the largest single problem: the call
+ * then uses fewer workers or smaller classes.  0 on invalid arguments. */
+size_t ps_workspace_size_batched(int batch, const int* m, const ps_opts* o);
+
+/* Lend `count` (0..PS_MAX_WORKER_STREAMS) extra streams (hipStream_t, on the handle's
+ * device, distinct from the handle's stream) for the concurrent parts of a call: the
+ * first runs the FP32 shift group of a mixed step, and batched calls and the
+ * eigen-decomposition run one worker per stream (at most six, resp. four).  The handle
+ * keeps the pointers: the streams must outlive it or be replaced by another call
+ * (count 0 withdraws them).  Streams should have the default priority.  Returns 0,
+ * -1 (no handle), -2 (bad count), -3 (a null stream or the handle's own), or
+ * PS_HIP_ERROR. */
+#define PS_MAX_WORKER_STREAMS 8
+int ps_set_worker_streams(ps_handle h, int count, void* const* streams);
 
 /* Host-only: coefficients of the scaled Zolotarev function hat Z_{2r+1}(x; ell)
  * (Eq:Compcis, Eq:hatZ, Eq:ZPartialFrac2): c[0..2r-1] = c_1..c_2r,
@@ -200,9 +244,10 @@ int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B,
  * and outputs Qp[i] (2m[i] x m[i], ldq[i] >= 2 m[i]) and Hp[i] (ldh[i] >= m[i]), with
  * the conventions of pseudosym_divide.  m, lda, ldb, ldq, ldh and the pointer arrays
  * are HOST arrays of length batch holding device pointers.  The problems run largest
- * first on six worker streams owned by the handle (each with its own library-owned
- * workspace; ps_set_workspace does not apply to them); the call returns when all are
- * done.  In FP64 (or mixed below its size threshold), problems of one padded size (m
+ * first, on the caller's worker streams (ps_set_worker_streams; one worker per stream,
+ * at most six, each with an equal share of the handle's workspace, sized by
+ * ps_workspace_size_batched) or, without them, in order on the handle's stream; the
+ * call returns when all are done.  In FP64 (or mixed below its size threshold), problems of one padded size (m
  * rounded up to 64) run together, with either basis, up to 32 per batched pipeline
  * (fewer where their workspace would pass 3 GiB): their results agree with single calls
  * to rounding (the sums are split differently), not bit for bit; other problems run the

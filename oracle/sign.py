@@ -119,6 +119,45 @@ def sign_definition_geev(h: np.ndarray) -> np.ndarray:
     return s.real
 
 
+def sign_blocks_from_spectral_factors(qm: np.ndarray, dm: np.ndarray, q: np.ndarray,
+                                      mu: np.ndarray):
+    """Closed form of the blocks (A_s, B_s) of sign(H) = [[A_s, B_s], [-B_s, -A_s]] when
+    A + B = M = q_M diag(d_M) q_M^T and A - B = K = M^{-1/2} q diag(mu) q^T M^{-1/2}.
+
+    With Q_h = [[I, I], [I, -I]] / sqrt(2), Q_h H Q_h = [[0, K], [M, 0]] =: X, and
+    eq:signDef gives sign(X) = X (X^2)^{-1/2} = [[0, K (MK)^{-1/2}], [M (KM)^{-1/2}, 0]].
+    For this K, KM = M^{-1/2} q diag(mu) q^T M^{1/2}, so
+        S12 = K (MK)^{-1/2} = M^{-1/2} q diag(mu^{1/2}) q^T M^{-1/2},
+        S21 = M (KM)^{-1/2} = M^{1/2} q diag(mu^{-1/2}) q^T M^{1/2},
+    and Q_h [[0, S12], [S21, 0]] Q_h has blocks A_s = (S21 + S12)/2, B_s = (S21 - S12)/2.
+    Only matrix products of the factors: usable at sizes where no eigensolver is.
+    Returns (A_s, B_s) and a function cols(j) giving the columns j of both blocks
+    at O(m^2 len(j)) cost."""
+    mh = (qm * np.sqrt(dm)[None, :]) @ qm.T
+    mih = (qm * (1.0 / np.sqrt(dm))[None, :]) @ qm.T
+    cp = (q * np.sqrt(mu)[None, :]) @ q.T
+    cm = (q * (1.0 / np.sqrt(mu))[None, :]) @ q.T
+    s12 = mih @ (cp @ mih)
+    s21 = mh @ (cm @ mh)
+    return 0.5 * (s21 + s12), 0.5 * (s21 - s12)
+
+
+def sign_columns_from_spectral_factors(qm, dm, q, mu, cols):
+    """Columns `cols` of A_s and B_s (same closed form as above), applying every factor
+    to the few columns instead of forming the m x m products."""
+    e = np.zeros((qm.shape[0], len(cols)))
+    e[np.asarray(cols), np.arange(len(cols))] = 1.0
+
+    def apply(diag_m, diag_mu, x):
+        x = qm @ (diag_m[:, None] * (qm.T @ x))
+        x = q @ (diag_mu[:, None] * (q.T @ x))
+        return qm @ (diag_m[:, None] * (qm.T @ x))
+
+    s12 = apply(1.0 / np.sqrt(dm), np.sqrt(mu), e)
+    s21 = apply(np.sqrt(dm), 1.0 / np.sqrt(mu), e)
+    return 0.5 * (s21 + s12), 0.5 * (s21 - s12)
+
+
 # --------------------------------------------------------------------------- Alg. 8
 @dataclass
 class ZoloRecord:

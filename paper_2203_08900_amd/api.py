@@ -23,6 +23,10 @@ PS_PREC_FP64 = 0
 PS_PREC_MIXED = 1
 PS_BASIS_ALG6 = 0
 PS_BASIS_CORE = 1
+# kernel classes of info["kclass_*"] (PS_KC_* in the header)
+KERNEL_CLASSES = ["chol_step_kernel<double,wide>", "chol_step_kernel<double,narrow>",
+                  "chol_step_kernel<float>", "gemm_mfma_kernel<double,128x128>",
+                  "gemm_mfma_kernel<double,64x64>", "gemm_mfma_kernel<float>"]
 
 STATUS = {
     0: "ok", 1: "not definite", 2: "shift breakdown", 3: "not converged",
@@ -70,6 +74,10 @@ class PsInfo(ctypes.Structure):
         ("eig_sweeps", ctypes.c_int),
         ("eig_steps", ctypes.c_int),
         ("eig_restarts", ctypes.c_int),
+        ("eig_clusters", ctypes.c_int),
+        ("kclass_launches", ctypes.c_int * 8),
+        ("kclass_ms", ctypes.c_double * 8),
+        ("kclass_flops", ctypes.c_double * 8),
     ]
 
     def as_dict(self):
@@ -84,15 +92,22 @@ class PsInfo(ctypes.Structure):
             "gemm_flops": self.gemm_flops, "eig_splits": self.eig_splits,
             "eig_leaves": self.eig_leaves, "eig_sweeps": self.eig_sweeps,
             "eig_steps": self.eig_steps, "eig_restarts": self.eig_restarts,
+            "eig_clusters": self.eig_clusters,
+            "kclass_launches": list(self.kclass_launches),
+            "kclass_ms": list(self.kclass_ms), "kclass_flops": list(self.kclass_flops),
         }
 
 
 EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
-    "ps_set_workspace", "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
+    "ps_set_workspace", "ps_workspace_size_batched", "ps_set_worker_streams",
+    "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
     "pseudosym_eig", "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
     "ps_status_string",
 ]
+
+# worker streams lent to each handle (batched calls and the recursion use up to six)
+N_WORKER_STREAMS = 6
 
 _lib = None
 _lock = threading.Lock()
@@ -122,6 +137,11 @@ def load():
         lib.ps_workspace_size.restype = sz
         lib.ps_set_workspace.argtypes = [hp, vp, sz]
         lib.ps_set_workspace.restype = ip
+        lib.ps_workspace_size_batched.argtypes = [ip, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(PsOpts)]
+        lib.ps_workspace_size_batched.restype = sz
+        lib.ps_set_worker_streams.argtypes = [hp, ip, ctypes.POINTER(ctypes.c_void_p)]
+        lib.ps_set_worker_streams.restype = ip
         lib.ps_zolotarev_coeffs.argtypes = [ctypes.c_double, ip, dp, dp, dp, dp]
         lib.ps_zolotarev_coeffs.restype = ip
         mat = [hp, ip, vp, ip, vp, ip]
@@ -197,6 +217,7 @@ class _HandleState:
     handle: ctypes.c_void_p
     workspace: object
     ws_bytes: int
+    streams: list = None      # torch streams lent to the handle (kept alive here)
 
 
 _handles = {}
@@ -212,12 +233,19 @@ def _handle(device, stream_ptr):
     key = (device, stream_ptr)
     st = _handles.get(key)
     if st is None:
+        torch = _torch()
         lib = load()
         h = ctypes.c_void_p()
         rc = lib.ps_create(ctypes.byref(h), ctypes.c_void_p(stream_ptr))
         if rc != 0:
             raise PseudosymError(rc)
-        st = _HandleState(h, None, 0)
+        # PyTorch supplies the streams of the concurrent parts (default priority)
+        streams = [torch.cuda.Stream(device=device) for _ in range(N_WORKER_STREAMS)]
+        arr = (ctypes.c_void_p * len(streams))(*[x.cuda_stream for x in streams])
+        rc = lib.ps_set_worker_streams(h, len(streams), arr)
+        if rc != 0:
+            raise PseudosymError(rc)
+        st = _HandleState(h, None, 0, streams)
         _handles[key] = st
     return st
 
@@ -234,9 +262,10 @@ def _prepare(A, B):
     return A.contiguous(), B.contiguous()
 
 
-def _ensure_workspace(st, lib, m, opts, what, device):
+def _ensure_workspace(st, lib, m, opts, what, device, need=None):
     torch = _torch()
-    need = int(lib.ps_workspace_size(int(m), ctypes.byref(opts), int(what)))
+    if need is None:
+        need = int(lib.ps_workspace_size(int(m), ctypes.byref(opts), int(what)))
     if st.ws_bytes < need:
         st.workspace = torch.empty(need + 256, dtype=torch.uint8, device=device)
         st.ws_bytes = need
@@ -319,10 +348,12 @@ def divide_batched(As, Bs, raise_on_error=True, **kw):
     if n == 0:
         return [], [], []
     dev = pairs[0][0].device
+    ms = [A.shape[0] for A, _ in pairs]
     with torch.cuda.device(dev):
         stream = torch.cuda.current_stream(dev)
         st = _handle(dev.index, stream.cuda_stream)
-    ms = [A.shape[0] for A, _ in pairs]
+        need = int(lib.ps_workspace_size_batched(n, (ctypes.c_int * n)(*ms), ctypes.byref(opts)))
+        _ensure_workspace(st, lib, 0, opts, 1, dev, need=need)
     Qts = [torch.empty((mi, 2 * mi), dtype=torch.float64, device=dev) for mi in ms]
     Hps = [torch.empty((mi, mi), dtype=torch.float64, device=dev) for mi in ms]
     I = ctypes.c_int * n
@@ -374,13 +405,7 @@ def sign_bwd(lam, V, gSA, gSB):
         stream = torch.cuda.current_stream(dev)
         st = _handle(dev.index, stream.cuda_stream)
         need = int(lib.ps_workspace_size(int(m), None, 3))
-        if st.ws_bytes < need:
-            st.workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-            st.ws_bytes = need
-            aligned = (st.workspace.data_ptr() + 255) // 256 * 256
-            rc = lib.ps_set_workspace(st.handle, ctypes.c_void_p(aligned), ctypes.c_size_t(need))
-            if rc != 0:
-                raise PseudosymError(rc)
+        _ensure_workspace(st, lib, m, None, 3, dev, need=need)
     Vc = _colmajor(V.to(torch.float64))
     ga_in = _colmajor(gSA.to(torch.float64))
     gb_in = _colmajor(gSB.to(torch.float64))

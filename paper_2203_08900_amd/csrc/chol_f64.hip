@@ -203,6 +203,101 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
   }
 }
 
+// Inverse factor alongside the factorization (one or two matrices).  With
+// V(i, j) = sum_{l = i}^{j - 1} W(i, l) R(l, j) for block indices i < j, the blocks of
+// W = R^{-1} above the diagonal are W(i, j) = -V(i, j) W_jj.  Launch L of the chain (the
+// one that factors diagonal block L) has row block L - 1 of R and W_{L-1, L-1} final, and
+// V(i, L - 1) complete for i < L - 1.  Its inverse workgroup (i, j), i <= L - 1 < L <= j,
+// forms T = W(i, L - 1) (= W_{L-1,L-1} for i = L - 1, else -V(i, L - 1) W_{L-1,L-1}) and
+// adds T R(L - 1, j) to V(i, j) (sets it for i = L - 1); workgroup (i, L) also stores
+// T as W(i, L - 1).  A last launch stores W(i, nb - 1).  V lives in a separate buffer
+// (upper blocks only), so the blocks the launch reads and writes are all distinct.
+struct InvPlan {
+  int L;        // launch index (diagonal block being factored); L == nbk: finishing pass
+  int nbk;      // number of 64-blocks
+  int ncols;    // nbk - L (columns j = L .. nbk - 1), 0 in the finishing pass
+  int per;      // inverse workgroups per matrix
+};
+
+template <class T>
+__device__ __forceinline__ void inverse_tile(T* lds, int q, T* z, long long sz, T* w, long long sw,
+                                             T* v, long long sv, int ld, const InvPlan& ip) {
+  using Acc = typename blk::BlkMfma<T>::acc_t;
+  constexpr int Q = NB * NB / NTD;
+  const int b = q / ip.per, e = q - b * ip.per;
+  const int L = ip.L;
+  int i, j;
+  if (ip.ncols > 0) {
+    i = e / ip.ncols;
+    j = L + (e - i * ip.ncols);
+  } else {        // finishing pass: W(i, nbk - 1) for i < nbk - 1
+    i = e;
+    j = -1;
+  }
+  const int c = L - 1;   // the block column of W finished here
+  const T* Wcc = w + b * sw + (long long)c * NB * (ld + 1);
+  T* Vb = v + b * sv;
+  T* const Wl = lds;                     // W_{cc}, row-major [64][65]
+  T* const Tl = lds + NB * blk::kLdS;    // V(i, c) then T = W(i, c)
+  T* const Rl = lds + 2 * NB * blk::kLdS;  // R(c, j)
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  const bool diag_row = (i == c);
+  {
+    T vw[Q], vt[Q], vr[Q];
+    load_block(Wcc, ld, vw);
+    if (!diag_row) load_block(Vb + (long long)i * NB + (long long)c * NB * ld, ld, vt);
+    if (j >= 0) load_block(z + b * sz + (long long)c * NB + (long long)j * NB * ld, ld, vr);
+    stage_block(Wl, vw);
+    if (!diag_row) stage_block(Tl, vt);
+    if (j >= 0) stage_block(Rl, vr);
+  }
+  // V(i, j) in the accumulator layout (wave w: rows 16w.., four 16-column tiles)
+  Acc acc[4];
+  T* Vij = (j >= 0) ? Vb + (long long)i * NB + (long long)j * NB * ld : nullptr;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      acc[t][u] = (j >= 0 && !diag_row)
+                      ? Vij[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld]
+                      : T(0);
+  __syncthreads();
+  // T = -V(i, c) W_cc, rows 16w.. of each wave (each wave reads and then overwrites only
+  // its own rows of Tl; W_cc is read by all and never written)
+  const T* Trow = Wl;
+  if (!diag_row) {
+    Acc tt[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      tt[t] = blk::tile_mm(Tl + 16 * wave * blk::kLdS, blk::kLdS, Wl + 16 * t, blk::kLdS, NB);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        Tl[(16 * wave + blk::BlkMfma<T>::row(lk, u)) * blk::kLdS + 16 * t + li] = -tt[t][u];
+    Trow = Tl;
+    // the first column's workgroup (or the finishing pass) stores W(i, c)
+    if (j == L || j < 0) {
+      T* Wic = w + b * sw + (long long)i * NB + (long long)c * NB * ld;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          Wic[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld] = -tt[t][u];
+    }
+  }
+  if (j < 0) return;
+  // V(i, j) += T R(c, j)   (T rows of this wave only)
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    acc[t] += blk::tile_mm(Trow + 16 * wave * blk::kLdS, blk::kLdS, Rl + 16 * t, blk::kLdS, NB);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      Vij[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld] = acc[t][u];
+}
+
 // One launch of the factorization: workgroups below ndiag run diag_panel for the block
 // at k0 (with the previous panel's update of block row k0 when fold is set); the others
 // are tiles of the trailing update, `tp` then `tq` (np tiles of tp), that the step
@@ -219,7 +314,8 @@ template <class T, bool kWide>
 __global__ __launch_bounds__(NTD)
 __attribute__((amdgpu_waves_per_eu(step_waves<T, kWide>()))) void chol_step_kernel(
     T* z, long long sz, T* w, long long sw, int ld, int k0, int rest, int ntiles, int fold,
-    int* info, GemmProblemT<T> tp, GemmProblemT<T> tq, int ndiag, int np) {
+    int* info, GemmProblemT<T> tp, GemmProblemT<T> tq, int ndiag, int np, int ntrail, T* v,
+    long long sv, InvPlan ip) {
   constexpr int kAB = 2 * GemmLds<64, 64>::ASZ + 2 * GemmLds<64, 64>::BSZ;
   constexpr int kElems = kWide ? kWideElems : blk::kLdsElems;
   __shared__ T lds[kElems > kAB ? kElems : kAB];
@@ -228,8 +324,10 @@ __attribute__((amdgpu_waves_per_eu(step_waves<T, kWide>()))) void chol_step_kern
     diag_panel<T, kWide>(lds, bid, z, sz, w, sw, ld, k0, rest, ntiles, fold, info);
   else if (bid < ndiag + np)
     gemm_tile<T, 64, 64, 2, 2, 1, 0>(tp, bid - ndiag, lds);
-  else
+  else if (bid < ndiag + ntrail)
     gemm_tile<T, 64, 64, 2, 2, 1, 0>(tq, bid - ndiag - np, lds);
+  else if constexpr (kWide)
+    inverse_tile<T>(lds, bid - ndiag - ntrail, z, sz, w, sw, v, sv, ld, ip);
 }
 
 inline void gemm_t(hipStream_t s, const GemmProblem* p, int n) { gemm_f64(s, p, n); }
@@ -237,7 +335,7 @@ inline void gemm_t(hipStream_t s, const GemmProblemF* p, int n) { gemm_f32(s, p,
 
 template <class T>
 void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, int batch,
-                 int* info, bool inverse, LaunchList* defer) {
+                 int* info, bool inverse, LaunchList* defer, T* v = nullptr, long long sv = 0) {
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
   // every launch goes through issue (closures own copies of their arguments)
   auto issue = [defer](std::function<void()> f) {
@@ -281,10 +379,22 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     }
     return n;
   };
+  // the inverse alongside the chain: one or two matrices, no outer blocks, a V buffer
+  const bool fused_inv = inverse && v && wide && mp < kOuterMin;
+  const int nbk_all = mp / NB;
+  auto inv_plan = [&](int L) {
+    InvPlan ip{L, nbk_all, 0, 0};
+    if (!fused_inv || L < 1) return ip;
+    ip.ncols = nbk_all - L;
+    ip.per = L < nbk_all ? L * ip.ncols : L - 1;   // (i, j) pairs, or the finishing stores
+    return ip;
+  };
   auto step = [&](int k0, int fold, const GemmProblemT<T>* tp, int ntp) {
     const int rest = mp - k0 - NB;
     const int nt = rest > 0 ? rest / NB : 1;
     const int ndiag = batch * nt;
+    const InvPlan ip = inv_plan(k0 / NB);
+    const int ninv = batch * ip.per;
     GemmProblemT<T> t[2] = {};
     int cnt[2] = {0, 0};
     for (int q = 0; q < ntp; ++q) {
@@ -299,15 +409,21 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
       cnt[q] = t[q].tiles * batch;
     }
     const GemmProblemT<T> t0 = t[0], t1 = t[1];
-    const int np = cnt[0], grid = ndiag + cnt[0] + cnt[1];
+    const int np = cnt[0], ntrail = cnt[0] + cnt[1], grid = ndiag + ntrail + ninv;
     issue([=] {
+      const int slot = krec_begin(s);
       if (wide)
         hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(grid), dim3(NTD), 0, s, z, sz, w, sw,
-                           mp, k0, rest, nt, fold, info, t0, t1, ndiag, np);
+                           mp, k0, rest, nt, fold, info, t0, t1, ndiag, np, ntrail, v, sv, ip);
       else
         hipLaunchKernelGGL((chol_step_kernel<T, false>), dim3(grid), dim3(NTD), 0, s, z, sz, w,
-                           sw, mp, k0, rest, nt, fold, info, t0, t1, ndiag, np);
+                           sw, mp, k0, rest, nt, fold, info, t0, t1, ndiag, np, ntrail, v, sv,
+                           ip);
       PS_HIP(hipGetLastError());
+      // algorithmic work of a launch: the factorization's batch mp^3 / 3 spread evenly over
+      // its mp / 64 block steps
+      krec_end(s, slot, sizeof(T) == 4 ? kKcChol32 : (wide ? kKcCholWide : kKcCholNarrow),
+               (double)batch * mp * mp * (double)NB / 3.0);
     });
   };
   // Eight or more matrices of padded size 1024 to 4095 (no outer blocks): the trailing
@@ -366,6 +482,22 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     }
   }
   if (!inverse) return;   // W then holds only the inverted diagonal blocks
+  if (fused_inv) {
+    // the finishing pass: W(i, nbk - 1) = -V(i, nbk - 1) W_{nbk-1, nbk-1}
+    const InvPlan ip = inv_plan(nbk_all);
+    const int ninv = batch * ip.per;
+    if (ninv > 0) {
+      const GemmProblemT<T> none{};
+      issue([=] {
+        const int slot = krec_begin(s);
+        hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(ninv), dim3(NTD), 0, s, z, sz, w, sw,
+                           mp, 0, 0, 1, 0, info, none, none, 0, 0, 0, v, sv, ip);
+        PS_HIP(hipGetLastError());
+        krec_end(s, slot, sizeof(T) == 4 ? kKcChol32 : kKcCholWide, 0.0);
+      });
+    }
+    return;
+  }
   // ---- W = R^{-1} by recursive doubling over the block diagonal: at level S every
   // diagonal block of size S is already inverted, and for each pair of neighbours
   //   W12 = -W11 R12 W22.
@@ -416,8 +548,8 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
 
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
                    double* /*tmp*/, int mp, int batch, int* info, bool inverse,
-                   LaunchList* defer) {
-  potrf_inv_t(s, z, sz, w, sw, mp, batch, info, inverse, defer);
+                   LaunchList* defer, double* v, long long sv) {
+  potrf_inv_t(s, z, sz, w, sw, mp, batch, info, inverse, defer, v, sv);
 }
 
 void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,

@@ -58,6 +58,51 @@ void get_diag(hipStream_t s, const double* x, int ld, int n, double* out) {
   PS_HIP(hipGetLastError());
 }
 
+// Sum of squares of the off-diagonal entries of the leading n x n block (two passes:
+// per-workgroup partials, then one workgroup adds them in a fixed order).
+constexpr int kOffParts = 256;
+
+__device__ inline double wg_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+__global__ void offdiag_part_kernel(const double* x, int ld, int n, double* part) {
+  __shared__ double sh[NT / 64];
+  double q = 0.0;
+  PS_GRID_LOOP(e, (size_t)n * n) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i != j) {
+      const double v = x[i + (size_t)j * ld];
+      q += v * v;
+    }
+  }
+  const double t = wg_sum(q, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void offdiag_sum_kernel(const double* part, double* out) {
+  __shared__ double sh[NT / 64];
+  double q = 0.0;
+  for (int e = threadIdx.x; e < kOffParts; e += blockDim.x) q += part[e];
+  const double t = wg_sum(q, sh);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+void offdiag_norm2(hipStream_t s, const double* x, int ld, int n, double* out) {
+  // out[0] receives the result; out[1 .. kOffParts] hold the partials
+  hipLaunchKernelGGL(offdiag_part_kernel, dim3(kOffParts), dim3(NT), 0, s, x, ld, n, out + 1);
+  hipLaunchKernelGGL(offdiag_sum_kernel, dim3(1), dim3(NT), 0, s, out + 1, out);
+  PS_HIP(hipGetLastError());
+}
+
 __global__ void copy_pad_kernel(const double* src, int lds, int rows, int cols, double* dst,
                                 int ldd, int rows_pad, int cols_pad) {
   PS_GRID_LOOP(e, (size_t)rows_pad * cols_pad) {

@@ -104,7 +104,7 @@ GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, 
 }
 
 namespace {
-thread_local GemmRecorder* g_rec = nullptr;   // per host thread (batched calls use several)
+thread_local KernelRecorder* g_rec = nullptr;   // per host thread (batched calls use several)
 
 template <class T, int BM, int BN, int WM, int WN>
 void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
@@ -133,8 +133,7 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
   bool use_c = false;
   for (int q = 0; q < g.count; ++q)
     use_c = use_c || (g.p[q].ksplit <= 1 && (g.p[q].beta_b || g.p[q].beta != 0.0));
-  const bool rec = BM == 128 && std::is_same<T, double>::value && g_rec && g_rec->n < g_rec->cap;
-  if (rec) PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n], s));
+  const int slot = krec_begin(s);
   if (use_c)
     hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN, true>), dim3(total),
                        dim3(WM * WN * 64), 0, s, g);
@@ -142,13 +141,6 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
     hipLaunchKernelGGL((gemm_mfma_kernel<T, BM, BN, WM, WN, false>), dim3(total),
                        dim3(WM * WN * 64), 0, s, g);
   PS_HIP(hipGetLastError());
-  if (rec) {
-    PS_HIP(hipEventRecord(g_rec->ev[2 * g_rec->n + 1], s));
-    double f = 0.0;
-    for (int q = 0; q < g.count; ++q) f += gemm_algorithmic_flops(g.p[q]);
-    g_rec->flops[g_rec->n] = f;
-    g_rec->n += 1;
-  }
   for (int q = 0; q < g.count; ++q) {
     const GemmProblemT<T>& p = g.p[q];
     if (p.ksplit > 1) {
@@ -158,11 +150,32 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
       PS_HIP(hipGetLastError());
     }
   }
+  if (slot >= 0) {   // the window covers the split-K reductions
+    double f = 0.0;
+    for (int q = 0; q < g.count; ++q) f += gemm_algorithmic_flops(g.p[q]);
+    const int cls = std::is_same<T, float>::value ? kKcGemm32 : (BM == 128 ? kKcGemm128 : kKcGemm64);
+    krec_end(s, slot, cls, f);
+  }
 }
 
 }  // namespace
 
-void gemm_set_recorder(GemmRecorder* r) { g_rec = r; }
+void kernel_set_recorder(KernelRecorder* r) { g_rec = r; }
+KernelRecorder* kernel_recorder() { return g_rec; }
+
+int krec_begin(hipStream_t s) {
+  if (!g_rec || g_rec->n >= g_rec->cap) return -1;
+  const int slot = g_rec->n++;
+  PS_HIP(hipEventRecord(g_rec->ev[2 * slot], s));
+  return slot;
+}
+
+void krec_end(hipStream_t s, int slot, int cls, double flops) {
+  if (!g_rec || slot < 0) return;
+  PS_HIP(hipEventRecord(g_rec->ev[2 * slot + 1], s));
+  g_rec->cls[slot] = cls;
+  g_rec->flops[slot] = flops;
+}
 
 // 2 x (number of structurally non-zero products) over the stored output entries.  For
 // each output (i, j) the K range is the intersection of the non-zero bands of op(A) row

@@ -36,19 +36,21 @@ void form_shifts_v(hipStream_t s, const double* g, double* z, int mp, const doub
 struct ps_handle_s {
   hipStream_t stream = nullptr;
   int device = 0;
-  void* own_ws = nullptr;
-  size_t own_bytes = 0;
-  void* user_ws = nullptr;
+  void* user_ws = nullptr;      // the caller's workspace (the library allocates none)
   size_t user_bytes = 0;
   double* pinned = nullptr;  // host staging for scalars
   hipEvent_t ev[10] = {};
   bool events = false;
-  std::vector<hipEvent_t> kev;  // per-launch GEMM timing (opts.timing == 2)
+  std::vector<hipEvent_t> kev;  // per-launch kernel timing (opts.timing == 2)
   std::vector<double> kflops;
-  hipStream_t side = nullptr;   // second stream: the FP32 shift group of a mixed step
+  std::vector<int> kcls;
+  // the caller's extra streams (ps_set_worker_streams): the first is also the second
+  // stream of a mixed step (FP32 shift group); without any, that work is serialized on
+  // `stream`
+  std::vector<hipStream_t> wstreams;
+  hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
-  bool owns_stream = false;     // worker handles of batched calls own their stream
-  std::vector<ps_handle_s*> workers;
+  std::vector<ps_handle_s*> workers;   // one per worker stream (batched calls, recursion)
 };
 
 namespace ps {
@@ -60,6 +62,12 @@ constexpr int kPinned = 1 << 16;  // doubles (host staging: up to m = 32768 valu
 // stream hand-offs than its arithmetic saves (measured on 256 problems of 32..512): such
 // problems run in FP64
 constexpr int kMixedMin = 1024;
+
+// whether a problem of half-size m runs the mixed-precision steps (and needs their FP32
+// buffers)
+inline bool mixed_arith(const ps_opts& o, int m) {
+  return o.precision == PS_PREC_MIXED && pad_to(m) >= kMixedMin;
+}
 
 struct Arena {
   char* base = nullptr;
@@ -201,7 +209,7 @@ struct EigBuffers {
 size_t eig_region_offset(int m, const ps_opts& o) {
   Arena a1, a2;
   Buffers b1, b2;
-  carve(a1, b1, m, resolve_r(o), 1, o.precision == PS_PREC_MIXED);
+  carve(a1, b1, m, resolve_r(o), 1, mixed_arith(o, m));
   carve(a2, b2, m, 8, 2);
   return std::max(a1.off, a2.off);
 }
@@ -261,7 +269,7 @@ size_t workspace_bytes(int m, const ps_opts& o, int what) {
     }
     return a.off + kAlign;
   }
-  carve(a, b, m, resolve_r(o), what, o.precision == PS_PREC_MIXED);
+  carve(a, b, m, resolve_r(o), what, mixed_arith(o, m));
   return a.off + kAlign;
 }
 
@@ -448,10 +456,12 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
   // the two groups' factorizations are latency-bound chains of launches: record both and
   // issue them alternately, so that neither waits for the host to enqueue the other
   LaunchList chain32, chain64;
-  hipStream_t s2 = mx.side;
+  hipStream_t s2 = mx.side ? mx.side : s;   // no second stream: both groups in order on s
   if (n32 > 0) {
-    PS_HIP(hipEventRecord(mx.fork, s));
-    PS_HIP(hipStreamWaitEvent(s2, mx.fork, 0));
+    if (s2 != s) {
+      PS_HIP(hipEventRecord(mx.fork, s));
+      PS_HIP(hipStreamWaitEvent(s2, mx.fork, 0));
+    }
     form_shifts_f32(s2, b.g, b.z32, mp, c32, n32);
     potrf_inv_f32(s2, b.z32, S, b.w32, S, mp, n32, dinfo32, &chain32);
   }
@@ -471,7 +481,7 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
       pn.ws = b.z32;
     }
     gemm_f32(s2, pn);
-    PS_HIP(hipEventRecord(mx.join, s2));
+    if (s2 != s) PS_HIP(hipEventRecord(mx.join, s2));
   }
   if (n64 > 0) {
     GemmProblem pn = gemm_problem(mp, mp, n64 * mp, b.w, mp, 0, b.w, mp, 1, b.nmat, mp, 1.0, 0.0,
@@ -485,7 +495,7 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
     fill_zero(s, b.nmat, b.S);
   }
   if (n32 > 0) {
-    PS_HIP(hipStreamWaitEvent(s, mx.join, 0));
+    if (s2 != s) PS_HIP(hipStreamWaitEvent(s, mx.join, 0));
     axpy_f32(s, b.nmat, 1.0, 1.0, b.n32, b.S);
   }
   GemmProblem px = gemm_problem(mp, mp, mp, x, mp, 0, b.nmat, mp, 0, xn, mp, co.chat, co.chat, x,
@@ -541,24 +551,23 @@ void estimate_bounds(hipStream_t s, Buffers& b, const double* ymats, int steps, 
   *beta = 0.99 / smax[1];
 }
 
-// The workspace (caller's, or the handle's own, grown on demand), aligned; null when
-// the caller's is too small.
+// The caller's workspace (ps_set_workspace, 256-byte aligned), or null when there is
+// none or it is smaller than `need`: the library never allocates device memory.
 char* workspace_base(ps_handle h, size_t need) {
-  char* base;
-  if (h->user_ws) {
-    if (h->user_bytes < need) return nullptr;
-    base = (char*)h->user_ws;
-  } else {
-    if (h->own_bytes < need) {
-      if (h->own_ws) PS_HIP(hipFree(h->own_ws));
-      h->own_ws = nullptr;
-      h->own_bytes = 0;
-      PS_HIP(hipMalloc(&h->own_ws, need));
-      h->own_bytes = need;
-    }
-    base = (char*)h->own_ws;
+  if (!h->user_ws || h->user_bytes < need) return nullptr;
+  return (char*)h->user_ws;
+}
+
+// Worker handles bound to the caller's worker streams (created on first use; they hold
+// host staging and events only, and borrow their streams).
+int ensure_workers(ps_handle h, int n) {
+  n = std::min(n, (int)h->wstreams.size());
+  while ((int)h->workers.size() < n) {
+    ps_handle w = nullptr;
+    if (ps_create(&w, h->wstreams[h->workers.size()]) != PS_OK) return -1;
+    h->workers.push_back(w);
   }
-  return (char*)(((uintptr_t)base + kAlign - 1) / kAlign * kAlign);
+  return n;
 }
 
 // The Zolotarev iteration of Alg. 8 on the core matrix y (padded b.mp x b.mp, zero
@@ -644,7 +653,7 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
       auto_split(pg, b.splitws);
       gemm_f64(s, pg);
       spd_pad(s, b.g, b.z, b.m, mp, 0.0);
-      potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, 1, b.dinfo + 3);
+      potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, 1, b.dinfo + 3, true, nullptr, b.z + S, S);
       // estimator pair: y = [X2, W_G]
       PS_HIP(hipMemcpyAsync(b.y, b.x2, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
       PS_HIP(hipMemcpyAsync(b.y + S, b.w, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -661,17 +670,18 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
 }
 
 int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
-        int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what) {
+        int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what,
+        char* ws = nullptr) {
   hipStream_t s = h->stream;
   const int r = resolve_r(o);
-  // workspace
-  char* base = workspace_base(h, workspace_bytes(m, o, what));
+  // workspace: the caller's (or `ws`, which the caller has checked for size)
+  char* base = ws ? ws : workspace_base(h, workspace_bytes(m, o, what));
   if (!base) return PS_NO_WORKSPACE;
   Arena ar;
   ar.base = base;
   ar.dry = false;
   Buffers b;
-  carve(ar, b, m, r, what, o.precision == PS_PREC_MIXED);
+  carve(ar, b, m, r, what, mixed_arith(o, m));
   const int mp = b.mp;
   const long long S = (long long)b.S;
   double* pin = h->pinned;
@@ -681,12 +691,12 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   inf.r = r;
   Timer tm{h, o.timing != 0};
   tm.mark(-1);
-  GemmRecorder grec;
+  KernelRecorder grec;
   struct RecGuard {
-    ~RecGuard() { gemm_set_recorder(nullptr); }
+    ~RecGuard() { kernel_set_recorder(nullptr); }
   } rec_guard;
   if (o.timing >= 2) {
-    const int cap = 256;
+    const int cap = 1024;
     if ((int)h->kev.size() < 2 * cap) {
       while ((int)h->kev.size() < 2 * cap) {
         hipEvent_t e;
@@ -695,16 +705,18 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
       }
     }
     h->kflops.assign(cap, 0.0);
+    h->kcls.assign(cap, -1);
     grec.ev = h->kev.data();
     grec.flops = h->kflops.data();
+    grec.cls = h->kcls.data();
     grec.cap = cap;
-    gemm_set_recorder(&grec);
+    kernel_set_recorder(&grec);
   }
 
   fill_int_zero(s, b.dinfo, 16);
   // ---- setup: M = A + B = R_M^T R_M, K = A - B = R_K^T R_K, Y0 = R_M R_K^T, Y0^{-1} = W_K^T W_M
   pack_casida(s, m, mp, A, lda, B, ldb, b.mk);
-  potrf_inv_f64(s, b.mk, S, b.wmk, S, b.tmp, mp, 2, b.dinfo + 0);
+  potrf_inv_f64(s, b.mk, S, b.wmk, S, b.tmp, mp, 2, b.dinfo + 0, true, nullptr, b.y, S);
   {
     GemmProblem pg[2];
     pg[0] = gemm_problem(mp, mp, mp, b.mk, mp, 0, b.mk + S, mp, 1, b.y, mp, 1.0, 0.0, nullptr, 0,
@@ -742,7 +754,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
 
   // ---- Zolotarev steps with the stopping test of Alg. 8
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
-  const bool mixed = o.precision == PS_PREC_MIXED && mp >= kMixedMin;
+  const bool mixed = mixed_arith(o, m);
   const int status =
       polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm, mixed ? &mxc : nullptr);
   if (status != PS_OK) {
@@ -772,7 +784,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     auto_split(pv, b.splitws);
     gemm_f64(s, pv);
     sym_scale_upper(s, b.t2, b.p11, m, mp, 1.0);              // upper(G), padding I
-    potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4);
+    potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4, true, nullptr, b.t2, S);
     {
       GemmProblem pe[2];
       pe[0] = gemm_problem(mp, mp, mp, b.t1, mp, 0, b.wc, mp, 0, b.t2, mp, 1.0, 0.0, nullptr, 0,
@@ -817,7 +829,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   } else {
     // ---- Alg. 6: C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
     half_shift_upper(s, b.as, b.p11, mp);
-    potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4);
+    potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4, true, nullptr, b.t1, S);
     {
       GemmProblem pq = gemm_problem(mp, mp, mp, b.bs, mp, 0, b.wc, mp, 0, b.qbot, mp, -0.5, 0.0,
                                     nullptr, 0, kBUpper);
@@ -861,12 +873,17 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   }
   tm.finish(inf.phase_ms);
   for (int q = 0; q < grec.n; ++q) {
+    const int c = grec.cls[q];
+    if (c < 0 || c >= kKcCount) continue;
     float t = 0.f;
     PS_HIP(hipEventElapsedTime(&t, grec.ev[2 * q], grec.ev[2 * q + 1]));
-    inf.gemm_ms += t;
-    inf.gemm_flops += grec.flops[q];
+    inf.kclass_launches[c] += 1;
+    inf.kclass_ms[c] += t;
+    inf.kclass_flops[c] += grec.flops[q];
   }
-  inf.gemm_launches = grec.n;
+  inf.gemm_launches = inf.kclass_launches[kKcGemm128];
+  inf.gemm_ms = inf.kclass_ms[kKcGemm128];
+  inf.gemm_flops = inf.kclass_flops[kKcGemm128];
   inf.status = PS_OK;
   if (info) *info = inf;
   return PS_OK;
@@ -922,11 +939,25 @@ int eig_split(const SplitCtx& c, const EigBuffers& gl, int m, int o, int n, cons
     gemm_f64(s, pa);
   }
   get_diag(s, e.zbd, np, n, e.dscratch);
+  offdiag_norm2(s, e.zbd, np, n, b.norms);
   PS_HIP(hipMemcpyAsync(pin, e.dscratch, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipMemcpyAsync(pin + n, b.norms, sizeof(double), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
+  const double off = std::sqrt(std::max(0.0, pin[n]));
   std::vector<double> dg(pin, pin + n);
   std::sort(dg.begin(), dg.end());
   const double lo = dg.front(), hi = dg.back();
+  // A block whose eigenvalues all lie within (hi - lo) + 2 ||offdiag||_F of each other,
+  // at most kClusterTol of its magnitude, is lambda I to that accuracy: every basis is an
+  // eigenbasis, no shift can split it, and any split loses at most that much.  Its
+  // columns are halved as they are (the halves end as leaves of this same kind or as
+  // Jacobi leaves, which diagonalize what coupling is left).
+  constexpr double kClusterTol = 1e-12;
+  if ((hi - lo) + 2.0 * off <= kClusterTol * std::max(std::fabs(lo), std::fabs(hi))) {
+    *rminus = n / 2;
+    inf.eig_clusters += 1;
+    return PS_OK;
+  }
   double sigma = (n & 1) ? dg[n / 2] : 0.5 * (dg[n / 2 - 1] + dg[n / 2]);
   int rp = 0;
   bool ok = false;
@@ -948,7 +979,8 @@ int eig_split(const SplitCtx& c, const EigBuffers& gl, int m, int o, int n, cons
       auto_split(pg, b.splitws);
       gemm_f64(s, pg);
       spd_pad(s, b.g, b.z, n, np, 0.0);
-      potrf_inv_f64(s, b.z, Sn, b.w, Sn, b.tmp, np, 1, b.dinfo + 3);
+      potrf_inv_f64(s, b.z, Sn, b.w, Sn, b.tmp, np, 1, b.dinfo + 3, true, nullptr, b.z + Sn,
+                    Sn);
       PS_HIP(hipMemcpyAsync(b.y + Sn, b.w, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     // the estimator pair overwrites b.y: keep Y in x1 meanwhile
@@ -1006,8 +1038,8 @@ int eig_split(const SplitCtx& c, const EigBuffers& gl, int m, int o, int n, cons
   gather_sym(s, U, np, pm, pp, rm, rp, 0.5, 0.5, z[1], npm, npm, npp, 0.0, 0);
   gather_sym(s, U, np, pm, pm, rm, rm, -0.5, 0.5, z[3], npm, npm, npm, 1.0, 1);
   gather_sym(s, U, np, pp, pm, rp, rm, -0.5, 0.5, z[4], npp, npp, npm, 0.0, 0);
-  potrf_inv_f64(s, z[0], 0, w[0], 0, b.tmp, npp, 1, b.dinfo + 4);
-  potrf_inv_f64(s, z[3], 0, w[1], 0, b.tmp, npm, 1, b.dinfo + 5);
+  potrf_inv_f64(s, z[0], 0, w[0], 0, b.tmp, npp, 1, b.dinfo + 4, true, nullptr, w[3], 0);
+  potrf_inv_f64(s, z[3], 0, w[1], 0, b.tmp, npm, 1, b.dinfo + 5, true, nullptr, w[4], 0);
   {
     GemmProblem q1 = gemm_problem(npm, npp, npp, z[1], npm, 0, w[0], npp, 0, z[2], npm, 1.0, 0.0,
                                   nullptr, 0, kBUpper);
@@ -1029,7 +1061,7 @@ int eig_split(const SplitCtx& c, const EigBuffers& gl, int m, int o, int n, cons
     auto_split(pg, b.splitws);
     gemm_f64(s, pg);
     spd_pad(s, b.g, z[7], n, np, 0.0);
-    potrf_inv_f64(s, z[7], 0, w[2], 0, b.tmp, np, 1, b.dinfo + 6);
+    potrf_inv_f64(s, z[7], 0, w[2], 0, b.tmp, np, 1, b.dinfo + 6, true, nullptr, w[3], 0);
     GemmProblem pq = gemm_problem(np, np, np, z[6], np, 0, w[2], np, 0, b.x0, np, 1.0, 0.0,
                                   nullptr, 0, kBUpper);
     gemm_f64(s, pq);
@@ -1077,7 +1109,7 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
     ra.base = base;
     ra.dry = false;
     Buffers db;
-    carve(ra, db, m, resolve_r(o), 1, o.precision == PS_PREC_MIXED);
+    carve(ra, db, m, resolve_r(o), 1, mixed_arith(o, m));
     copy_out(s, db.as, mp, SA, lds, m, m);
     copy_out(s, db.bs, mp, SB, lds, m, m);
   }
@@ -1117,20 +1149,17 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
   }
   if (!subtrees.empty()) {
     PS_HIP(hipStreamSynchronize(s));   // the workers' streams start from the current V
-    const int nw = kEigWorkers;
-    while ((int)h->workers.size() < nw) {
-      hipStream_t ws;
-      PS_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
-      ps_handle w = nullptr;
-      if (ps_create(&w, ws) != PS_OK) {
-        (void)hipStreamDestroy(ws);
-        return PS_HIP_ERROR;
-      }
-      w->owns_stream = true;
-      h->workers.push_back(w);
-    }
+    // the caller's worker streams (up to kEigWorkers); without any, the subtrees run on
+    // the handle's own stream and scratch, one after the other
+    const int nwk = ensure_workers(h, kEigWorkers);
+    if (nwk < 0) return PS_HIP_ERROR;
+    const int nw = std::max(1, nwk);
     std::vector<SplitCtx> ctx(nw);
     for (int k = 0; k < nw; ++k) {
+      if (nwk == 0) {
+        ctx[k] = main_ctx;
+        continue;
+      }
       ctx[k].s = h->workers[k]->stream;
       ctx[k].pin = h->workers[k]->pinned;
       carve_eig_worker(ea, m, &ctx[k].base, &ctx[k].vs, &ctx[k].t, &ctx[k].zbd,
@@ -1203,6 +1232,7 @@ int run_eig(ps_handle h, int m, const double* A, int lda, const double* B, int l
     for (auto& t : threads) t.join();
     for (int k = 0; k < nw; ++k) {
       inf.eig_splits += winf[k].eig_splits;
+      inf.eig_clusters += winf[k].eig_clusters;
       inf.eig_steps += winf[k].eig_steps;
       inf.eig_restarts += winf[k].eig_restarts;
       leaves.insert(leaves.end(), wleaves[k].begin(), wleaves[k].end());
@@ -1420,16 +1450,66 @@ size_t class_bytes(int nb, int mp, int r) {
   return a.off + kAlign;
 }
 
-// At most this many problems per class, and at most kClassBytes of workspace for one
-// (about (37 + 2r) mp^2 doubles per problem).  Measured on 256 problems of m = 32..512
-// (about 32 per padded size): classes of 8, 16, 32, 64: 41, 36, 33, 32 ms.
+// At most this many problems per class, and at most the worker's share of the
+// workspace for one (about (37 + 2r) mp^2 doubles per problem).  Measured on 256
+// problems of m = 32..512 (about 32 per padded size): classes of 8, 16, 32, 64: 41, 36,
+// 33, 32 ms.  kClassBytes is the share per worker that ps_workspace_size_batched asks
+// for (classes of 19 at padded size 512, 32 from 384 down).
 constexpr int kClassMax = 32;
-constexpr size_t kClassBytes = (size_t)3 << 30;
+constexpr size_t kClassBytes = (size_t)2 << 30;
 
-int class_limit(int mp, int r) {
-  const size_t one = class_bytes(1, mp, r);
-  const size_t fit = kClassBytes / (one ? one : 1);
-  return (int)std::min<size_t>(kClassMax, fit);
+int class_limit(int mp, int r, size_t region) {
+  int nb = 1;
+  while (nb < kClassMax && class_bytes(nb + 1, mp, r) <= region) ++nb;
+  return class_bytes(nb, mp, r) <= region ? nb : 0;
+}
+
+// Jobs of a batched call, largest problems first: in FP64 arithmetic (mixed requests
+// below the mixed threshold run in FP64 anyway) problems of one padded size form
+// classes of up to kClassMax that fit `region` bytes and run as one batched pipeline;
+// everything else, and what a class hands back, runs one problem at a time.
+std::vector<std::vector<int>> plan_batch(int batch, const int* m, const ps_opts& o,
+                                         size_t region) {
+  const bool classes = o.max_steps != 1 && o.timing == 0 &&
+                       (o.precision == PS_PREC_FP64 || o.precision == PS_PREC_MIXED);
+  std::vector<std::vector<int>> jobs;
+  std::vector<int> order(batch);
+  for (int i = 0; i < batch; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m[x] > m[y]; });
+  size_t i = 0;
+  while (i < order.size()) {
+    const int mp = pad_to(m[order[i]]);
+    size_t j = i;
+    while (j < order.size() && pad_to(m[order[j]]) == mp) ++j;
+    const int lim = classes ? class_limit(mp, resolve_r(o), region) : 0;
+    const bool cls = classes && j - i >= 2 && lim >= 2 &&
+                     (o.precision == PS_PREC_FP64 || mp < kMixedMin);
+    if (cls) {
+      for (size_t a = i; a < j; a += lim)
+        jobs.emplace_back(order.begin() + a, order.begin() + std::min(j, a + (size_t)lim));
+    } else {
+      for (size_t a = i; a < j; ++a) jobs.push_back({order[a]});
+    }
+    i = j;
+  }
+  return jobs;
+}
+
+size_t max_single_bytes(int batch, const int* m, const ps_opts& o) {
+  size_t need = 0;
+  for (int i = 0; i < batch; ++i) need = std::max(need, workspace_bytes(m[i], o, 1));
+  return need;
+}
+
+// Workspace of a batched call with `nw` workers: nw regions, each holding the largest
+// single problem and the largest class planned within kClassBytes.
+size_t batched_bytes(int batch, const int* m, const ps_opts& o, int nw) {
+  size_t region = max_single_bytes(batch, m, o);
+  for (const auto& job : plan_batch(batch, m, o, std::max(region, kClassBytes)))
+    if (job.size() > 1)
+      region = std::max(region, class_bytes((int)job.size(), pad_to(m[job[0]]), resolve_r(o)));
+  region = (region + kAlign - 1) / kAlign * kAlign;
+  return (size_t)nw * region;
 }
 
 int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const double* const* A,
@@ -1721,6 +1801,8 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
       inf.ell[1] = std::min(c1[b].ell_next, 1.0 - 1e-15);
       inf.step_change = change[b];
       inf.step2_terms = P;
+      inf.shifts_fp64[0] = r;    // classes run every shift of step 1 in FP64
+      inf.shifts_fp64[1] = 0;    // step 2 by the series
     }
   }
   PS_HIP(hipStreamSynchronize(s));
@@ -1730,54 +1812,38 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
 int run_batched(ps_handle h, int batch, const int* m, const double* const* A, const int* lda,
                 const double* const* B, const int* ldb, double* const* Qp, const int* ldq,
                 double* const* Hp, const int* ldh, const ps_opts& o, ps_info* infos) {
-  const int nw = std::min(kWorkers, batch);
-  while ((int)h->workers.size() < nw) {
-    hipStream_t st;
-    PS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    ps_handle w = nullptr;
-    if (ps_create(&w, st) != PS_OK) {
-      (void)hipStreamDestroy(st);
-      return PS_HIP_ERROR;
+  // Workers: one per caller worker stream (up to kWorkers), each with an equal share of
+  // the caller's workspace that holds the largest single problem (fewer workers if the
+  // shares would not); without worker streams the handle itself is the one worker.
+  if (!h->user_ws) return PS_NO_WORKSPACE;
+  const int nwk = ensure_workers(h, std::min(kWorkers, batch));
+  if (nwk < 0) return PS_HIP_ERROR;
+  int nw = std::max(1, nwk);
+  const size_t single = max_single_bytes(batch, m, o);
+  auto share = [&](int n) { return h->user_bytes / (size_t)n / kAlign * kAlign; };
+  while (nw > 1 && share(nw) < single) --nw;
+  const size_t region = share(nw);
+  if (region < single) return PS_NO_WORKSPACE;
+  std::vector<ps_handle> wk;
+  if (nwk == 0) {
+    wk.push_back(h);
+  } else {
+    for (int k = 0; k < nw; ++k) {
+      ps_handle w = h->workers[k];
+      w->user_ws = (char*)h->user_ws + (size_t)k * region;
+      w->user_bytes = region;
+      wk.push_back(w);
     }
-    w->owns_stream = true;
-    h->workers.push_back(w);
+    // the inputs may still be in flight on the caller's stream
+    PS_HIP(hipEventRecord(h->fork, h->stream));
+    for (int k = 0; k < nw; ++k) PS_HIP(hipStreamWaitEvent(wk[k]->stream, h->fork, 0));
   }
-  // the inputs may still be in flight on the caller's stream
-  PS_HIP(hipEventRecord(h->fork, h->stream));
-  for (int k = 0; k < nw; ++k) PS_HIP(hipStreamWaitEvent(h->workers[k]->stream, h->fork, 0));
-  // Jobs, largest first: in FP64 arithmetic (mixed requests below the mixed threshold
-  // run in FP64 anyway), problems of one padded size form classes of
-  // up to kClassMax that run as one batched pipeline; everything else, and what a class
-  // hands back, runs one problem at a time.
-  const bool classes = o.max_steps != 1 && o.timing == 0 &&
-                       (o.precision == PS_PREC_FP64 || o.precision == PS_PREC_MIXED);
-  std::vector<std::vector<int>> jobs;
-  {
-    std::vector<int> order(batch);
-    for (int i = 0; i < batch; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m[x] > m[y]; });
-    size_t i = 0;
-    while (i < order.size()) {
-      const int mp = pad_to(m[order[i]]);
-      size_t j = i;
-      while (j < order.size() && pad_to(m[order[j]]) == mp) ++j;
-      const int lim = class_limit(mp, resolve_r(o));
-      const bool cls = classes && j - i >= 2 && lim >= 2 &&
-                       (o.precision == PS_PREC_FP64 || mp < kMixedMin);
-      if (cls) {
-        for (size_t a = i; a < j; a += lim)
-          jobs.emplace_back(order.begin() + a, order.begin() + std::min(j, a + (size_t)lim));
-      } else {
-        for (size_t a = i; a < j; ++a) jobs.push_back({order[a]});
-      }
-      i = j;
-    }
-  }
+  const std::vector<std::vector<int>> jobs = plan_batch(batch, m, o, region);
   std::vector<int> status(batch, PS_OK);
   std::atomic<int> next{0};
   const int njobs = (int)jobs.size();
   auto work = [&](int k) {
-    ps_handle w = h->workers[k];
+    ps_handle w = wk[k];
     if (hipSetDevice(h->device) != hipSuccess) {
       for (int i; (i = next.fetch_add(1)) < njobs;)
         for (int p : jobs[i]) status[p] = PS_HIP_ERROR;
@@ -1859,8 +1925,7 @@ int ps_create(ps_handle* h, void* stream) {
       return PS_HIP_ERROR;
     }
   p->events = true;
-  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
+  if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess) {
     delete p;
     return PS_HIP_ERROR;
@@ -1873,23 +1938,14 @@ int ps_destroy(ps_handle h) {
   if (!h) return -1;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
-  if (h->own_ws) (void)hipFree(h->own_ws);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->events)
     for (auto& e : h->ev) (void)hipEventDestroy(e);
   for (auto& e : h->kev) (void)hipEventDestroy(e);
-  if (h->side) {
-    (void)hipStreamSynchronize(h->side);
-    (void)hipStreamDestroy(h->side);
-  }
+  if (h->side) (void)hipStreamSynchronize(h->side);   // borrowed: the caller's stream
   if (h->fork) (void)hipEventDestroy(h->fork);
   if (h->join) (void)hipEventDestroy(h->join);
-  for (ps_handle w : h->workers) {
-    hipStream_t st = w->stream;
-    const bool own = w->owns_stream;
-    (void)ps_destroy(w);
-    if (own && st) (void)hipStreamDestroy(st);
-  }
+  for (ps_handle w : h->workers) (void)ps_destroy(w);   // their streams are the caller's
   delete h;
   return PS_OK;
 }
@@ -1913,6 +1969,39 @@ int ps_set_workspace(ps_handle h, void* dptr, size_t bytes) {
   if (dptr && ((uintptr_t)dptr % kAlign)) return -2;
   h->user_ws = dptr;
   h->user_bytes = dptr ? bytes : 0;
+  return PS_OK;
+}
+
+size_t ps_workspace_size_batched(int batch, const int* m, const ps_opts* o) {
+  if (batch < 1 || !m) return 0;
+  for (int i = 0; i < batch; ++i)
+    if (m[i] < 1) return 0;
+  ps_opts d;
+  ps_opts_default(&d);
+  if (o) d = *o;
+  d.max_steps = 0;
+  d.timing = 0;
+  return batched_bytes(batch, m, d, std::min(kWorkers, batch)) + kAlign;
+}
+
+int ps_set_worker_streams(ps_handle h, int count, void* const* streams) {
+  if (!h) return -1;
+  if (count < 0 || count > PS_MAX_WORKER_STREAMS) return -2;
+  if (count > 0 && !streams) return -3;
+  for (int k = 0; k < count; ++k)
+    if (!streams[k] || streams[k] == (void*)h->stream) return -3;
+  try {
+    if (h->stream) PS_HIP(hipStreamSynchronize(h->stream));
+    for (ps_handle w : h->workers) {
+      if (w->stream) PS_HIP(hipStreamSynchronize(w->stream));
+      (void)ps_destroy(w);
+    }
+  } catch (const HipError&) {
+    return PS_HIP_ERROR;
+  }
+  h->workers.clear();
+  h->wstreams.assign((hipStream_t*)streams, (hipStream_t*)streams + count);
+  h->side = count > 0 ? h->wstreams[0] : nullptr;
   return PS_OK;
 }
 

@@ -88,15 +88,31 @@ GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, 
                           double beta = 0.0, const float* C = nullptr, int ldc = 0,
                           int flags = 0);
 
-// Optional per-launch timing of the large-tile GEMM kernel: when set, gemm_f64 brackets
-// each such launch with events from this recorder and adds the algorithmic flops.
-struct GemmRecorder {
+// Optional per-launch timing of the matrix-core kernels: when a recorder is set (for the
+// calling host thread), every launch of a recorded class is bracketed by a pair of
+// events on its own stream (a GEMM's window also covers its split-K reduction) and its
+// algorithmic flops are noted.  Classes (ps_info.kclass_*):
+enum KernelClass : int {
+  kKcCholWide = 0,     // chol_step_kernel<double, wide>   (one or two matrices)
+  kKcCholNarrow = 1,   // chol_step_kernel<double, narrow> (more matrices)
+  kKcChol32 = 2,       // chol_step_kernel<float, *>
+  kKcGemm128 = 3,      // FP64 GEMM, 128 x 128 tiles
+  kKcGemm64 = 4,       // FP64 GEMM, 64 x 64 tiles
+  kKcGemm32 = 5,       // FP32 GEMM, either tile
+  kKcCount = 8
+};
+struct KernelRecorder {
   hipEvent_t* ev = nullptr;   // pairs (start, stop)
   double* flops = nullptr;    // per recorded launch
+  int* cls = nullptr;         // class per recorded launch
   int cap = 0;                // number of pairs available
   int n = 0;                  // pairs used
 };
-void gemm_set_recorder(GemmRecorder* r);
+void kernel_set_recorder(KernelRecorder* r);
+KernelRecorder* kernel_recorder();
+// start / stop of one recorded launch on stream s (no-ops without a recorder or room)
+int krec_begin(hipStream_t s);
+void krec_end(hipStream_t s, int slot, int cls, double flops);
 template <class T>
 double gemm_algorithmic_flops(const GemmProblemT<T>& p);
 
@@ -121,10 +137,12 @@ void issue_interleaved(LaunchList& a, LaunchList& b);
 // matrix stride sz) with the strictly lower part zero on entry, producing the
 // inverse factor W = R^{-1} (upper) in `w` (stride sw).  `tmp` is unused.  A
 // non-positive pivot in matrix b sets bit min(b, 30) of the device int *info.  With
-// `defer`, the launches are appended there instead of issued.
+// `defer`, the launches are appended there instead of issued.  With `v` (mp x mp per
+// matrix, stride sv, contents irrelevant, clobbered) and one or two matrices below the
+// outer-block size, W is formed alongside the factorization instead of afterwards.
 void potrf_inv_f64(hipStream_t s, double* z, long long sz, double* w, long long sw,
                    double* tmp, int mp, int batch, int* info, bool inverse = true,
-                   LaunchList* defer = nullptr);
+                   LaunchList* defer = nullptr, double* v = nullptr, long long sv = 0);
 // the same in FP32 (pivots taken and inverted through FP64 square roots)
 void potrf_inv_f32(hipStream_t s, float* z, long long sz, float* w, long long sw, int mp,
                    int batch, int* info, LaunchList* defer = nullptr);
@@ -173,6 +191,9 @@ void shift_diag(hipStream_t s, double* y, int ld, int n, double b);   // y(i,i) 
 // z = upper(g) + c I on the first n diagonal entries, 1 on the padded diagonal
 void spd_pad(hipStream_t s, const double* g, double* z, int n, int np, double c);
 void get_diag(hipStream_t s, const double* x, int ld, int n, double* out);
+// out[0] = sum of squares of the off-diagonal entries of the leading n x n block of x;
+// out must hold 1 + 256 doubles
+void offdiag_norm2(hipStream_t s, const double* x, int ld, int n, double* out);
 // dst(i,j) = src(i,j) for i < rows, j < cols, 0 elsewhere in rows_pad x cols_pad
 void copy_pad(hipStream_t s, const double* src, int lds, int rows, int cols, double* dst,
               int ldd, int rows_pad, int cols_pad);

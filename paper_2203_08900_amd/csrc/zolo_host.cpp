@@ -11,8 +11,10 @@
 // transformations (Abramowitz & Stegun 16.4 and 17.6).  The AGM is started from
 // b_0 = l itself, the complementary modulus of l', so the parameter 1 - l^2 never
 // has to be formed.  The back-recurrence evaluates asin close to +-1 when l is tiny,
-// which amplifies rounding by about 1/sqrt(l), so the whole computation runs in
-// IEEE quadruple precision (113-bit significand) and is rounded to double once.
+// which amplifies rounding by about 1/sqrt(l): for l >= 1e-4 (amplification <= 100)
+// the x87 extended format (64-bit significand, rounding 5.4e-20) keeps the result far
+// below double rounding and runs on the hardware; smaller l use IEEE quadruple
+// precision (113-bit significand, software).  Both round to double once at the end.
 // This file is host-only C++ (compiled by the host compiler, linked to libquadmath).
 #include <quadmath.h>
 
@@ -24,20 +26,45 @@
 namespace ps {
 
 namespace {
-using ld = __float128;
-const ld kPi = M_PIq;
+// the elementary functions of each working format
+struct Ext {
+  using T = long double;
+  static T sqrt_(T x) { return sqrtl(x); }
+  static T abs_(T x) { return fabsl(x); }
+  static T asin_(T x) { return asinl(x); }
+  static T sin_(T x) { return sinl(x); }
+  static T tan_(T x) { return tanl(x); }
+  static T ldexp_(T x, int e) { return ldexpl(x, e); }
+  static T pi() { return 3.141592653589793238462643383279502884L; }
+  static T eps() { return std::numeric_limits<long double>::epsilon(); }
+};
+struct Quad {
+  using T = __float128;
+  static T sqrt_(T x) { return sqrtq(x); }
+  static T abs_(T x) { return fabsq(x); }
+  static T asin_(T x) { return asinq(x); }
+  static T sin_(T x) { return sinq(x); }
+  static T tan_(T x) { return tanq(x); }
+  static T ldexp_(T x, int e) { return ldexpq(x, e); }
+  static T pi() { return M_PIq; }
+  static T eps() { return FLT128_EPSILON; }
+};
 
-// tan(phi_0) for u = i K'/(2r+1) with modulus k' whose complementary modulus is l
-void sc_values(ld ell, int r, ld* sc2 /* 2r values: (sn/cn)^2 at u_1..u_2r */) {
-  ld a[64], c[64];
-  ld an = 1, bn = ell, cn = sqrtq((1 - ell) * (1 + ell));
+// (sn/cn)^2 at u_i = i K'/(2r+1), i = 1..r (the upper half follows from the reflection
+// c_i c_{2r+1-i} = l^2), for modulus k' whose complementary modulus is l
+template <class F>
+void sc_values(double ell_d, int r, typename F::T* sc2) {
+  using T = typename F::T;
+  const T ell = ell_d;
+  T a[64], c[64];
+  T an = 1, bn = ell, cn = F::sqrt_((1 - ell) * (1 + ell));
   int N = 0;
   a[0] = an;
   c[0] = cn;
-  while (fabsq(cn) > 4 * FLT128_EPSILON * an && N < 60) {
-    const ld a1 = (an + bn) / 2;
-    const ld b1 = sqrtq(an * bn);
-    const ld c1 = (an - bn) / 2;
+  while (F::abs_(cn) > 4 * F::eps() * an && N < 60) {
+    const T a1 = (an + bn) / 2;
+    const T b1 = F::sqrt_(an * bn);
+    const T c1 = (an - bn) / 2;
     an = a1;
     bn = b1;
     cn = c1;
@@ -46,44 +73,51 @@ void sc_values(ld ell, int r, ld* sc2 /* 2r values: (sn/cn)^2 at u_1..u_2r */) {
     c[N] = cn;
   }
   // K' = pi / (2 a_N);  phi_N = 2^N a_N u_i = 2^(N-1) i pi / (2r+1)
-  for (int i = 1; i <= 2 * r; ++i) {
-    ld phi = ldexpq(kPi * (ld)i / (ld)(2 * r + 1), N - 1);
-    for (int n = N; n >= 1; --n) phi = (phi + asinq(c[n] / a[n] * sinq(phi))) / 2;
-    const ld t = tanq(phi);
+  for (int i = 1; i <= r; ++i) {
+    T phi = F::ldexp_(F::pi() * (T)i / (T)(2 * r + 1), N - 1);
+    for (int n = N; n >= 1; --n) phi = (phi + F::asin_(c[n] / a[n] * F::sin_(phi))) / 2;
+    const T t = F::tan_(phi);
     sc2[i - 1] = t * t;
   }
 }
-}  // namespace
 
-int zolotarev_host(double ell_in, int r, ZoloHost* out) {
-  if (!(ell_in > 0.0) || !(ell_in < 1.0) || r < 1 || r > 8 || !out) return -1;
-  const ld ell = ell_in;
-  ld sc2[16];
-  sc_values(ell, r, sc2);
-  ld c[16];
-  for (int i = 0; i < 2 * r; ++i) c[i] = ell * ell * sc2[i];
-  // the reflection c_i c_{2r+1-i} = l^2 holds exactly; use it for the upper half,
-  // where cn is small and tan(phi_0) is least accurate
+template <class F>
+void coefficients(double ell_in, int r, ZoloHost* out) {
+  using T = typename F::T;
+  const T ell = ell_in;
+  T sc2[16];
+  sc_values<F>(ell_in, r, sc2);
+  T c[16];
+  for (int i = 0; i < r; ++i) c[i] = ell * ell * sc2[i];
   for (int i = r + 1; i <= 2 * r; ++i) c[i - 1] = ell * ell / c[2 * r - i];
-  ld chat = 1, zl = ell;
+  T chat = 1, zl = ell;
   for (int j = 0; j < r; ++j) {
     chat *= (1 + c[2 * j]) / (1 + c[2 * j + 1]);
     zl *= (ell * ell + c[2 * j + 1]) / (ell * ell + c[2 * j]);
   }
   zl *= chat;
   for (int j = 0; j < r; ++j) {
-    ld num = 1, den = 1;
+    T num = 1, den = 1;
     for (int k = 0; k < r; ++k) {
       num *= c[2 * j] - c[2 * k + 1];
       if (k != j) den *= c[2 * j] - c[2 * k];
     }
     out->a[j] = (double)(-num / den);
   }
-  out->r = r;
-  out->ell = ell_in;
   for (int i = 0; i < 2 * r; ++i) out->c[i] = (double)c[i];
   out->chat = (double)chat;
   out->ell_next = (double)zl;
+}
+}  // namespace
+
+int zolotarev_host(double ell_in, int r, ZoloHost* out) {
+  if (!(ell_in > 0.0) || !(ell_in < 1.0) || r < 1 || r > 8 || !out) return -1;
+  if (ell_in >= 1e-4)
+    coefficients<Ext>(ell_in, r, out);
+  else
+    coefficients<Quad>(ell_in, r, out);
+  out->r = r;
+  out->ell = ell_in;
   return 0;
 }
 

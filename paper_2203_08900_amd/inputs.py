@@ -102,8 +102,13 @@ def batched(count: int = 256, seed: int = 2):
     return [small_dense(mi, i) for i, mi in enumerate(batched_sizes(count, seed))]
 
 
-def ill_separated(m: int, seed: int, mu_lo: float = 1e-6, mu_hi: float = 1.0):
-    """Blocks whose (A-B)(A+B) has eigenvalues exactly mu (log-uniform, ends pinned)."""
+def ill_separated(m: int, seed: int, mu_lo: float = 1e-6, mu_hi: float = 1.0,
+                  return_factors: bool = False):
+    """Blocks whose (A-B)(A+B) has eigenvalues exactly mu (log-uniform, ends pinned).
+
+    With ``return_factors`` also returns the draws the blocks are built from,
+    (q_M, d_M, q, mu) in draw order (mu unsorted), for references that use the
+    construction itself."""
     rng = np.random.default_rng(seed)
     qm = haar(rng, m)
     dm = rng.uniform(1.0, 2.0, m)
@@ -117,6 +122,9 @@ def ill_separated(m: int, seed: int, mu_lo: float = 1e-6, mu_hi: float = 1.0):
     k = _sym(m_inv_half @ kcore @ m_inv_half)
     a = _sym(0.5 * (mmat + k))
     b = _sym(0.5 * (mmat - k))
+    if return_factors:
+        return (np.ascontiguousarray(a), np.ascontiguousarray(b), np.sort(mu),
+                (qm, dm, q, mu.copy()))
     return np.ascontiguousarray(a), np.ascontiguousarray(b), np.sort(mu)
 
 

@@ -57,9 +57,12 @@ def test_batched_mixed_and_empty():
                                        precision="mixed")
     for (a, b), H, inf, m in zip(probs, Hs, infos, sizes):
         assert inf["status"] == 0
+        # below the padded size 1024 a mixed request runs every shift in FP64 (the FP32
+        # group's extra launches cost more than they save there): FP64 accuracy
+        assert inf["shifts_fp64"][0] == inf["r"]
         lam = np.sqrt(np.linalg.eigvals((a - b) @ (a + b)).real)
         w = np.linalg.eigvalsh(0.5 * (H + H.T).cpu().numpy())
-        assert np.max(np.abs(np.sort(w) - np.sort(lam)) / np.sort(lam)) < 1e-10
+        assert np.max(np.abs(np.sort(w) - np.sort(lam)) / np.sort(lam)) < 1e-12
 
 
 def test_batched_bad_arguments():

@@ -109,3 +109,68 @@ def test_eig_casida_m1024():
     lam, V, info = api.eig(dev(a), dev(b))
     assert info["status"] == 0 and info["eig_splits"] >= 15
     check(a, b, lam.cpu().numpy(), V.cpu().numpy(), info, m)
+
+
+def check_clusters(a, b, lam, V, m):
+    """Checks that hold with multiple eigenvalues: values against the definition,
+    Sigma-orthonormality, the residual, the +-pairing, and for every group of equal
+    eigenvalues the projector onto its eigenspace (unique) against the oracle's."""
+    lam_ref, v_ref = eg.eig_casida(a, b)
+    h = sg.casida_matrix(a, b)
+    sigma = sg.casida_sigma(m)
+    assert np.array_equal(lam[m:], -lam[:m])
+    assert np.all(np.diff(lam[:m]) >= 0)
+    assert np.max(np.abs(lam - lam_ref) / np.abs(lam_ref)) < 1e-12
+    sig_hat = np.concatenate([np.ones(m), -np.ones(m)])
+    assert np.abs(V.T @ (sigma[:, None] * V) - np.diag(sig_hat)).max() < 1e-11
+    assert np.abs(h @ V - V * lam[None, :]).max() / np.abs(h).max() < 1e-11
+    # group the positive eigenvalues by relative gaps above 1e-8
+    lp = lam_ref[:m]
+    cuts = np.where(np.diff(lp) / lp[1:] > 1e-8)[0] + 1
+    for grp in np.split(np.arange(m), cuts):
+        proj = V[:, grp] @ (V[:, grp].T * sigma[None, :])
+        pref = v_ref[:, grp] @ (v_ref[:, grp].T * sigma[None, :])
+        assert np.abs(proj - pref).max() < 1e-9 * max(1.0, np.abs(pref).max())
+
+
+@pytest.mark.parametrize("m,a0,b0", [(100, 3.0, 1.0), (300, 2.5, -0.7), (90, 4.0, 0.0)])
+def test_eig_multiple_of_identity(m, a0, b0):
+    """A = aI, B = bI: all m positive eigenvalues equal sqrt(a^2 - b^2), so no shift can
+    split a block of the recursion; such blocks are recognized as lambda I and halved as
+    they are (Thm. EVREalSigmaOrth: any Sigma-orthonormal basis of the eigenspace is an
+    eigenbasis)."""
+    print(f"[eig cluster] m={m} a={a0} b={b0}", flush=True)
+    a = a0 * np.eye(m)
+    b = b0 * np.eye(m)
+    lam, V, info = api.eig(dev(a), dev(b))
+    assert info["status"] == 0
+    assert info["eig_clusters"] >= 1
+    lam = lam.cpu().numpy()
+    exact = np.sqrt(a0 * a0 - b0 * b0)
+    assert np.abs(lam[:m] - exact).max() < 1e-13 * exact
+    check_clusters(a, b, lam, V.cpu().numpy(), m)
+
+
+def test_eig_cluster_inside_spread_spectrum():
+    """A 100-fold eigenvalue in the middle of a spectrum spread over two decades: the
+    median shifts land on or near it; nudged shifts split the others off and the
+    cluster block is then recognized as lambda I."""
+    m = 260
+    rng = np.random.default_rng(31)
+    qm = inputs.haar(rng, m)
+    dm = rng.uniform(1.0, 2.0, m)
+    mu = 10.0 ** rng.uniform(-1.0, 1.0, m)
+    mu[:100] = 1.0                                   # eig((A-B)(A+B)) = mu: 100-fold 1
+    q = inputs.haar(rng, m)
+    mih = (qm * dm[None, :] ** -0.5) @ qm.T
+    k = mih @ ((q * mu[None, :]) @ q.T) @ mih
+    mm = (qm * dm[None, :]) @ qm.T
+    a = 0.5 * (mm + k)
+    b = 0.5 * (mm - k)
+    a, b = 0.5 * (a + a.T), 0.5 * (b + b.T)
+    print("[eig cluster] m=260 with a 100-fold eigenvalue", flush=True)
+    lam, V, info = api.eig(dev(a), dev(b))
+    assert info["status"] == 0
+    lam = lam.cpu().numpy()
+    assert np.sum(np.abs(lam[:m] - 1.0) < 1e-12) == 100
+    check_clusters(a, b, lam, V.cpu().numpy(), m)

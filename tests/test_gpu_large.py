@@ -4,8 +4,8 @@ worst shifted Gram matrix of the first Zolotarev step has condition ~8e5.
 
 The oracle cannot factorize n = 16384 in test time, so the checks are properties that
 hold at any size, against closed forms of the construction:
-  * eigenvalues of H_+ against sqrt(mu) (the construction itself reproduces mu to
-    ~1e-11 relative, so the bar is 1e-9 for FP64 and 1e-8 for the mixed mode);
+  * eigenvalues of H_+ against sqrt(mu): 2e-11 for FP64 (measured 4e-12) and the 1e-10
+    target for the mixed mode (measured 2e-11);
   * Sigma-orthonormality of Q_+;
   * trace(H_+) = sum sqrt(mu).
 """
@@ -37,7 +37,7 @@ def eigvals_sym(h):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-8)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 2e-11), ("mixed", 1e-10)])
 def test_ill_separated_m8192(ill, precision, tol):
     a, b, mu = ill
     A = torch.tensor(a, dtype=torch.float64, device="cuda")
@@ -48,6 +48,9 @@ def test_ill_separated_m8192(ill, precision, tol):
     print(f"[large] info r={info['r']} ell={info['ell'][:2]} restarts={info['restarts']} "
           f"fp64 shifts={info['shifts_fp64']}", flush=True)
     assert info["status"] == 0
+    if precision == "mixed":
+        # some shifts of the first step must run in FP32 (else the mode fell back)
+        assert 0 < info["shifts_fp64"][0] < info["r"]
     exact = np.sqrt(mu)
     # l = beta / alpha: the estimator brackets the spectrum within a few percent
     assert 0.9e-3 < info["beta"] / info["alpha"] < 1.0e-3

@@ -72,3 +72,40 @@ def test_host_coefficients_tiny_ell():
     for x, y in zip(got["c"], ref.c):
         assert abs(x - y) <= 4e-16 * abs(y)
     assert abs(got["ell_next"] - ref.ell_next) <= 4e-16 * ref.ell_next
+
+
+def test_workspace_and_stream_arguments_host_only():
+    """The caller owns every device buffer and stream: the batched workspace size is a
+    host computation, and the stream call validates its arguments before anything else."""
+    lib = api.load()
+    n = 5
+    ms = (ctypes.c_int * n)(40, 300, 64, 300, 7)
+    o = api.make_opts()
+    full = lib.ps_workspace_size_batched(n, ms, ctypes.byref(o))
+    assert full > 0
+    # at least one share per worker holding the largest single problem
+    one = lib.ps_workspace_size(300, ctypes.byref(o), 1)
+    assert full >= min(n, 6) * (one - 256)
+    assert lib.ps_workspace_size_batched(0, ms, None) == 0
+    assert lib.ps_workspace_size_batched(n, None, None) == 0
+    bad = (ctypes.c_int * 2)(5, 0)
+    assert lib.ps_workspace_size_batched(2, bad, None) == 0
+    assert lib.ps_set_worker_streams(None, 0, None) == -1
+
+
+def _c_struct_fields(name):
+    txt = open(HEADER).read()
+    body = txt[:txt.index("} " + name + ";")]
+    body = body[body.rindex("typedef struct {"):]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    out = []
+    for decl in re.findall(r"(?:int|double)\s+([^;]+);", body):
+        for part in decl.split(","):
+            out.append(re.sub(r"\[.*\]", "", part).strip())
+    return out
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes mirrors of ps_opts and ps_info declare the header's fields in its order."""
+    assert [n for n, _ in api.PsOpts._fields_] == _c_struct_fields("ps_opts")
+    assert [n for n, _ in api.PsInfo._fields_] == _c_struct_fields("ps_info")

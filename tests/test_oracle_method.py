@@ -276,3 +276,23 @@ def test_example1_backward_error_bound(kappa):
     if kappa == 10.0:
         assert bwd < 100 * GOLDEN["example1_backward_error_bound"]["zolo_avg_kappa10"]
     assert int(np.sum(sigma > 0)) == qp.shape[1]          # p positive eigenvalues
+
+
+@pytest.mark.parametrize("m,seed,mu_lo", [(5, 1, 1e-2), (60, 3, 1e-3), (150, 8, 1e-6)])
+def test_sign_definition_against_construction(m, seed, mu_lo):
+    """The ill-separated construction fixes sign(H) in closed form (products of its own
+    spectral factors, no eigensolver); the definition through the definite pencil must
+    reproduce it, and the column form must equal the full one."""
+    a, b, _, fac = inputs.ill_separated(m, seed, mu_lo=mu_lo, return_factors=True)
+    As, Bs = sg.sign_blocks_from_spectral_factors(*fac)
+    s = sg.sign_definition(sg.casida_matrix(a, b), sg.casida_sigma(m))
+    scale = np.abs(s).max()
+    # rounding of A, B (~1e-16 relative) moves sign(H) by about that over the squared
+    # spectral gap, min|lambda|^2 = mu_lo (measured: 2.4e-13 at 1e-4, 2.4e-11 at 1e-6)
+    tol = 1e-16 / mu_lo
+    for blk, ref in ((s[:m, :m], As), (s[:m, m:], Bs), (s[m:, :m], -Bs), (s[m:, m:], -As)):
+        assert np.abs(blk - ref).max() < tol * scale
+    cols = [0, m // 2, m - 1]
+    ca, cb = sg.sign_columns_from_spectral_factors(*fac, cols)
+    assert np.abs(ca - As[:, cols]).max() < 1e-13 * scale
+    assert np.abs(cb - Bs[:, cols]).max() < 1e-13 * scale

@@ -157,3 +157,18 @@ def test_choose_r_rule_monotone():
     rs = [zol.choose_r(e) for e in [0.5, 0.1, 1e-2, 1e-4, 1e-8, 1e-12, 1e-16]]
     assert rs == sorted(rs)
     assert rs[-1] <= 8
+
+
+@pytest.mark.parametrize("ell", [0.5, 0.2, 0.1, 0.04, 0.01, 1e-3, 1e-6, 1e-10])
+def test_choose_r_against_composite_function(ell):
+    """The rule for r (Alg. 8 takes it from a table that is not in the text): the smallest
+    r whose two steps reach 1 - 1e-15 at x = l.  By the composition property of Sec. 5.2,
+    two steps of hat Z_{2r+1} are the single function hat Z_{(2r+1)^2}(x; l), whose value
+    at l comes from its own coefficients (degree parameter R = ((2r+1)^2 - 1)/2 = 2r(r+1)),
+    not from the two-step schedule.  The returned r must meet the bound and r - 1 must not."""
+    tol = mp.mpf("1e-15")
+    r = zol.choose_r(ell)
+    with mp.workdps(60):
+        assert 1 - zol.coefficients(ell, 2 * r * (r + 1)).ell_next_mp <= tol
+        if r > 1:
+            assert 1 - zol.coefficients(ell, 2 * (r - 1) * r).ell_next_mp > tol
