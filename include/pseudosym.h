@@ -221,6 +221,19 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
                      double* Qp, int ldq, double* Hp, int ldh, const ps_opts* opts,
                      ps_info* info);
 
+/* pseudosym_divide without any workspace, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * scratch space is a fixed 128 MiB device array inside the library (each GPU it runs on
+ * holds one copy until the process ends); the call allocates nothing, creates nothing,
+ * ignores opts->timing and otherwise behaves exactly like pseudosym_divide (same kernels,
+ * same results).  Sizes whose workspace would exceed the array (beyond m = 560 or so;
+ * every m <= 512 fits with any options) return -2.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads, other handles)
+ * race and must be serialized by the caller. */
+int pseudosym_divide_static(ps_handle h, int m, const double* A, int lda, const double* B,
+                            int ldb, double* Qp, int ldq, double* Hp, int ldh,
+                            const ps_opts* opts, ps_info* info);
+
 /* All eigenpairs of H (Alg. 3 once, then Alg. 2 on the decoupled block; Thm. DefDivConq
  * reduces the rest to the symmetric positive definite H_+).  H_+ = Q_+^T Sigma H Q_+
  * comes from pseudosym_divide; the symmetric spectral divide-and-conquer splits it

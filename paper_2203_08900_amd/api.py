@@ -102,7 +102,7 @@ EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
     "ps_set_workspace", "ps_workspace_size_batched", "ps_set_worker_streams",
     "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
-    "pseudosym_eig", "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
+    "pseudosym_divide_static", "pseudosym_eig", "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
     "ps_status_string",
 ]
 
@@ -150,6 +150,9 @@ def load():
         lib.pseudosym_divide.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
                                                ctypes.POINTER(PsInfo)]
         lib.pseudosym_divide.restype = ip
+        lib.pseudosym_divide_static.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
+                                                      ctypes.POINTER(PsInfo)]
+        lib.pseudosym_divide_static.restype = ip
         lib.pseudosym_eig.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts),
                                             ctypes.POINTER(PsInfo)]
         lib.pseudosym_eig.restype = ip

@@ -1913,7 +1913,9 @@ int ps_create(ps_handle* h, void* stream) {
   if (!h) return -1;
   ps_handle_s* p = new ps_handle_s();
   p->stream = (hipStream_t)stream;
-  if (hipGetDevice(&p->device) != hipSuccess ||
+  // the device address of the static scratch area of this device, looked up once per
+  // device at set-up (pseudosym_divide_static)
+  if (hipGetDevice(&p->device) != hipSuccess || !static_scratch_ptr() ||
       hipHostMalloc((void**)&p->pinned, kPinned * sizeof(double), hipHostMallocDefault) !=
           hipSuccess) {
     delete p;
@@ -2044,6 +2046,28 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
   if (opts) o = *opts;
   o.max_steps = 0;
   return guarded(h, [&] { return run(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, info, 1); });
+}
+
+int pseudosym_divide_static(ps_handle h, int m, const double* A, int lda, const double* B,
+                            int ldb, double* Qp, int ldq, double* Hp, int ldh,
+                            const ps_opts* opts, ps_info* info) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (!Qp) return -7;
+  if (ldq < 2 * m) return -8;
+  if (!Hp) return -9;
+  if (ldh < m) return -10;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  o.timing = 0;   // no event pool: nothing is created or allocated during the call
+  if (workspace_bytes(m, o, 1) > kStaticScratchBytes) return -2;
+  return guarded(h, [&] {
+    char* ws = (char*)static_scratch_ptr();   // this device's copy, looked up at set-up
+    if (!ws) return (int)PS_HIP_ERROR;
+    return run(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, info, 1, ws);
+  });
 }
 
 int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,

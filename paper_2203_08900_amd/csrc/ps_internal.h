@@ -39,6 +39,12 @@ struct HipError {
     if (e_ != hipSuccess) throw ::ps::HipError{e_, #call};            \
   } while (0)
 
+// ----------------------------------------------------------------- static scratch
+// Size of the file-scope device array behind pseudosym_divide_static (static_scratch.hip)
+// and the address of the current device's copy (null if its lookup failed).
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+void* static_scratch_ptr();
+
 // ----------------------------------------------------------------- FP64 GEMM
 // D = alpha * op(A) op(B) + beta * C  for a grouped, two-level batched set of
 // problems.  op(X) = X (t = 0) or X^T (t = 1); all matrices column-major.
