@@ -61,6 +61,34 @@ def alg6_cholesky_bases_plus(s: np.ndarray, p: int):
     return np.vstack([sigma[:p, None] * c_plus.T, bottom])
 
 
+def alg6_bases_general(s: np.ndarray, sigma: np.ndarray):
+    """Alg. 6 for any signature Sigma (diagonal entries +-1 in any order), with r_+ and
+    r_- the numbers of +1 and -1 entries (Thm. EVREalSigmaOrth).  As printed, the
+    Cholesky factors come from the leading r_+ (resp. r_-) rows and columns of Sigma P_+
+    (resp. -Sigma P_-), whatever signs Sigma has there:
+        Q_{1,+} = chol(Sigma(1:r_+) P_+(1:r_+, 1:r_+))  (upper, R^T R),
+        Q_+ = [Sigma(1:r_+) Q_{1,+}^T; P_+(r_+ + 1:n, 1:r_+) Q_{1,+}^{-1}].
+    Q_- takes the sign of Thm. HRisLDL (see the module docstring): with
+    -Sigma P_- = R^T R pivoted on the leading r_- indices, Q_- = Sigma R^T hat Sigma_-,
+        Q_- = [-Sigma(1:r_-) Q_{1,-}^T; P_-(r_- + 1:n, 1:r_-) Q_{1,-}^{-1}].
+    Returns (Q_+, Q_-)."""
+    n = s.shape[0]
+    p = int(np.sum(sigma > 0))
+    q = n - p
+    pp, pm = projectors(s)
+    sp = sigma[:, None] * pp
+    c_plus = sla.cholesky(0.5 * (sp[:p, :p] + sp[:p, :p].T), lower=False)
+    top = sigma[:p, None] * c_plus.T
+    bottom = sla.solve_triangular(c_plus, pp[p:, :p].T, trans="T", lower=False).T
+    q_plus = np.vstack([top, bottom])
+    sm = -(sigma[:, None] * pm)
+    c_minus = sla.cholesky(0.5 * (sm[:q, :q] + sm[:q, :q].T), lower=False)
+    top_m = -(sigma[:q, None] * c_minus.T)
+    bottom_m = sla.solve_triangular(c_minus, pm[q:, :q].T, trans="T", lower=False).T
+    q_minus = np.vstack([top_m, bottom_m])
+    return q_plus, q_minus
+
+
 def alg6_cholesky_bases_as_printed(s: np.ndarray, p: int):
     """Alg. 6 exactly as printed (kept only to document the sign error of Q_-)."""
     n = s.shape[0]

@@ -55,3 +55,16 @@ def divide_casida(a: np.ndarray, b: np.ndarray, r: int = 8, alpha=None, beta=Non
     hp, hm, bwd = decouple(h, sigma, qp, qm)
     return {"H": h, "sigma": sigma, "S": s, "Q_plus": qp, "Q_minus": qm,
             "H_plus": hp, "H_minus": hm, "backward_error": bwd, "record": rec}
+
+
+def divide_general(h: np.ndarray, sigma: np.ndarray, r: int = 8, alpha=None, beta=None,
+                   max_restarts: int = 2):
+    """Spectral division of a definite pseudosymmetric H for any signature Sigma
+    (Sigma H symmetric positive definite; Sec. 5 and the matrices of Sec. 6.1): sign(H)
+    by Alg. 8 with LDL^T solves on H, bases by Alg. 6 as printed (leading indices,
+    Q_- with the sign of Thm. HRisLDL), decoupled blocks and backward error."""
+    s, rec = sg.zolo_pd(h, sigma, r=r, alpha=alpha, beta=beta, max_restarts=max_restarts)
+    qp, qm = bs.alg6_bases_general(s, sigma)
+    hp, hm, bwd = decouple(h, sigma, qp, qm)
+    return {"H": h, "sigma": sigma, "S": s, "Q_plus": qp, "Q_minus": qm,
+            "H_plus": hp, "H_minus": hm, "backward_error": bwd, "record": rec}

@@ -27,6 +27,9 @@ Workload families (draw order matters for reproducibility and is fixed here):
   mu log-uniform in [1e-6, 1] with both ends pinned, so that the
   eigenvalues of (A - B)(A + B) = K M are exactly mu (spectral gap ratio 1e6).
 * ``gradient_weight(m, seed)`` - a symmetric Gaussian 2m x 2m weight W.
+* ``general_sigma(n, seed, kappa)`` - H = Sigma Q D Q^T with a random signature Sigma,
+  Q orthonormalized from U[0, 1) entries and D equally spaced in [1, kappa]: the
+  random definite pseudosymmetric matrices of the paper's experiments (Sec. 6.1).
 """
 from __future__ import annotations
 
@@ -40,6 +43,7 @@ __all__ = [
     "batched",
     "ill_separated",
     "gradient_weight",
+    "general_sigma",
     "workload",
     "WORKLOADS",
 ]
@@ -126,6 +130,20 @@ def ill_separated(m: int, seed: int, mu_lo: float = 1e-6, mu_hi: float = 1.0,
         return (np.ascontiguousarray(a), np.ascontiguousarray(b), np.sort(mu),
                 (qm, dm, q, mu.copy()))
     return np.ascontiguousarray(a), np.ascontiguousarray(b), np.sort(mu)
+
+
+def general_sigma(n: int, seed: int, kappa: float):
+    """A definite pseudosymmetric H = Sigma Q D Q^T of any signature, as in the paper's
+    random experiments (Sec. 6.1): Sigma with +1 or -1 on the diagonal with equal
+    probability, Q the orthogonal factor of a matrix of U[0, 1) entries, D equally
+    spaced values from 1 to kappa.  Returns (H, sigma)."""
+    rng = np.random.default_rng(seed)
+    sigma = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    q, _ = np.linalg.qr(rng.random((n, n)))
+    d = np.linspace(1.0, kappa, n)
+    m = _sym((q * d[None, :]) @ q.T)
+    h = sigma[:, None] * m
+    return np.ascontiguousarray(h), sigma
 
 
 def gradient_weight(m: int, seed: int) -> np.ndarray:

@@ -296,3 +296,71 @@ def test_sign_definition_against_construction(m, seed, mu_lo):
     ca, cb = sg.sign_columns_from_spectral_factors(*fac, cols)
     assert np.abs(ca - As[:, cols]).max() < 1e-13 * scale
     assert np.abs(cb - Bs[:, cols]).max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize("n,seed,kappa", [(60, 1, 10.0), (120, 3, 1e4), (97, 5, 1e2)])
+def test_general_sigma_division(n, seed, kappa):
+    """Any signature (Sec. 6.1 matrices): Alg. 8 on H reaches the definition of sign(H);
+    rank P_+ = number of +1 in Sigma (Thm. EVREalSigmaOrth); the Alg. 6 bases are
+    (Sigma, +-I)-orthonormal and invariant; H_+ holds the positive eigenvalues of H and
+    H_- the negative ones (a second LAPACK route, the nonsymmetric eigensolver); the
+    backward error stays below the paper's 1e-9 (Fig. BackErr_all)."""
+    h, sig = inputs.general_sigma(n, seed, kappa)
+    ref = dv.divide_general(h, sig)
+    s = ref["S"]
+    p = int(np.sum(sig > 0))
+    assert np.abs(s - sg.sign_definition(h, sig)).max() < 1e-12 * kappa * np.abs(s).max()
+    assert int(round(np.trace(0.5 * (np.eye(n) + s)))) == p
+    qp, qm = ref["Q_plus"], ref["Q_minus"]
+    assert qp.shape == (n, p) and qm.shape == (n, n - p)
+    # Alg. 6 factors the leading blocks of +-Sigma P_+-, whose condition numbers (up to
+    # ~1e6 here for a random Sigma) bound the accuracy of the bases (measured ~1e-17 cond)
+    pp = 0.5 * (np.eye(n) + s)
+    sp, sm = sig[:, None] * pp, -(sig[:, None] * (np.eye(n) - pp))
+    cnd = max(np.linalg.cond(sp[:p, :p]), np.linalg.cond(sm[:n - p, :n - p]))
+    tol = 1e-15 * max(cnd, kappa)
+    assert np.abs(qp.T @ (sig[:, None] * qp) - np.eye(p)).max() < tol
+    assert np.abs(qm.T @ (sig[:, None] * qm) + np.eye(n - p)).max() < tol
+    assert np.abs(pp @ qp - qp).max() < tol and np.abs(pp @ qm).max() < tol
+    lam = np.linalg.eigvals(h).real
+    wp = np.linalg.eigvalsh(0.5 * (ref["H_plus"] + ref["H_plus"].T))
+    wm = np.linalg.eigvalsh(0.5 * (ref["H_minus"] + ref["H_minus"].T))
+    scale = np.abs(lam).max()
+    # H_+- inherit the bases' departure from Sigma-orthonormality (above)
+    etol = max(1e-13 * kappa, 1e-14 * cnd) * scale
+    assert np.abs(np.sort(wp) - np.sort(lam[lam > 0])).max() < etol
+    assert np.abs(np.sort(wm) - np.sort(lam[lam < 0])).max() < etol
+    assert ref["backward_error"] < 1e-9
+    assert len(ref["record"].changes) == 1          # two Zolotarev steps, no restart
+
+
+def test_general_bases_reduce_to_casida_case():
+    """With Sigma = diag(I_m, -I_m) the general Alg. 6 is the block form used for H of
+    Casida type."""
+    a, b = inputs.small_dense(30, 2)
+    h = sg.casida_matrix(a, b)
+    sig = sg.casida_sigma(30)
+    s = sg.sign_definition(h, sig)
+    qp, qm = bs.alg6_bases_general(s, sig)
+    qp2, qm2 = bs.alg6_cholesky_bases(s, 30)
+    # the same factorizations; they differ only in how the leading block is symmetrized
+    assert np.abs(qp - qp2).max() < 1e-12 and np.abs(qm - qm2).max() < 1e-11
+
+
+@pytest.mark.parametrize("which", ["dwh", "newton"])
+def test_comparison_iterations_reach_sign(which):
+    """Sigma-DWH (Eq:LDLZolo with r = 1) and the scaled Newton iteration reach the
+    definition of sign(H) and pass their stopping tests (u^{1/3}, u^{1/2})."""
+    from oracle import iterations as it
+    a, b = inputs.small_dense(50, 3)
+    h = sg.casida_matrix(a, b)
+    sig = sg.casida_sigma(50)
+    amax, amin = sg.abs_eig_bounds(h, sig)
+    sd = sg.sign_definition(h, sig)
+    if which == "dwh":
+        s, steps, change = it.sign_dwh(h, sig, 1.01 * amax, 0.99 * amin)
+        assert change <= (2.0 ** -53) ** (1 / 3)
+    else:
+        s, steps, change = it.sign_newton(h, 1.01 * amax, 0.99 * amin)
+        assert change <= (2.0 ** -53) ** (1 / 2)
+    assert np.abs(s - sd).max() < 1e-13 * np.abs(sd).max()

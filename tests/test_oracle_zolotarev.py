@@ -172,3 +172,28 @@ def test_choose_r_against_composite_function(ell):
         assert 1 - zol.coefficients(ell, 2 * r * (r + 1)).ell_next_mp <= tol
         if r > 1:
             assert 1 - zol.coefficients(ell, 2 * (r - 1) * r).ell_next_mp > tol
+
+
+def test_comparison_iteration_counts_table1():
+    """Tab:ItRuntime: Sigma-DWH takes 5, 6, 6 steps and the scaled Newton iteration 7, 9, 9
+    at kappa = 1e2, 1e8, 1e12.  The oracle's schedules (r = 1 steps until the l-recurrence
+    reaches 1 - 1e-15 plus the step of the stopping test; Newton with the Byers-Xu
+    scaling until the modulus interval reaches [1, 1 + 1e-15] plus one) give those counts."""
+    from oracle import iterations as it
+    g = GOLDEN["table1_iterations"]
+    for kappa, d, nw in zip(g["kappa"], g["sigma_dwh_ldliqr2"], g["newton"]):
+        assert len(it.dwh_schedule(1.0 / kappa)) == d
+        assert len(it.newton_schedule(1.0 / kappa)) == nw
+
+
+def test_newton_scaling_scalar_map():
+    """The scaled Newton map x -> (mu x + 1/(mu x))/2 with the schedule's scalings takes
+    every modulus in [l, 1] into [1, 1 + 1e-15] (evaluated in multiprecision)."""
+    from oracle import iterations as it
+    for ell in (1e-1, 1e-4, 1e-10):
+        mus = it.newton_schedule(ell)
+        with mp.workdps(50):
+            xs = [mp.mpf(ell) * (mp.mpf(1) / ell) ** (mp.mpf(k) / 20) for k in range(21)]
+            for mu in mus:
+                xs = [(mu * x + 1 / (mu * x)) / 2 for x in xs]
+            assert max(abs(x - 1) for x in xs) <= mp.mpf("2e-15")
