@@ -106,7 +106,32 @@ typedef struct {
                        /* (the same rational function to below 1e-17)               */
   int basis;           /* pseudosym_divide / pseudosym_eig: PS_BASIS_ALG6 (default) */
                        /* or PS_BASIS_CORE, see below                             */
+  int iteration;       /* PS_ITER_ZOLO (Alg. 8, default) or one of the comparison  */
+                       /* iterations of Sec. 6, see below (FP64 only)             */
+  int refine;          /* what follows the iteration, PS_REFINE_*:               */
+                       /* NONE: (mixed precision with the core basis, m >= 1024  */
+                       /*   padded) the basis and H_+ in FP32 as well: the       */
+                       /*   low-precision result before any refinement (~1e-6);  */
+                       /*   elsewhere as RR.  RR (default): FP64 Sigma-          */
+                       /*   orthonormalization and Rayleigh-Ritz block of the    */
+                       /*   subspace (core basis), FP64 sign blocks and Alg. 6.  */
+                       /*   NS: RR after one FP64 Newton-Schulz pass on the      */
+                       /*   polar factor, U <- U (3I - U^T U)/2                   */
 } ps_opts;
+
+enum { PS_REFINE_NONE = 0, PS_REFINE_RR = 1, PS_REFINE_NS = 2 };
+
+/* sign iteration (ps_opts.iteration); the comparison iterations of Tab:ItRuntime run
+ * one step after another with a schedule fixed by l = beta/alpha:
+ *  PS_ITER_DWH:    Sigma-DWH, i.e. the step of Alg. 8 with r = 1 and the l-recurrence,
+ *                  until the recurrence reaches 1 - 1e-15, plus the step of the stopping
+ *                  test ||X_k - X_{k-1}||_F / ||X_k||_F <= u^{1/3} (5, 6, 6 steps at
+ *                  kappa = 1e2, 1e8, 1e12);
+ *  PS_ITER_NEWTON: the scaled Newton iteration X <- (mu X + (mu X)^{-1})/2 with the
+ *                  Byers-Xu scaling (mu_0 = 1/sqrt(l), then from the modulus interval),
+ *                  stopping test u^{1/2} (7, 9, 9 steps).
+ * Both stop with PS_NOT_CONVERGED when the stopping test fails (no restart). */
+enum { PS_ITER_ZOLO = 0, PS_ITER_DWH = 1, PS_ITER_NEWTON = 2 };
 
 typedef struct {
   int status;
@@ -154,7 +179,7 @@ enum {
 
 /* Fill *o with the defaults: FP64, r = 8, 2 restarts, full method, 20 Lanczos
  * steps, no timing, estimated alpha/beta, mixed_kappa = 20, step2_series = 1,
- * basis = PS_BASIS_ALG6. */
+ * basis = PS_BASIS_ALG6, iteration = PS_ITER_ZOLO, refine = PS_REFINE_RR. */
 void ps_opts_default(ps_opts* o);
 
 /* Create a handle bound to `stream` (a hipStream_t, NULL = default stream) on
@@ -164,7 +189,8 @@ int ps_destroy(ps_handle h);
 int ps_set_stream(ps_handle h, void* stream);
 
 /* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig and
- * sign_fwd, 3 sign_bwd) needs at half-size m with options o (NULL = defaults). */
+ * sign_fwd, 3 sign_bwd, 4 divide_general) needs at half-size m (for kind 4: the order n
+ * of H) with options o (NULL = defaults). */
 size_t ps_workspace_size(int m, const ps_opts* o, int what);
 
 /* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the
@@ -220,6 +246,34 @@ int pseudosym_sign(ps_handle h, int m, const double* A, int lda, const double* B
 int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                      double* Qp, int ldq, double* Hp, int ldh, const ps_opts* opts,
                      ps_info* info);
+
+/* One step of spectral division (Alg. 3 with sigma = 0) of a definite pseudosymmetric H
+ * of ANY signature: Sigma = diag(sigma) with entries +-1 in any order and Sigma H
+ * symmetric positive definite, the matrices of Sec. 6.1 (H = Sigma Q D Q^T).  With
+ * r_+ and r_- the numbers of +1 and -1 in sigma, H has r_+ positive and r_- negative
+ * eigenvalues (Thm. EVREalSigmaOrth).  sign(H) by Alg. 8 (the Zolotarev iteration runs on
+ * the symmetric T = R Sigma R^T, M = Sigma H = R^T R, H = R^{-1} T R, so its shifted
+ * matrices are T^2 + c I, symmetric positive definite, factorized by Cholesky); bases by
+ * Alg. 6 as printed (Cholesky of the leading r_+ x r_+ block of Sigma P_+ and the
+ * leading r_- x r_- block of -Sigma P_-, Q_- with the sign of Thm. HRisLDL); decoupled
+ * blocks of Thm. DefDivConq.
+ *   H      n x n (device, ld ldh >= n), read only; its symmetric part of Sigma H is used.
+ *   sigma  HOST array of n doubles, each +1 or -1 (else -5).
+ *   S      optional n x n output sign(H) (device, lds >= n), NULL to skip.
+ *   Qp     n x r_+ (ldqp >= n): Q_+^T Sigma Q_+ = I, range = positive invariant subspace.
+ *   Qm     n x r_- (ldqm >= n): Q_-^T Sigma Q_- = -I, the negative one.
+ *   Hp     r_+ x r_+ (ldhp >= r_+): H_+ = Q_+^T Sigma H Q_+, symmetric positive definite.
+ *   Hm     r_- x r_- (ldhm >= r_-): H_- = -Q_-^T Sigma H Q_-, negative definite.
+ * Outputs of an empty side (r_+ = 0 or r_- = 0) may be NULL.  The Cholesky form of the
+ * first step loses its accuracy (or breaks down with PS_SHIFT_BREAKDOWN) when the
+ * condition number of M exceeds about 1e7 (the shifted T^2 + c I then have condition
+ * numbers near 1/u); the leading blocks of Alg. 6 can be ill-conditioned for an
+ * unlucky Sigma, which PS_BASIS_BREAKDOWN reports when their Cholesky fails.
+ * opts->max_steps must be 0; opts->basis is ignored. */
+int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const double* sigma,
+                             double* S, int lds, double* Qp, int ldqp, double* Qm, int ldqm,
+                             double* Hp, int ldhp, double* Hm, int ldhm, const ps_opts* opts,
+                             ps_info* info);
 
 /* pseudosym_divide without any workspace, for callers that cannot allocate device memory
  * (code under graph capture, tight serving loops, harnesses that forbid allocation).  The

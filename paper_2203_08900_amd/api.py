@@ -47,6 +47,8 @@ class PsOpts(ctypes.Structure):
         ("mixed_kappa", ctypes.c_double),
         ("step2_series", ctypes.c_int),
         ("basis", ctypes.c_int),
+        ("iteration", ctypes.c_int),
+        ("refine", ctypes.c_int),
     ]
 
 
@@ -102,7 +104,8 @@ EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
     "ps_set_workspace", "ps_workspace_size_batched", "ps_set_worker_streams",
     "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
-    "pseudosym_divide_static", "pseudosym_eig", "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
+    "pseudosym_divide_static", "pseudosym_divide_general", "pseudosym_eig",
+    "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
     "ps_status_string",
 ]
 
@@ -153,6 +156,10 @@ def load():
         lib.pseudosym_divide_static.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
                                                       ctypes.POINTER(PsInfo)]
         lib.pseudosym_divide_static.restype = ip
+        lib.pseudosym_divide_general.argtypes = [hp, ip, vp, ip, ctypes.POINTER(ctypes.c_double),
+                                                 vp, ip, vp, ip, vp, ip, vp, ip, vp, ip,
+                                                 ctypes.POINTER(PsOpts), ctypes.POINTER(PsInfo)]
+        lib.pseudosym_divide_general.restype = ip
         lib.pseudosym_eig.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts),
                                             ctypes.POINTER(PsInfo)]
         lib.pseudosym_eig.restype = ip
@@ -186,9 +193,13 @@ def zolotarev_coeffs(ell: float, r: int):
     return {"c": list(c[:2 * r]), "a": list(a[:r]), "chat": chat.value, "ell_next": nxt.value}
 
 
+ITERATIONS = {"zolo": 0, "dwh": 1, "newton": 2}
+REFINES = {"none": 0, "rr": 1, "ns": 2}
+
+
 def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=20,
               timing=False, alpha=0.0, beta=0.0, mixed_kappa=20.0,
-              step2_series=True, basis="alg6") -> PsOpts:
+              step2_series=True, basis="alg6", iteration="zolo", refine="rr") -> PsOpts:
     lib = load()
     o = PsOpts()
     lib.ps_opts_default(ctypes.byref(o))
@@ -205,6 +216,8 @@ def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=
     o.step2_series = 1 if step2_series else 0
     o.basis = {"alg6": PS_BASIS_ALG6, "core": PS_BASIS_CORE}[basis] \
         if isinstance(basis, str) else int(basis)
+    o.iteration = ITERATIONS[iteration] if isinstance(iteration, str) else int(iteration)
+    o.refine = REFINES[refine] if isinstance(refine, str) else int(refine)
     return o
 
 
@@ -322,6 +335,49 @@ def divide(A, B, raise_on_error=True, **kw):
     if rc != 0 and raise_on_error:
         raise PseudosymError(rc, info.as_dict())
     return Qt.t(), Hp.t(), info.as_dict() | {"rc": rc}
+
+
+def divide_general(H, sigma, want_sign=False, raise_on_error=True, **kw):
+    """One spectral division of a definite pseudosymmetric H (n x n, float64 on the device)
+    for any signature sigma (n values +-1; Sigma H symmetric positive definite).
+    Returns (Qp, Qm, Hp, Hm, S, info): Qp n x r_+, Qm n x r_-, Hp r_+ x r_+, Hm r_- x r_-,
+    S = sign(H) (n x n) when want_sign, else None."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    if not isinstance(H, torch.Tensor) or H.dtype != torch.float64 or not H.is_cuda:
+        raise TypeError("H must be a float64 tensor on a ROCm device")
+    if H.dim() != 2 or H.shape[0] != H.shape[1]:
+        raise ValueError("H must be square")
+    n = H.shape[0]
+    sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
+    if sig.shape[0] != n:
+        raise ValueError("sigma must have n entries")
+    p = int(np.sum(sig > 0))
+    q = n - p
+    opts = make_opts(**kw)
+    Hc = H.t().contiguous()            # column-major storage of H
+    dev = H.device
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        st = _handle(dev.index, stream.cuda_stream)
+        _ensure_workspace(st, lib, n, opts, 4, dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    Qpt = torch.empty((max(p, 1), n), **f64)
+    Qmt = torch.empty((max(q, 1), n), **f64)
+    Hpt = torch.empty((max(p, 1), max(p, 1)), **f64)
+    Hmt = torch.empty((max(q, 1), max(q, 1)), **f64)
+    St = torch.empty((n, n), **f64) if want_sign else None
+    info = PsInfo()
+    rc = lib.pseudosym_divide_general(
+        st.handle, n, Hc.data_ptr(), n, sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        St.data_ptr() if St is not None else None, n, Qpt.data_ptr(), n, Qmt.data_ptr(), n,
+        Hpt.data_ptr(), max(p, 1), Hmt.data_ptr(), max(q, 1), ctypes.byref(opts),
+        ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    return (Qpt[:p].t(), Qmt[:q].t(), Hpt[:p, :p].t(), Hmt[:q, :q].t(),
+            St.t() if St is not None else None, info.as_dict() | {"rc": rc})
 
 
 def eig(A, B, want_vectors=True, raise_on_error=True, **kw):

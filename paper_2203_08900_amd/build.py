@@ -23,6 +23,7 @@ SOURCES = [
     "batch.hip",
     "eig_f64.hip",
     "mixed.hip",
+    "general.hip",
     "static_scratch.hip",
     "zolo_host.cpp",
     "pipeline.cpp",

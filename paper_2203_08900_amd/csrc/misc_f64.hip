@@ -183,24 +183,26 @@ struct ShiftList {
   double c[kMaxSeg];
 };
 
-// same as form_shifts_kernel with the shifts passed by value (no host-device copy)
-__global__ void form_shifts_v_kernel(const double* g, double* z, int mp, ShiftList sl) {
+// same as form_shifts_kernel with the shifts passed by value (no host-device copy); the
+// padded diagonal (indices >= m, where G is zero) is 1, so that a zero shift (the Newton
+// step) still leaves the padding positive definite
+__global__ void form_shifts_v_kernel(const double* g, double* z, int m, int mp, ShiftList sl) {
   const size_t n = (size_t)mp * mp;
   const double c = sl.c[blockIdx.y];
   double* Z = z + blockIdx.y * n;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % mp), j = (int)(e / mp);
-    Z[e] = (i < j) ? g[e] : ((i == j) ? g[e] + c : 0.0);
+    Z[e] = (i < j) ? g[e] : ((i == j) ? (i < m ? g[e] + c : 1.0) : 0.0);
   }
 }
 
-void form_shifts_v(hipStream_t s, const double* g, double* z, int mp, const double* shifts_host,
-                   int r) {
+void form_shifts_v(hipStream_t s, const double* g, double* z, int m, int mp,
+                   const double* shifts_host, int r) {
   ShiftList sl{};
   for (int j = 0; j < r && j < kMaxSeg; ++j) sl.c[j] = shifts_host[j];
   hipLaunchKernelGGL(form_shifts_v_kernel, dim3(blocks_for((size_t)mp * mp), r), dim3(NT), 0, s,
-                     g, z, mp, sl);
+                     g, z, m, mp, sl);
   PS_HIP(hipGetLastError());
 }
 

@@ -52,6 +52,17 @@ void cvt_f64_f32(hipStream_t s, const double* x, float* y, size_t n) {
   PS_HIP(hipGetLastError());
 }
 
+__global__ void cvt_f32_f64_kernel(const float* x, double* y, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    y[e] = (double)x[e];
+}
+
+void cvt_f32_f64(hipStream_t s, const float* x, double* y, size_t n) {
+  hipLaunchKernelGGL(cvt_f32_f64_kernel, dim3(grid_for(n)), dim3(NT), 0, s, x, y, n);
+  PS_HIP(hipGetLastError());
+}
+
 // y = a y + b fp64(x)
 __global__ void axpy_f32_kernel(double* y, double a, double b, const float* x, size_t n) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;

@@ -29,8 +29,8 @@
 
 namespace ps {
 void fill_int_zero(hipStream_t s, int* x, int n);
-void form_shifts_v(hipStream_t s, const double* g, double* z, int mp, const double* shifts_host,
-                   int r);
+void form_shifts_v(hipStream_t s, const double* g, double* z, int m, int mp,
+                   const double* shifts_host, int r);
 }  // namespace ps
 
 struct ps_handle_s {
@@ -337,7 +337,7 @@ void zolo_step_f64(hipStream_t s, Buffers& b, const double* x, double* xn, const
   }
   double shifts[8];
   for (int j = 0; j < r; ++j) shifts[j] = co.c[2 * j];
-  form_shifts_v(s, b.g, b.z, mp, shifts, r);
+  form_shifts_v(s, b.g, b.z, b.m, mp, shifts, r);
   potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, r, dinfo_slot);
   GemmProblem pn = gemm_problem(mp, mp, r * mp, b.w, mp, 0, b.w, mp, 1, b.nmat, mp, 1.0, 0.0,
                                 nullptr, 0, kAUpper | kBLower | kOutUpper | kMirror);
@@ -466,7 +466,7 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
     potrf_inv_f32(s2, b.z32, S, b.w32, S, mp, n32, dinfo32, &chain32);
   }
   if (n64 > 0) {
-    form_shifts_v(s, b.g, b.z, mp, c64, n64);
+    form_shifts_v(s, b.g, b.z, b.m, mp, c64, n64);
     potrf_inv_f64(s, b.z, S, b.w, S, b.tmp, mp, n64, dinfo64, true, &chain64);
   }
   issue_interleaved(chain32, chain64);
@@ -570,6 +570,100 @@ int ensure_workers(ps_handle h, int n) {
   return n;
 }
 
+// The comparison iterations of Sec. 6 (Tab:ItRuntime) on the core matrix y, one step per
+// launch sequence with a schedule fixed on the host from l = beta / alpha:
+//  Sigma-DWH: Zolotarev steps with r = 1 (the l-recurrence updated per step) until
+//    1 - l <= 1e-15, plus one step for the stopping test with u^{1/3};
+//  scaled Newton, X <- (mu X + (mu X)^{-T}) / 2 (the odd rational map of the sign
+//    iteration, on the core): the step X (mu/2) (I + mu^{-2} (X^T X)^{-1}) is the r = 1
+//    step with c = 0, a = mu^{-2}, hat C = mu/2; Byers-Xu scaling mu_0 = 1/sqrt(l),
+//    mu_k = 1/sqrt(u_k), u_{k+1} = (mu_k + 1/mu_k)/2, until u_k - 1 <= 1e-15, plus one
+//    step for the stopping test with u^{1/2}.
+// Steps whose shifted Gram matrices are within the series' reach (the singular values of
+// the iterate in [l_k, 1]) use the series form of the second Zolotarev step.  The final
+// iterate is in b.x2.
+int single_step_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, double beta,
+                        const ps_opts& o, double* pin, ps_info& inf, Timer& tm) {
+  scale_copy(s, y, b.x0, 1.0 / alpha, b.S);
+  const double ell0 = std::min(beta / alpha, 1.0 - 1e-15);
+  std::vector<ZoloHost> sched;
+  std::vector<double> ells;   // lower bound of the singular values before each step
+  const bool newton = o.iteration == PS_ITER_NEWTON;
+  double tol;
+  if (!newton) {
+    tol = std::pow(std::ldexp(1.0, -53), 1.0 / 3.0);
+    double ell = ell0;
+    for (int k = 0; k < 30; ++k) {
+      ZoloHost c;
+      if (zolotarev_host(std::min(ell, 1.0 - 1e-16), 1, &c)) return PS_NOT_CONVERGED;
+      sched.push_back(c);
+      ells.push_back(ell);
+      const bool done = 1.0 - ell <= 1e-15;
+      ell = std::min(c.ell_next, 1.0 - 1e-16);
+      if (done) break;
+      if (1.0 - ell <= 1e-15) {
+        if (zolotarev_host(ell, 1, &c)) return PS_NOT_CONVERGED;
+        sched.push_back(c);
+        ells.push_back(ell);
+        break;
+      }
+    }
+  } else {
+    tol = std::pow(std::ldexp(1.0, -53), 0.5);
+    double mu = 1.0 / std::sqrt(ell0), u = 0.5 * (mu + 1.0 / mu), lo = ell0;
+    for (int k = 0; k < 60; ++k) {
+      ZoloHost c{};
+      c.r = 1;
+      c.c[0] = 0.0;
+      c.a[0] = 1.0 / (mu * mu);
+      c.chat = 0.5 * mu;
+      sched.push_back(c);
+      ells.push_back(lo);
+      if (k > 0 && u - 1.0 <= 1e-15) break;
+      if (k > 0) u = 0.5 * (mu + 1.0 / mu);
+      mu = 1.0 / std::sqrt(u);
+      lo = 1.0;   // after the first step the moduli lie in [1, u]
+    }
+  }
+  inf.r = 1;
+  const double* xin = b.x0;
+  double* bufs[2] = {b.x1, b.x2};
+  int k = 0;
+  for (const ZoloHost& c : sched) {
+    double* xout = bufs[k & 1];
+    // Sigma-DWH steps after the first: the series form when it reaches 1e-17 (Newton
+    // steps always factorize: their iterates' singular values lie above 1)
+    double gam[kMaxSeries];
+    const int P = (o.step2_series && k > 0 && !newton) ? series_terms(c, ells[k], gam) : 0;
+    if (P > 0)
+      zolo_step_series(s, b, xin, xout, c, P, gam);
+    else
+      zolo_step_f64(s, b, xin, xout, c, b.dinfo + 1);
+    xin = xout;
+    ++k;
+  }
+  tm.mark(2);
+  inf.steps = k;
+  inf.shifts_fp64[0] = 1;
+  // stopping test on the last two iterates
+  const double* last = bufs[(k - 1) & 1];
+  const double* prev = k >= 2 ? bufs[(k - 2) & 1] : b.x0;
+  diff_norms(s, prev, last, b.S, b.norms);
+  PS_HIP(hipMemcpyAsync(pin, b.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  const int* di = (const int*)(pin + 8);
+  if (di[1]) {
+    inf.failed_step = 1;
+    inf.failed_mask = di[1];
+    return PS_SHIFT_BREAKDOWN;
+  }
+  inf.step_change = std::sqrt(pin[0]) / std::sqrt(pin[1]);
+  if (last != b.x2) PS_HIP(hipMemcpyAsync(b.x2, last, b.S * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!(inf.step_change <= tol)) return PS_NOT_CONVERGED;
+  return PS_OK;
+}
+
 // The Zolotarev iteration of Alg. 8 on the core matrix y (padded b.mp x b.mp, zero
 // padding): X0 = y / alpha, l = beta / alpha, two steps per attempt, the stopping
 // test ||X2 - X1||_F / ||X2||_F <= u^{1/(2r+1)} and restarts from X2 with bounds
@@ -578,6 +672,7 @@ int ensure_workers(ps_handle h, int n) {
 int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, double beta,
                   int r_opt, const ps_opts& o, double* pin, ps_info& inf, Timer& tm,
                   const MixedCtx* mx = nullptr) {
+  if (o.iteration != PS_ITER_ZOLO) return single_step_iterate(s, b, y, alpha, beta, o, pin, inf, tm);
   const int mp = b.mp;
   const long long S = (long long)b.S;
   const int r = r_opt <= 0 ? 8 : std::min(r_opt, 8);
@@ -765,7 +860,58 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   }
 
   const double* U = b.x2;
-  if (what == 1 && o.basis == PS_BASIS_CORE) {
+  // ---- FP64 Newton-Schulz pass on the polar factor: U <- U (3I - U^T U)/2 (refine 2)
+  if (o.refine >= PS_REFINE_NS) {
+    GemmProblem pg = gemm_problem(mp, mp, mp, U, mp, 1, U, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
+                                  kOutUpper | kMirror);
+    auto_split(pg, b.splitws);
+    gemm_f64(s, pg);
+    axpb_identity(s, b.g, b.g, -0.5, 1.5, mp);
+    GemmProblem pu = gemm_problem(mp, mp, mp, U, mp, 0, b.g, mp, 0, b.x1, mp);
+    auto_split(pu, b.splitws);
+    gemm_f64(s, pu);
+    mask_pad(s, b.x1, m, mp, S, 1);
+    U = b.x1;
+  }
+  tm.mark(4);
+  if (what == 1 && o.basis == PS_BASIS_CORE && o.refine == PS_REFINE_NONE && mixed) {
+    // ---- the core basis in the bulk precision (no FP64 refinement): the same products
+    // and Cholesky factorization as below on FP32 matrix cores, the element-wise steps
+    // in FP64; the result of the low-precision path before any refinement
+    float* u32 = b.x32;    // U
+    float* wm32 = b.d32;   // R_M^{-1}
+    float* wk32 = b.t32;   // R_K^{-1}
+    float* t132 = b.u32;   // R_M^{-1} U
+    float* g32 = b.z32;    // G, then its factor
+    float* wg32 = b.w32;   // R_G^{-1}
+    cvt_f64_f32(s, U, u32, b.S);
+    cvt_f64_f32(s, b.wmk, wm32, b.S);
+    cvt_f64_f32(s, b.wmk + S, wk32, b.S);
+    tm.mark(5);
+    gemm_f32(s, gemm_problem(mp, mp, mp, wm32, mp, 0, u32, mp, 0, t132, mp, 1.0, 0.0, nullptr,
+                             0, kAUpper));
+    gemm_f32(s, gemm_problem(mp, mp, mp, wk32, mp, 1, t132, mp, 0, b.y32, mp, 1.0, 0.0, nullptr,
+                             0, kALower));
+    cvt_f32_f64(s, b.y32, b.t2, b.S);
+    sym_scale_upper(s, b.t2, b.p11, m, mp, 1.0);
+    cvt_f64_f32(s, b.p11, g32, b.S);
+    potrf_inv_f32(s, g32, S, wg32, S, mp, 1, b.dinfo + 4);
+    gemm_f32(s, gemm_problem(mp, mp, mp, t132, mp, 0, wg32, mp, 0, b.y32, mp, 1.0, 0.0, nullptr,
+                             0, kBUpper));
+    gemm_f32(s, gemm_problem(mp, mp, mp, wk32, mp, 0, wg32, mp, 0, b.n32, mp, 1.0, 0.0, nullptr,
+                             0, kAUpper | kBUpper));
+    cvt_f32_f64(s, b.y32, b.t2, b.S);
+    cvt_f32_f64(s, b.n32, b.s12, b.S);
+    sum_diff_scaled(s, b.t2, b.s12, b.top, b.qbot, M_SQRT1_2, mp);
+    tm.mark(6);
+    gemm_f32(s, gemm_problem(mp, mp, mp, wg32, mp, 1, wg32, mp, 0, t132, mp, 2.0, 0.0, nullptr,
+                             0, kALower | kBUpper | kOutUpper | kMirror));
+    cvt_f32_f64(s, t132, b.hp, b.S);
+    tm.mark(7);
+    copy_out(s, b.top, mp, out1, ld1, m, m);
+    copy_out(s, b.qbot, mp, out1 + m, ld1, m, m);
+    copy_out(s, b.hp, mp, out2, ld2, m, m);
+  } else if (what == 1 && o.basis == PS_BASIS_CORE) {
     // ---- basis from the half-size core (no sign blocks needed).  With Q_h the
     // orthogonal symmetric [[I, I], [I, -I]]/sqrt(2), Q_h H Q_h = [[0, K], [M, 0]] maps
     // Z = Q_h [R_M^{-1} U; R_K^{-1}] onto Z P, P = U^T Y0, when U is the polar factor of
@@ -889,6 +1035,167 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   return PS_OK;
 }
 
+
+// ---------------------------------------------------------------- any signature
+// Division of a definite pseudosymmetric H of any signature Sigma = diag(sigma) (Sigma H
+// symmetric positive definite; the random matrices of Sec. 6.1).  With
+// M = Sigma H = R^T R and T = R Sigma R^T, H = R^{-1} T R, so sign(H) = R^{-1} sign(T) R,
+// and sign(T) of the symmetric T is its polar factor: the Zolotarev iteration of Alg. 8
+// on T (same alpha, beta, coefficients and stopping test, T^2 + c I SPD) runs on the
+// kernels of the Casida form at size n.  The bases follow Alg. 6 as printed (Cholesky of
+// the leading r_+ x r_+ block of Sigma P_+ and the leading r_- x r_- block of
+// -Sigma P_-, r_+- the numbers of +-1 in Sigma, Thm. EVREalSigmaOrth), Q_- with the sign
+// of Thm. HRisLDL, and the decoupled blocks H_+ = Q_+^T M Q_+ = (R Q_+)^T (R Q_+),
+// H_- = -(R Q_-)^T (R Q_-) (Thm. DefDivConq).
+size_t general_bytes(int n, const ps_opts& o) {
+  Arena a;
+  Buffers b;
+  carve(a, b, n, resolve_r(o), 1, mixed_arith(o, n));
+  a.take<double>(pad_to(n));   // the signs
+  return a.off + kAlign;
+}
+
+int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigma, double* S_out,
+                int ldso, double* Qp, int ldqp, double* Qm, int ldqm, double* Hp, int ldhp,
+                double* Hm, int ldhm, const ps_opts& o, ps_info* info) {
+  hipStream_t s = h->stream;
+  const int r = resolve_r(o);
+  char* base = workspace_base(h, general_bytes(n, o));
+  if (!base) return PS_NO_WORKSPACE;
+  Arena ar;
+  ar.base = base;
+  ar.dry = false;
+  Buffers b;
+  carve(ar, b, n, r, 1, mixed_arith(o, n));
+  double* sg = ar.take<double>(pad_to(n));
+  const int np = b.mp;
+  const long long S = (long long)b.S;
+  double* pin = h->pinned;
+  int p = 0;
+  for (int i = 0; i < n; ++i) p += sigma[i] > 0 ? 1 : 0;
+  const int q = n - p;
+  for (int i = 0; i < np; ++i) pin[i] = i < n ? sigma[i] : 0.0;
+  PS_HIP(hipMemcpyAsync(sg, pin, np * sizeof(double), hipMemcpyHostToDevice, s));
+  PS_HIP(hipStreamSynchronize(s));   // the staging area is reused below
+
+  ps_info inf{};
+  inf.failed_step = -1;
+  inf.r = r;
+  Timer tm{h, o.timing != 0};
+  tm.mark(-1);
+  fill_int_zero(s, b.dinfo, 16);
+  // ---- M = Sigma H = R^T R (in mk), W = R^{-1} (in wmk)
+  double* R = b.mk;
+  double* W = b.wmk;
+  pack_general(s, n, np, H, ldh, sg, R);
+  potrf_inv_f64(s, R, S, W, S, b.tmp, np, 1, b.dinfo + 0, true, nullptr, b.y, S);
+  // ---- T = R Sigma R^T (y) and T^{-1} = W^T Sigma W (y + S): symmetric, zero padding
+  scale_signs(s, R, b.t1, n, np, sg, true);    // R Sigma
+  scale_signs(s, W, b.t2, n, np, sg, false);   // Sigma W
+  {
+    GemmProblem pg[2];
+    pg[0] = gemm_problem(np, np, np, b.t1, np, 0, R, np, 1, b.y, np, 1.0, 0.0, nullptr, 0,
+                         kAUpper | kBLower | kOutUpper | kMirror);
+    pg[1] = gemm_problem(np, np, np, W, np, 1, b.t2, np, 0, b.y + S, np, 1.0, 0.0, nullptr, 0,
+                         kALower | kBUpper | kOutUpper | kMirror);
+    gemm_f64(s, pg, 2);
+  }
+  tm.mark(0);
+  // ---- alpha >= sigma_max(T) = max |lambda(H)|, beta <= 1 / sigma_max(T^{-1}) (Alg. 8)
+  double alpha = o.alpha, beta = o.beta;
+  if (!(alpha > 0.0) || !(beta > 0.0)) {
+    double a_est, b_est;
+    estimate_bounds(s, b, b.y, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a_est, &b_est,
+                    inf.sigma_est);
+    if (!(alpha > 0.0)) alpha = a_est;
+    if (!(beta > 0.0)) beta = b_est;
+  }
+  PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  if (((int*)pin)[0] != 0) {
+    inf.status = PS_NOT_DEFINITE;
+    inf.failed_step = 0;
+    inf.failed_mask = ((int*)pin)[0];
+    if (info) *info = inf;
+    return PS_NOT_DEFINITE;
+  }
+  inf.alpha = alpha;
+  inf.beta = beta;
+  tm.mark(1);
+  // ---- sign(T) by the Zolotarev iteration with the stopping test of Alg. 8
+  MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
+  const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm,
+                                   mixed_arith(o, n) ? &mxc : nullptr);
+  if (status != PS_OK) {
+    inf.status = status;
+    tm.finish(inf.phase_ms);
+    if (info) *info = inf;
+    return status;
+  }
+  // ---- sign(H) = W U R (s12), zero padding
+  {
+    GemmProblem p1 = gemm_problem(np, np, np, W, np, 0, b.x2, np, 0, b.t1, np, 1.0, 0.0, nullptr,
+                                  0, kAUpper);
+    auto_split(p1, b.splitws);
+    gemm_f64(s, p1);
+    GemmProblem p2 = gemm_problem(np, np, np, b.t1, np, 0, R, np, 0, b.s12, np, 1.0, 0.0, nullptr,
+                                  0, kBUpper);
+    auto_split(p2, b.splitws);
+    gemm_f64(s, p2);
+  }
+  const double* Sg = b.s12;
+  if (S_out) copy_out(s, Sg, np, S_out, ldso, n, n);
+  tm.mark(5);
+  // ---- Alg. 6 for one sign: k leading indices, a = +1 (Sigma P_+) or -1 (-Sigma P_-),
+  // top block t Sigma C^T (t = +1, resp. -1), bottom (a/2) S(k:n, 0:k) C^{-1}; then the
+  // decoupled block hs (R Q)^T (R Q)
+  auto basis = [&](int k, double a, double t, double hs, double* Qout, int ldqo, double* Hout,
+                   int ldho, int slot) {
+    if (k == 0) return;
+    const int kp = pad_to(k), rp = pad_to(std::max(n - k, 1));
+    lead_block(s, Sg, np, sg, k, kp, a, b.p11);
+    potrf_inv_f64(s, b.p11, 0, b.wc, 0, b.tmp, kp, 1, b.dinfo + slot, true, nullptr, b.t2, 0);
+    chol_top(s, b.p11, kp, sg, k, t, b.top);
+    double* Q = b.ab;   // np x kp, ld np
+    copy_pad(s, b.top, kp, k, k, Q, np, k, kp);
+    if (n > k) {
+      copy_pad(s, Sg + k, np, n - k, k, b.qbot, rp, rp, kp);
+      GemmProblem pb = gemm_problem(rp, kp, kp, b.qbot, rp, 0, b.wc, kp, 0, b.t1, rp, 0.5 * a, 0.0,
+                                    nullptr, 0, kBUpper);
+      gemm_f64(s, pb);
+      copy_pad(s, b.t1, rp, n - k, k, Q + k, np, np - k, kp);
+    } else if (np > k) {
+      copy_pad(s, b.t1, rp, 0, 0, Q + k, np, np - k, kp);   // zero padding rows
+    }
+    GemmProblem pf = gemm_problem(np, kp, np, R, np, 0, Q, np, 0, b.F, np, 1.0, 0.0, nullptr, 0,
+                                  kAUpper);
+    gemm_f64(s, pf);
+    GemmProblem ph = gemm_problem(kp, kp, np, b.F, np, 1, b.F, np, 0, b.hp, kp, hs, 0.0, nullptr,
+                                  0, kOutUpper | kMirror);
+    auto_split(ph, b.splitws);
+    gemm_f64(s, ph);
+    copy_out(s, Q, np, Qout, ldqo, n, k);
+    copy_out(s, b.hp, kp, Hout, ldho, k, k);
+  };
+  basis(p, 1.0, 1.0, 1.0, Qp, ldqp, Hp, ldhp, 4);
+  tm.mark(6);
+  basis(q, -1.0, -1.0, -1.0, Qm, ldqm, Hm, ldhm, 5);
+  tm.mark(7);
+  PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  const int* di = (const int*)(pin + 8);
+  if (di[4] || di[5]) {
+    inf.status = PS_BASIS_BREAKDOWN;
+    inf.failed_step = 4;
+    inf.failed_mask = di[4] ? 1 : 2;
+    if (info) *info = inf;
+    return PS_BASIS_BREAKDOWN;
+  }
+  tm.finish(inf.phase_ms);
+  inf.status = PS_OK;
+  if (info) *info = inf;
+  return PS_OK;
+}
 
 // ---------------------------------------------------------------- eigen-decomposition
 // Leaves of the recursion: subproblems of at most this size go to the Jacobi kernel.
@@ -1363,7 +1670,11 @@ int check_common(ps_handle h, int m, const double* A, int lda, const double* B, 
   if (ldb < m) return -6;
   if (o && (o->r < 0 || o->r > 8 || o->max_restarts < 0 || o->max_steps < 0 ||
             o->max_steps > 1 || (o->precision != PS_PREC_FP64 && o->precision != PS_PREC_MIXED) ||
-            (o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE)))
+            (o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE) ||
+            o->iteration < PS_ITER_ZOLO || o->iteration > PS_ITER_NEWTON ||
+            o->refine < PS_REFINE_NONE || o->refine > PS_REFINE_NS ||
+            (o->iteration != PS_ITER_ZOLO &&
+             (o->precision != PS_PREC_FP64 || o->max_steps != 0))))
     return -11;
   return 0;
 }
@@ -1907,6 +2218,8 @@ void ps_opts_default(ps_opts* o) {
   o->mixed_kappa = 20.0;
   o->step2_series = 1;
   o->basis = PS_BASIS_ALG6;
+  o->iteration = PS_ITER_ZOLO;
+  o->refine = PS_REFINE_RR;
 }
 
 int ps_create(ps_handle* h, void* stream) {
@@ -1962,6 +2275,7 @@ size_t ps_workspace_size(int m, const ps_opts* o, int what) {
   ps_opts d;
   ps_opts_default(&d);
   if (m < 1) return 0;
+  if (what == 4) return general_bytes(m, o ? *o : d);
   if (what >= 3) return adjoint_bytes(m);
   return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : what);
 }
@@ -2067,6 +2381,43 @@ int pseudosym_divide_static(ps_handle h, int m, const double* A, int lda, const 
     char* ws = (char*)static_scratch_ptr();   // this device's copy, looked up at set-up
     if (!ws) return (int)PS_HIP_ERROR;
     return run(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, info, 1, ws);
+  });
+}
+
+int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const double* sigma,
+                             double* S, int lds, double* Qp, int ldqp, double* Qm, int ldqm,
+                             double* Hp, int ldhp, double* Hm, int ldhm, const ps_opts* opts,
+                             ps_info* info) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!H) return -3;
+  if (ldh < n) return -4;
+  if (!sigma) return -5;
+  int p = 0;
+  for (int i = 0; i < n; ++i) {
+    if (sigma[i] != 1.0 && sigma[i] != -1.0) return -5;
+    p += sigma[i] > 0 ? 1 : 0;
+  }
+  const int q = n - p;
+  if (S && lds < n) return -7;
+  if (p > 0 && !Qp) return -8;
+  if (p > 0 && ldqp < n) return -9;
+  if (q > 0 && !Qm) return -10;
+  if (q > 0 && ldqm < n) return -11;
+  if (p > 0 && !Hp) return -12;
+  if (p > 0 && ldhp < p) return -13;
+  if (q > 0 && !Hm) return -14;
+  if (q > 0 && ldhm < q) return -15;
+  if (n > kPinned) return -2;
+  if (opts && (opts->r < 0 || opts->r > 8 || opts->max_restarts < 0 || opts->max_steps != 0 ||
+               (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED)))
+    return -16;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  return guarded(h, [&] {
+    return run_general(h, n, H, ldh, sigma, S, lds, Qp, ldqp, Qm, ldqm, Hp, ldhp, Hm, ldhm, o,
+                       info);
   });
 }
 

@@ -189,6 +189,7 @@ void sum_diff_scaled(hipStream_t s, const double* e1, const double* e2, double* 
 void form_shifts_f32(hipStream_t s, const double* g, float* z, int mp, const double* shifts,
                      int r);   // z[j] = fp32(upper(G) + shifts[j] I)
 void cvt_f64_f32(hipStream_t s, const double* x, float* y, size_t n);
+void cvt_f32_f64(hipStream_t s, const float* x, double* y, size_t n);
 void axpy_f32(hipStream_t s, double* y, double a, double b, const float* x, size_t n);
 void axpb_identity_f32(hipStream_t s, const float* x, float* y, float a, float b, int mp);
 
@@ -228,6 +229,16 @@ void build_gbar(hipStream_t s, const double* ga, const double* gb, int ldg, int 
 void dk_hadamard(hipStream_t s, double* t, int np, const double* lam, int m);
 void grad_assemble(hipStream_t s, const double* k, int np, int m, double* ga, double* gb,
                    int ldo);
+
+// division for any signature (general.hip); sg holds sigma (0 beyond n)
+void pack_general(hipStream_t s, int n, int np, const double* H, int ldh, const double* sg,
+                  double* m);   // upper(sym(Sigma H)), pad diag 1
+void scale_signs(hipStream_t s, const double* x, double* y, int n, int np, const double* sg,
+                 bool cols);    // y = Sigma x (rows) or x Sigma (cols), zero padding
+void lead_block(hipStream_t s, const double* S, int lds, const double* sg, int k, int kp, double a,
+                double* out);   // upper(sym(Sigma (a I + S)/2)) on the leading k x k, pad diag 1
+void chol_top(hipStream_t s, const double* c, int kp, const double* sg, int k, double t,
+              double* top);     // top(i, j) = t sigma_i C(j, i)
 
 // Golub-Kahan bidiagonalization (batch of two matrices M_b with transposes Mt_b).
 void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned seed);

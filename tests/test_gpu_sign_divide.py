@@ -353,3 +353,30 @@ def test_divide_core_basis(m, seed, kind, precision):
     lam, _ = eg.eig_casida(a, b)
     w = np.linalg.eigvalsh(Hp)
     assert np.max(np.abs(w - lam[:m]) / lam[:m]) < 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_refinement_levels_m2048():
+    """Mixed precision at the benchmark size, core basis, with each refinement level:
+    none (basis and H_+ in FP32 too: the low-precision result), rr (FP64
+    Sigma-orthonormalization and Rayleigh-Ritz block: 1e-10) and ns (an FP64
+    Newton-Schulz pass on the polar factor first: 1e-10).  At level none H_+ is formed by
+    FP32 products over n = 2m terms, so its perturbation is about sqrt(n) u32 |H_+| and
+    the relative eigenvalue error is bounded by sqrt(n) u32 kappa(H_+)."""
+    m = 2048
+    ref = full_size_reference(m, 1)
+    a, b, sigma = ref["a"], ref["b"], ref["sigma"]
+    errs = {}
+    for level in ("none", "rr", "ns"):
+        Qp, Hp, info = api.divide(dev(a), dev(b), precision="mixed", basis="core", refine=level)
+        assert info["status"] == 0
+        Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+        w = np.linalg.eigvalsh(0.5 * (Hp + Hp.T))
+        errs[level] = np.max(np.abs(w - ref["lam"]) / ref["lam"])
+        orth = np.abs(Qp.T @ (sigma[:, None] * Qp) - np.eye(m)).max()
+        print(f"[refine {level}] eig err {errs[level]:.3e} orth {orth:.3e}", flush=True)
+        assert orth < (1e-4 if level == "none" else 1e-10)
+    u32 = float(np.finfo(np.float32).eps) / 2
+    kappa = ref["lam"].max() / ref["lam"].min()
+    assert errs["none"] < np.sqrt(2 * m) * u32 * kappa
+    assert errs["rr"] < 1e-10 and errs["ns"] < 1e-10
