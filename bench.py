@@ -75,8 +75,7 @@ def gpu_leg(args, a, b):
     torch.cuda.synchronize()
     out = {}
     for mode in args.modes:
-        kw = dict(precision=mode.split("-")[0], r=args.r,
-                  basis="core" if mode.endswith("-core") else "alg6")
+        kw = mode_options(mode, args.r)
         for _ in range(args.warmup):
             api.divide(A, B, **kw)
         torch.cuda.synchronize()
@@ -111,6 +110,14 @@ def gpu_leg(args, a, b):
     return out
 
 
+def mode_options(mode: str, r: int):
+    """precision[-core][-norefine]: FP64 or mixed steps, Alg. 6 or the core basis, and the
+    FP64 refinement (default) or none (the mixed path's result before refinement)."""
+    parts = mode.split("-")
+    return dict(precision=parts[0], r=r, basis="core" if "core" in parts else "alg6",
+                refine="none" if "norefine" in parts else "rr")
+
+
 def batched_leg(args):
     """256 independent problems, m_i uniform over {32..512}: one batched call (worker
     streams) against the same problems called one at a time."""
@@ -124,8 +131,7 @@ def batched_leg(args):
     Bs = [torch.tensor(b, dtype=torch.float64, device="cuda:0") for _, b in probs]
     out = {}
     for mode in args.modes:
-        kw = dict(precision=mode.split("-")[0], r=args.r,
-                  basis="core" if mode.endswith("-core") else "alg6")
+        kw = mode_options(mode, args.r)
         for _ in range(args.warmup):
             api.divide_batched(As, Bs, **kw)
         torch.cuda.synchronize()
@@ -234,6 +240,47 @@ def adjoint_leg(args):
             "config": {"workload": "casida_like m=1024 (n=2048) seed 3, W symmetric Gaussian "
                                    "seed 1003", "n": 2 * m, "m": m},
             "forward_ms": ms_f, "backward_ms": ms_b, "rel_grad_err_vs_oracle": err}
+
+
+def general_leg(args):
+    """Division of the random definite pseudosymmetric matrices of the paper's experiments
+    (any signature, H = Sigma Q D Q^T, D equally spaced in [1, kappa]): the n = 5000
+    matrix of the runtime table at kappa = 1e2 (time per divide, backward error), and the
+    n = 250 backward-error experiment (10 matrices per kappa, kappa = 1e1 .. 1e6)."""
+    import numpy as np
+    import torch
+    from paper_2203_08900_amd import api, inputs
+
+    n = args.m or 5000
+    h, sig = inputs.general_sigma(n, 0, 1e2)
+    H = torch.tensor(h, dtype=torch.float64, device="cuda:0")
+    ms, (Qp, Qm, Hp, Hm, _, info) = _timed(lambda: api.divide_general(H, sig), args.steps,
+                                           args.warmup)
+    Hs = torch.tensor(sig[:, None] * h, dtype=torch.float64, device="cuda:0")
+    bwd = float(torch.linalg.norm(Qp.T @ Hs @ Qm) / torch.linalg.norm(H))
+    sweep = {}
+    for kappa in (1e1, 1e2, 1e4, 1e6):
+        errs = []
+        for seed in range(10):
+            h2, s2 = inputs.general_sigma(250, 100 + seed, kappa)
+            H2 = torch.tensor(h2, dtype=torch.float64, device="cuda:0")
+            qp, qm, _, _, _, inf = api.divide_general(H2, s2, raise_on_error=False)
+            if inf["rc"] != 0:
+                errs.append(float("nan"))
+                continue
+            S2 = torch.tensor(s2[:, None] * h2, dtype=torch.float64, device="cuda:0")
+            errs.append(float(torch.linalg.norm(qp.T @ S2 @ qm) / torch.linalg.norm(H2)))
+        sweep[f"{kappa:g}"] = {"mean": float(np.nanmean(errs)), "max": float(np.nanmax(errs)),
+                               "failures": int(np.sum(np.isnan(errs)))}
+    return {"metric": "spectral division of a definite pseudosymmetric matrix, any signature",
+            "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"general_sigma n={n} seed 0 kappa=1e2: H = Sigma Q D Q^T, "
+                                   "random signature, D = linspace(1, kappa)", "n": n,
+                       "r_plus": int(np.sum(sig > 0))},
+            "steps_taken": info["steps"], "restarts": info["restarts"], "backward_error": bwd,
+            "backward_error_n250": sweep}
 
 
 def copy_probe(nbytes: int = 512 << 20):
@@ -347,10 +394,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="casida_n4096",
                     choices=["casida_n4096", "ill_separated_n16384", "batched_256", "eig_n128",
-                             "eig_n4096", "adjoint_n2048"])
+                             "eig_n4096", "adjoint_n2048", "general_n5000"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
     ap.add_argument("--r", type=int, default=8)
-    ap.add_argument("--modes", default="fp64,mixed,fp64-core,mixed-core")
+    ap.add_argument("--modes", default="fp64,mixed,fp64-core,mixed-core,mixed-core-norefine")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain device copy of 512 MiB three times (calibrates the "
@@ -376,6 +423,9 @@ def main():
         return
     if args.workload == "adjoint_n2048":
         print(json.dumps(adjoint_leg(args)), flush=True)
+        return
+    if args.workload == "general_n5000":
+        print(json.dumps(general_leg(args)), flush=True)
         return
     if args.workload == "casida_n4096":
         args.m = args.m or 2048
@@ -460,6 +510,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "rel_eig_err": rel_err.get(primary),
+        "rel_eig_err_before_refinement": rel_err.get("mixed-core-norefine"),
         "modes": {k: {"ms": v["ms"], "tflops": v["tflops"], "rel_eig_err": rel_err.get(k),
                       "phase_ms": [round(x, 4) for x in v["phase_ms"]],
                       "alpha": v["info"]["alpha"], "beta": v["info"]["beta"],
