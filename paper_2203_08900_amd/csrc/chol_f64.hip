@@ -172,9 +172,15 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
   if (t == 0 && k0 > 0) {
     T* src = W - (long long)NB * ld;              // block (k, k-1) of W
     T* dst = Z - NB - (long long)NB * ld;         // block (k-1, k-1) of Z
-    for (int e = threadIdx.x; e < NB * NB; e += NTD) {
+    // every load ahead of the stores (the compiler may not move loads past stores
+    // through pointers that could alias)
+    T val[Q];
+    load_block(src, ld, val);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + q * NTD;
       const long long o = e % NB + (long long)(e / NB) * ld;
-      dst[o] = src[o];
+      dst[o] = val[q];
       src[o] = T(0);
     }
   }
