@@ -304,6 +304,116 @@ __device__ __forceinline__ void inverse_tile(T* lds, int q, T* z, long long sz, 
       Vij[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld] = acc[t][u];
 }
 
+// One 64 x 64 tile of a trailing update D = alpha op(A) op(B) + beta C with op(A) = A^T,
+// op(B) = B and a short K (64 or 128, the panel rows).  Every global access is a
+// coalesced 16-byte vector along the contiguous dimension (a column of C and D, a K run
+// of A and B), which moves several times more bytes per compute unit than loads in the
+// matrix-core fragment layout: all loads of the tile are issued at once, the operands
+// go through LDS to the matrix cores, and the result goes back through LDS so that the
+// stores are coalesced too.  Wave w owns the 32 x 32 sub-tile (w % 2, w / 2).  C may be
+// D (it is read before any store); with kOutUpper the entries below the diagonal keep
+// their C values.  Operand addresses are 16-byte aligned (checked by the launcher).
+template <class T>
+__device__ __forceinline__ void trail_tile(const GemmProblemT<T>& P, int bid, T* lds) {
+  using Acc = typename Mfma<T>::acc_t;
+  constexpr int VW = 16 / sizeof(T);     // elements per 16-byte access
+  constexpr int TPC = 64 / VW;           // threads per 64-element column
+  constexpr int CPI = NTD / TPC;         // columns per block-wide access
+  constexpr int NV = 64 / CPI;           // accesses per 64 x 64 block
+  constexpr int LDT = 64 + VW;           // LDS row length (keeps rows 16-byte aligned)
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  const int z = bid / P.tiles_per_batch, t = bid - z * P.tiles_per_batch;
+  int I, J;
+  if (P.flags & kOutUpper) {
+    tri_index(t, J, I);
+  } else {
+    I = t % P.tm;
+    J = t / P.tm;
+  }
+  const int tid = threadIdx.x;
+  const int i0 = 64 * I, j0 = 64 * J;
+  const T* A = P.A + z * P.sA[0] + (long long)i0 * P.lda;   // op(A)(i, k) = A[k + i lda]
+  const T* B = P.B + z * P.sB[0] + (long long)j0 * P.ldb;   // op(B)(k, j) = B[k + j ldb]
+  const T* C = P.C + z * P.sC[0] + i0 + (long long)j0 * P.ldc;
+  T* D = P.D + z * P.sD[0] + i0 + (long long)j0 * P.ldd;
+  const int e0 = VW * (tid % TPC), c0 = tid / TPC;   // this thread's run: [e0, e0 + VW) of
+                                                     // columns c0 + CPI q
+  const int nch = P.K / 64;                          // 1 or 2 chunks of 64
+  vec_t cv[NV], av[2][NV], bv[2][NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    cv[q] = *reinterpret_cast<const vec_t*>(C + e0 + (long long)(c0 + CPI * q) * P.ldc);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h < nch) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        av[h][q] = *reinterpret_cast<const vec_t*>(A + 64 * h + e0 + (long long)(c0 + CPI * q) * P.lda);
+        bv[h][q] = *reinterpret_cast<const vec_t*>(B + 64 * h + e0 + (long long)(c0 + CPI * q) * P.ldb);
+      }
+    }
+  }
+  T* As = lds;                 // [i][k], row length LDT
+  T* Bs = lds + 64 * LDT;      // [j][k]
+  const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int ib = 32 * (wave & 1), jb = 32 * (wave >> 1);
+  Acc acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h < nch) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        *reinterpret_cast<vec_t*>(As + (c0 + CPI * q) * LDT + e0) = av[h][q];
+        *reinterpret_cast<vec_t*>(Bs + (c0 + CPI * q) * LDT + e0) = bv[h][q];
+      }
+      __syncthreads();
+      // lane lk takes k = 16 lk + kk (both operands agree on the k of every slot)
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = 16 * lk + kk;
+        T xa[2], xb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          xa[a] = As[(ib + 16 * a + li) * LDT + k];
+          xb[a] = Bs[(jb + 16 * a + li) * LDT + k];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::step(xa[a], xb[b], acc[a][b]);
+      }
+      __syncthreads();
+    }
+  }
+  // the product to LDS as [j][i], then D = alpha acc + beta C in the coalesced layout
+  T* Ds = lds;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ds[(jb + 16 * b + li) * LDT + ib + 16 * a + Mfma<T>::row(lk, v)] = acc[a][b][v];
+  __syncthreads();
+  const bool upper = (P.flags & kOutUpper) && I == J;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const int jj = c0 + CPI * q;
+    const vec_t pv = *reinterpret_cast<const vec_t*>(Ds + jj * LDT + e0);
+    vec_t out;
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      const T val = (T)(P.alpha * (double)pv[u] + P.beta * (double)cv[q][u]);
+      out[u] = (upper && e0 + u > jj) ? cv[q][u] : val;
+    }
+    *reinterpret_cast<vec_t*>(D + e0 + (long long)jj * P.ldd) = out;
+  }
+}
+
 // One launch of the factorization: workgroups below ndiag run diag_panel for the block
 // at k0 (with the previous panel's update of block row k0 when fold is set); the others
 // are tiles of the trailing update, `tp` then `tq` (np tiles of tp), that the step
@@ -322,16 +432,16 @@ __attribute__((amdgpu_waves_per_eu(step_waves<T, kWide>()))) void chol_step_kern
     T* z, long long sz, T* w, long long sw, int ld, int k0, int rest, int ntiles, int fold,
     int* info, GemmProblemT<T> tp, GemmProblemT<T> tq, int ndiag, int np, int ntrail, T* v,
     long long sv, InvPlan ip) {
-  constexpr int kAB = 2 * GemmLds<64, 64>::ASZ + 2 * GemmLds<64, 64>::BSZ;
+  constexpr int kAB = 2 * 64 * (64 + 16 / (int)sizeof(T));   // trail_tile's operands
   constexpr int kElems = kWide ? kWideElems : blk::kLdsElems;
-  __shared__ T lds[kElems > kAB ? kElems : kAB];
+  __shared__ __attribute__((aligned(16))) T lds[kElems > kAB ? kElems : kAB];
   const int bid = blockIdx.x;
   if (bid < ndiag)
     diag_panel<T, kWide>(lds, bid, z, sz, w, sw, ld, k0, rest, ntiles, fold, info);
   else if (bid < ndiag + np)
-    gemm_tile<T, 64, 64, 2, 2, 1, 0>(tp, bid - ndiag, lds);
+    trail_tile<T>(tp, bid - ndiag, lds);
   else if (bid < ndiag + ntrail)
-    gemm_tile<T, 64, 64, 2, 2, 1, 0>(tq, bid - ndiag - np, lds);
+    trail_tile<T>(tq, bid - ndiag - np, lds);
   else if constexpr (kWide)
     inverse_tile<T>(lds, bid - ndiag - ntrail, z, sz, w, sw, v, sv, ld, ip);
 }
@@ -413,6 +523,18 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
       t[q].tiles_per_batch = t[q].tiles;
       t[q].tile_begin = 0;
       cnt[q] = t[q].tiles * batch;
+    }
+    for (int q = 0; q < ntp; ++q) {
+      // trail_tile: K a multiple of 64, 16-byte aligned operands and batch strides
+      const bool ok = (t[q].K == 64 || t[q].K == 128) &&
+                      (reinterpret_cast<uintptr_t>(t[q].A) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(t[q].B) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(t[q].C) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(t[q].D) % 16) == 0 &&
+                      (t[q].sA[0] * sizeof(T)) % 16 == 0 && t[q].lda % (16 / sizeof(T)) == 0 &&
+                      t[q].ldb % (16 / sizeof(T)) == 0 && t[q].ldc % (16 / sizeof(T)) == 0 &&
+                      t[q].ldd % (16 / sizeof(T)) == 0;
+      if (!ok) throw HipError{hipErrorInvalidValue, "potrf_inv: misaligned factorization buffer"};
     }
     const GemmProblemT<T> t0 = t[0], t1 = t[1];
     const int np = cnt[0], ntrail = cnt[0] + cnt[1], grid = ndiag + ntrail + ninv;
