@@ -102,6 +102,22 @@ __device__ inline typename BlkMfma<T>::acc_t tile_mm_ta(const T* At, int ldat, c
   return acc;
 }
 
+// tile_mm_ta with the depth K fixed at compile time (operand loads ahead of the steps).
+template <class T, int K>
+__device__ inline typename BlkMfma<T>::acc_t tile_mm_ta_k(const T* At, int ldat, const T* B, int ldb) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  T a[K / 4], b[K / 4];
+#pragma unroll
+  for (int s = 0; s < K / 4; ++s) {
+    a[s] = At[(4 * s + lk) * ldat + li];
+    b[s] = B[(4 * s + lk) * ldb + li];
+  }
+  typename BlkMfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < K / 4; ++s) acc = BlkMfma<T>::step(a[s], b[s], acc);
+  return acc;
+}
+
 // Store -acc of tile_mm into a row-major LDS array.
 template <class T>
 __device__ inline void tile_store_neg(const typename BlkMfma<T>::acc_t& acc, T* D, int ldd) {

@@ -35,23 +35,62 @@ constexpr int kQt = blk::kLdsElems;
 constexpr int kUt = kQt + NB * blk::kLdS;
 constexpr int kWideElems = kUt + NB * blk::kLdS;
 
-// Load the 64 x 64 block at g (column-major, leading dimension ld) into registers, and
-// store such values row-major into LDS at l (leading dimension 65).
+// A 64 x 64 column-major block (leading dimension ld) moves between memory and
+// registers as coalesced 16-byte vectors: thread t holds rows [VW (t % TPC), + VW) of the
+// columns t / TPC + CPI q, value q VW + u in slot u of vector q.  Block origins and
+// leading dimensions are multiples of 16 bytes (checked by the launcher).
+template <class T>
+struct BlockVec {
+  static constexpr int VW = 16 / sizeof(T);   // elements per vector
+  static constexpr int TPC = NB / VW;         // threads per column
+  static constexpr int CPI = NTD / TPC;       // columns per block-wide access
+  static constexpr int NV = NB / CPI;         // vectors per thread
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  __device__ static int row0() { return VW * ((int)threadIdx.x % TPC); }
+  __device__ static int col0() { return (int)threadIdx.x / TPC; }
+};
 template <class T>
 __device__ inline void load_block(const T* g, long long ld, T (&val)[NB * NB / NTD]) {
+  using V = BlockVec<T>;
+  const int e0 = V::row0(), c0 = V::col0();
 #pragma unroll
-  for (int q = 0; q < NB * NB / NTD; ++q) {
-    const int e = threadIdx.x + q * NTD;
-    val[q] = g[e % NB + (long long)(e / NB) * ld];
+  for (int q = 0; q < V::NV; ++q) {
+    const auto x = *reinterpret_cast<const typename V::vec_t*>(g + e0 + (long long)(c0 + V::CPI * q) * ld);
+#pragma unroll
+    for (int u = 0; u < V::VW; ++u) val[q * V::VW + u] = x[u];
   }
 }
 template <class T>
-__device__ inline void stage_block(T* l, const T (&val)[NB * NB / NTD]) {
+__device__ inline void store_block(T* g, long long ld, const T (&val)[NB * NB / NTD]) {
+  using V = BlockVec<T>;
+  const int e0 = V::row0(), c0 = V::col0();
 #pragma unroll
-  for (int q = 0; q < NB * NB / NTD; ++q) {
-    const int e = threadIdx.x + q * NTD;
-    l[(e % NB) * blk::kLdS + e / NB] = val[q];
+  for (int q = 0; q < V::NV; ++q) {
+    typename V::vec_t x;
+#pragma unroll
+    for (int u = 0; u < V::VW; ++u) x[u] = val[q * V::VW + u];
+    *reinterpret_cast<typename V::vec_t*>(g + e0 + (long long)(c0 + V::CPI * q) * ld) = x;
   }
+}
+// Registers to / from LDS row-major at l (leading dimension 65): entry (i, j) at
+// l[i * 65 + j].
+template <class T>
+__device__ inline void stage_block(T* l, const T (&val)[NB * NB / NTD]) {
+  using V = BlockVec<T>;
+  const int e0 = V::row0(), c0 = V::col0();
+#pragma unroll
+  for (int q = 0; q < V::NV; ++q)
+#pragma unroll
+    for (int u = 0; u < V::VW; ++u) l[(e0 + u) * blk::kLdS + c0 + V::CPI * q] = val[q * V::VW + u];
+}
+template <class T>
+__device__ inline void unstage_block(const T* l, T (&val)[NB * NB / NTD]) {
+  using V = BlockVec<T>;
+  const int e0 = V::row0(), c0 = V::col0();
+#pragma unroll
+  for (int q = 0; q < V::NV; ++q)
+#pragma unroll
+    for (int u = 0; u < V::VW; ++u) val[q * V::VW + u] = l[(e0 + u) * blk::kLdS + c0 + V::CPI * q];
 }
 
 // D -= P^T Q for the 16 x 16 tile (ti, tj) of row-major LDS blocks (wave-wide).
@@ -174,20 +213,20 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
     T* dst = Z - NB - (long long)NB * ld;         // block (k-1, k-1) of Z
     // every load ahead of the stores (the compiler may not move loads past stores
     // through pointers that could alias)
-    T val[Q];
+    T val[Q], zero[Q];
     load_block(src, ld, val);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + q * NTD;
-      const long long o = e % NB + (long long)(e / NB) * ld;
-      dst[o] = val[q];
-      src[o] = T(0);
-    }
+    for (int q = 0; q < Q; ++q) zero[q] = T(0);
+    store_block(dst, ld, val);
+    store_block(src, ld, zero);
   }
   blk::factor_invert_block(lds, tile ? W + NB : Z, W, ld, info, b < 30 ? b : 30, t == 0);
   if (!tile) return;
-  // wave w forms rows 16w.. of R_kk^{-T} Z(k, tile), four 16-column tiles (narrow: the
-  // updated panel tile first goes into the staging area, free again)
+  // R(k, tile) = R_kk^{-T} Z(k, tile) = W_kk^T Z(k, tile): wave w forms column tile w
+  // for the four row tiles r, each over K = 16 (r + 1) (W_kk^T is lower triangular), so
+  // that every wave takes 40 matrix-core steps; the result goes to memory through the
+  // staging area (narrow: the updated panel tile first goes into the staging area, free
+  // again, and the result waits for every wave to finish reading it)
   const T* St = stage;
   if constexpr (kWide) {
     St = lds + kUt;
@@ -200,13 +239,21 @@ __device__ __forceinline__ void diag_panel(T* lds, int bid, T* z, long long sz, 
     __syncthreads();
   }
   const T* Wl = lds + blk::kWl;
+  Acc pr[4];
+  pr[0] = blk::tile_mm_ta_k<T, 16>(Wl, blk::kLdS, St + 16 * wave, blk::kLdS);
+  pr[1] = blk::tile_mm_ta_k<T, 32>(Wl + 16, blk::kLdS, St + 16 * wave, blk::kLdS);
+  pr[2] = blk::tile_mm_ta_k<T, 48>(Wl + 32, blk::kLdS, St + 16 * wave, blk::kLdS);
+  pr[3] = blk::tile_mm_ta_k<T, 64>(Wl + 48, blk::kLdS, St + 16 * wave, blk::kLdS);
+  if constexpr (!kWide) __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const auto acc = blk::tile_mm_ta(Wl + 16 * wave, blk::kLdS, St + 16 * c, blk::kLdS, NB);
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      Zt[(16 * wave + blk::BlkMfma<T>::row(lk, v)) + (long long)(16 * c + li) * ld] = acc[v];
-  }
+      stage[(16 * r + blk::BlkMfma<T>::row(lk, v)) * blk::kLdS + 16 * wave + li] = pr[r][v];
+  __syncthreads();
+  T val[Q];
+  unstage_block(stage, val);
+  store_block(Zt, ld, val);
 }
 
 // Inverse factor alongside the factorization (one or two matrices).  With
@@ -243,65 +290,73 @@ __device__ __forceinline__ void inverse_tile(T* lds, int q, T* z, long long sz, 
   const int c = L - 1;   // the block column of W finished here
   const T* Wcc = w + b * sw + (long long)c * NB * (ld + 1);
   T* Vb = v + b * sv;
-  T* const Wl = lds;                     // W_{cc}, row-major [64][65]
-  T* const Tl = lds + NB * blk::kLdS;    // V(i, c) then T = W(i, c)
+  T* const Wl = lds;                       // W_{cc}, row-major [64][65]
+  T* const Tl = lds + NB * blk::kLdS;      // V(i, c) then T = W(i, c)
   T* const Rl = lds + 2 * NB * blk::kLdS;  // R(c, j)
+  T* const Pl = lds + 3 * NB * blk::kLdS;  // T R(c, j)
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
   const bool diag_row = (i == c);
+  T* Vij = (j >= 0) ? Vb + (long long)i * NB + (long long)j * NB * ld : nullptr;
+  // every load at once, coalesced; V(i, j) stays in registers (zero for i = c, where this
+  // workgroup sets it)
+  T vij[Q];
   {
     T vw[Q], vt[Q], vr[Q];
     load_block(Wcc, ld, vw);
     if (!diag_row) load_block(Vb + (long long)i * NB + (long long)c * NB * ld, ld, vt);
     if (j >= 0) load_block(z + b * sz + (long long)c * NB + (long long)j * NB * ld, ld, vr);
+    if (j >= 0 && !diag_row) {
+      load_block(Vij, ld, vij);
+    } else {
+#pragma unroll
+      for (int u = 0; u < Q; ++u) vij[u] = T(0);
+    }
     stage_block(Wl, vw);
     if (!diag_row) stage_block(Tl, vt);
     if (j >= 0) stage_block(Rl, vr);
   }
-  // V(i, j) in the accumulator layout (wave w: rows 16w.., four 16-column tiles)
-  Acc acc[4];
-  T* Vij = (j >= 0) ? Vb + (long long)i * NB + (long long)j * NB * ld : nullptr;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      acc[t][u] = (j >= 0 && !diag_row)
-                      ? Vij[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld]
-                      : T(0);
   __syncthreads();
-  // T = -V(i, c) W_cc, rows 16w.. of each wave (each wave reads and then overwrites only
-  // its own rows of Tl; W_cc is read by all and never written)
+  // T = -V(i, c) W_cc, rows 16w.. of each wave, column tile t over K = 16 (t + 1) (W_cc is
+  // upper triangular); each wave reads and then overwrites only its own rows of Tl
   const T* Trow = Wl;
   if (!diag_row) {
+    const T* vr = Tl + 16 * wave * blk::kLdS;
     Acc tt[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      tt[t] = blk::tile_mm(Tl + 16 * wave * blk::kLdS, blk::kLdS, Wl + 16 * t, blk::kLdS, NB);
+    tt[0] = blk::tile_mm_k<T, 16>(vr, blk::kLdS, Wl, blk::kLdS);
+    tt[1] = blk::tile_mm_k<T, 32>(vr, blk::kLdS, Wl + 16, blk::kLdS);
+    tt[2] = blk::tile_mm_k<T, 48>(vr, blk::kLdS, Wl + 32, blk::kLdS);
+    tt[3] = blk::tile_mm_k<T, 64>(vr, blk::kLdS, Wl + 48, blk::kLdS);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         Tl[(16 * wave + blk::BlkMfma<T>::row(lk, u)) * blk::kLdS + 16 * t + li] = -tt[t][u];
     Trow = Tl;
-    // the first column's workgroup (or the finishing pass) stores W(i, c)
-    if (j == L || j < 0) {
-      T* Wic = w + b * sw + (long long)i * NB + (long long)c * NB * ld;
+  }
+  // V(i, j) + T R(c, j)   (T rows of this wave only), to LDS
+  if (j >= 0) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t) {
+      const Acc pr = blk::tile_mm_k<T, 64>(Trow + 16 * wave * blk::kLdS, blk::kLdS, Rl + 16 * t, blk::kLdS);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          Wic[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld] = -tt[t][u];
+      for (int u = 0; u < 4; ++u) Pl[(16 * wave + blk::BlkMfma<T>::row(lk, u)) * blk::kLdS + 16 * t + li] = pr[u];
     }
   }
-  if (j < 0) return;
-  // V(i, j) += T R(c, j)   (T rows of this wave only)
+  __syncthreads();
+  // coalesced stores: W(i, c) by the first column's workgroup (or the finishing pass),
+  // V(i, j)
+  if (!diag_row && (j == L || j < 0)) {
+    T val[Q];
+    unstage_block(Tl, val);
+    store_block(w + b * sw + (long long)i * NB + (long long)c * NB * ld, ld, val);
+  }
+  if (j >= 0) {
+    T val[Q];
+    unstage_block(Pl, val);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-    acc[t] += blk::tile_mm(Trow + 16 * wave * blk::kLdS, blk::kLdS, Rl + 16 * t, blk::kLdS, NB);
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      Vij[(16 * wave + blk::BlkMfma<T>::row(lk, u)) + (long long)(16 * t + li) * ld] = acc[t][u];
+    for (int u = 0; u < Q; ++u) val[u] += vij[u];
+    store_block(Vij, ld, val);
+  }
 }
 
 // One 64 x 64 tile of a trailing update D = alpha op(A) op(B) + beta C with op(A) = A^T,
@@ -453,6 +508,12 @@ template <class T>
 void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, int batch,
                  int* info, bool inverse, LaunchList* defer, T* v = nullptr, long long sv = 0) {
   if (mp % NB) throw HipError{hipErrorInvalidValue, "potrf_inv_f64: size not a multiple of 64"};
+  // the step kernel moves blocks as 16-byte vectors
+  auto misaligned = [](const void* p, long long stride) {
+    return (reinterpret_cast<uintptr_t>(p) % 16) != 0 || (stride * (long long)sizeof(T)) % 16 != 0;
+  };
+  if (misaligned(z, sz) || misaligned(w, sw) || (v && misaligned(v, sv)))
+    throw HipError{hipErrorInvalidValue, "potrf_inv: factorization buffers not 16-byte aligned"};
   // every launch goes through issue (closures own copies of their arguments)
   auto issue = [defer](std::function<void()> f) {
     if (defer)
