@@ -17,6 +17,8 @@
 #include "gemm_tile.h"
 #include "ps_internal.h"
 
+#include <memory>
+
 namespace ps {
 
 namespace {
@@ -566,6 +568,31 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     ip.per = L < nbk_all ? L * ip.ncols : L - 1;   // (i, j) pairs, or the finishing stores
     return ip;
   };
+  // Recording (per-class kernel timing): a chain without launches of other kernels
+  // between its steps (no outer blocks) is one window from its first step to its last
+  // launch; otherwise every step is its own window.
+  struct ChainWin {
+    int slot = -1, launches = 0;
+    double flops = 0.0;
+  };
+  const auto win = std::make_shared<ChainWin>();
+  const bool one_window = outer == mp;
+  const int kcls = sizeof(T) == 4 ? kKcChol32 : (wide ? kKcCholWide : kKcCholNarrow);
+  const bool has_finish = fused_inv && inv_plan(nbk_all).per * batch > 0;
+  auto rec_begin = [win, one_window](hipStream_t st) {
+    if (!one_window) return krec_begin(st);
+    if (win->slot < 0) win->slot = krec_begin(st);
+    return win->slot;
+  };
+  auto rec_end = [win, one_window, kcls](hipStream_t st, int slot, double flops, bool last) {
+    if (!one_window) {
+      krec_end(st, slot, kcls, flops);
+      return;
+    }
+    win->launches += 1;
+    win->flops += flops;
+    if (last) krec_end(st, win->slot, kcls, win->flops, win->launches);
+  };
   auto step = [&](int k0, int fold, const GemmProblemT<T>* tp, int ntp) {
     const int rest = mp - k0 - NB;
     const int nt = rest > 0 ? rest / NB : 1;
@@ -599,8 +626,9 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     }
     const GemmProblemT<T> t0 = t[0], t1 = t[1];
     const int np = cnt[0], ntrail = cnt[0] + cnt[1], grid = ndiag + ntrail + ninv;
+    const bool last = k0 + NB >= mp && !has_finish;
     issue([=] {
-      const int slot = krec_begin(s);
+      const int slot = rec_begin(s);
       if (wide)
         hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(grid), dim3(NTD), 0, s, z, sz, w, sw,
                            mp, k0, rest, nt, fold, info, t0, t1, ndiag, np, ntrail, v, sv, ip);
@@ -611,8 +639,7 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
       PS_HIP(hipGetLastError());
       // algorithmic work of a launch: the factorization's batch mp^3 / 3 spread evenly over
       // its mp / 64 block steps
-      krec_end(s, slot, sizeof(T) == 4 ? kKcChol32 : (wide ? kKcCholWide : kKcCholNarrow),
-               (double)batch * mp * mp * (double)NB / 3.0);
+      rec_end(s, slot, (double)batch * mp * mp * (double)NB / 3.0, last);
     });
   };
   // Eight or more matrices of padded size 1024 to 4095 (no outer blocks): the trailing
@@ -678,11 +705,11 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     if (ninv > 0) {
       const GemmProblemT<T> none{};
       issue([=] {
-        const int slot = krec_begin(s);
+        const int slot = rec_begin(s);
         hipLaunchKernelGGL((chol_step_kernel<T, true>), dim3(ninv), dim3(NTD), 0, s, z, sz, w, sw,
                            mp, 0, 0, 1, 0, info, none, none, 0, 0, 0, v, sv, ip);
         PS_HIP(hipGetLastError());
-        krec_end(s, slot, sizeof(T) == 4 ? kKcChol32 : kKcCholWide, 0.0);
+        rec_end(s, slot, 0.0, true);
       });
     }
     return;

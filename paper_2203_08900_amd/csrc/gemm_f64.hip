@@ -170,11 +170,12 @@ int krec_begin(hipStream_t s) {
   return slot;
 }
 
-void krec_end(hipStream_t s, int slot, int cls, double flops) {
+void krec_end(hipStream_t s, int slot, int cls, double flops, int launches) {
   if (!g_rec || slot < 0) return;
   PS_HIP(hipEventRecord(g_rec->ev[2 * slot + 1], s));
   g_rec->cls[slot] = cls;
   g_rec->flops[slot] = flops;
+  if (g_rec->nl) g_rec->nl[slot] = launches;
 }
 
 // 2 x (number of structurally non-zero products) over the stored output entries.  For

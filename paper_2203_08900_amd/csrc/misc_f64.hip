@@ -470,6 +470,116 @@ __global__ void gk_update_kernel(const double* p, long long pstride, double* w,
   for (int i = threadIdx.x; i < m; i += blockDim.x) Wv[i] *= inv;
 }
 
+// One half-step of the bidiagonalization per launch, with the vectors kept unnormalized
+// (w~ = ||w~|| w): w~ = M x / ||x~|| - ||x~|| wprev~ / ||wprev~||, where x~ is the previous
+// half-step's vector and wprev~ the one before (the coefficient of the recurrence is the
+// norm of x~).  Each workgroup owns four entries of w~ (one column dot per wave) and
+// writes the sum of their squares to its slot of wpart; norms are the sums of such
+// partials, taken in a fixed order by every workgroup of the next launch, so there is
+// no cross-workgroup traffic within a launch and the result is deterministic.  Workgroup
+// 0 also stores ||x~|| at hist[hist_x] (hist_x < 0: none).  Partials: npart = gridDim.x
+// per batch item.
+__device__ inline double gk_norm2(const double* part, int npart, double* sh) {
+  double q = 0.0;
+  for (int i = threadIdx.x; i < npart; i += blockDim.x) q += part[i];
+  __shared__ double tot;
+  const double r = block_sum(q, sh);
+  if (threadIdx.x == 0) tot = r;
+  __syncthreads();
+  return tot;
+}
+
+__global__ void gk_step_kernel(const double* mat, long long mstride, const double* x,
+                               long long xstride, const double* xpart, double* w,
+                               long long wstride, const double* wprev, long long wpstride,
+                               const double* wppart, double* wpart, double* hist, int hist_x,
+                               int hist_ld, int mp) {
+  constexpr int U = 8;
+  __shared__ double sh[NT / 64];
+  __shared__ double wv[NT / 64];
+  const int b = blockIdx.y, npart = gridDim.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = blockIdx.x * (NT / 64) + wave;
+  double dot = 0.0;
+  if (col < mp) {
+    const double2* Mc = reinterpret_cast<const double2*>(mat + b * mstride + (size_t)col * mp);
+    const double2* X = reinterpret_cast<const double2*>(x + b * xstride);
+    const int n2 = mp / 2;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int base = 0; base < n2; base += 64 * U) {
+      double2 a[U], v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = base + lane + 64 * u;
+        a[u] = i < n2 ? Mc[i] : double2{0.0, 0.0};
+        v[u] = i < n2 ? X[i] : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc0 += a[u].x * v[u].x;
+        acc1 += a[u].y * v[u].y;
+      }
+    }
+    dot = warp_sum(acc0 + acc1);
+  }
+  const double nx = sqrt(gk_norm2(xpart + (size_t)b * npart, npart, sh));
+  const double nwp = wprev ? sqrt(gk_norm2(wppart + (size_t)b * npart, npart, sh)) : 1.0;
+  const double inx = nx > 0.0 ? 1.0 / nx : 0.0;
+  const double cw = (wprev && nwp > 0.0) ? nx / nwp : 0.0;
+  double val = 0.0;
+  if (col < mp && lane == 0) {
+    val = dot * inx;
+    if (wprev) val -= cw * wprev[b * wpstride + col];
+    w[b * wstride + col] = val;
+    wv[wave] = val * val;
+  } else if (lane == 0) {
+    wv[wave] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double q = 0.0;
+    for (int i = 0; i < NT / 64; ++i) q += wv[i];
+    wpart[(size_t)b * npart + blockIdx.x] = q;
+    if (blockIdx.x == 0 && hist_x >= 0) hist[(size_t)b * hist_ld + hist_x] = nx;
+  }
+}
+
+// partials of a unit vector's squared norm: 1 in slot 0 of every batch item
+__global__ void gk_seed_kernel(double* part, int npart) {
+  for (int i = threadIdx.x; i < npart; i += blockDim.x) part[(size_t)blockIdx.x * npart + i] = i == 0 ? 1.0 : 0.0;
+}
+// hist[hist_out] = the norm given by the partials (the last half-step's vector)
+__global__ void gk_finish_kernel(const double* part, int npart, double* hist, int hist_out,
+                                 int hist_ld) {
+  __shared__ double sh[NT / 64];
+  const double n2 = gk_norm2(part + (size_t)blockIdx.x * npart, npart, sh);
+  if (threadIdx.x == 0) hist[(size_t)blockIdx.x * hist_ld + hist_out] = sqrt(n2);
+}
+
+int gk_parts(int mp) { return (mp + NT / 64 - 1) / (NT / 64); }
+
+void gk_seed(hipStream_t s, double* part, int mp, int batch) {
+  hipLaunchKernelGGL(gk_seed_kernel, dim3(batch), dim3(NT), 0, s, part, gk_parts(mp));
+  PS_HIP(hipGetLastError());
+}
+
+void gk_step(hipStream_t s, const double* mat, long long mstride, const double* x,
+             long long xstride, const double* xpart, double* w, long long wstride,
+             const double* wprev, long long wpstride, const double* wppart, double* wpart,
+             double* hist, int hist_x, int hist_ld, int mp, int batch) {
+  hipLaunchKernelGGL(gk_step_kernel, dim3(gk_parts(mp), batch), dim3(NT), 0, s, mat, mstride, x,
+                     xstride, xpart, w, wstride, wprev, wpstride, wppart, wpart, hist, hist_x,
+                     hist_ld, mp);
+  PS_HIP(hipGetLastError());
+}
+
+void gk_finish(hipStream_t s, const double* part, int mp, double* hist, int hist_out, int hist_ld,
+               int batch) {
+  hipLaunchKernelGGL(gk_finish_kernel, dim3(batch), dim3(NT), 0, s, part, gk_parts(mp), hist,
+                     hist_out, hist_ld);
+  PS_HIP(hipGetLastError());
+}
+
 void gk_update(hipStream_t s, const double* p, long long pstride, double* w, long long wstride,
                const double* wprev, long long wpstride, double* hist, int hist_prev,
                int hist_out, int hist_ld, int m, int batch) {

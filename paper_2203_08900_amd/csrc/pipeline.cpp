@@ -44,6 +44,7 @@ struct ps_handle_s {
   std::vector<hipEvent_t> kev;  // per-launch kernel timing (opts.timing == 2)
   std::vector<double> kflops;
   std::vector<int> kcls;
+  std::vector<int> knl;
   // the caller's extra streams (ps_set_worker_streams): the first is also the second
   // stream of a mixed step (FP32 shift group); without any, that work is serialized on
   // `stream`
@@ -88,6 +89,7 @@ struct Buffers {
   double *mk, *wmk, *tmp, *y, *yt, *x0, *x1, *x2, *g, *z, *w, *nmat;
   double *t1, *t2, *s12, *s21, *as, *bs, *p11, *wc, *qbot, *top, *ab, *F, *hp;
   double *vv, *uu, *pp, *hist, *norms;
+  double* gkpart;    // partial norms of the bidiagonalization vectors (3 generations)
   double* splitws;   // kMaxSplit partial products of split-K GEMMs
   int* dinfo;
   // mixed precision (null in FP64 mode)
@@ -166,6 +168,7 @@ void carve(Arena& a, Buffers& b, int m, int r, int what, bool mixed = false) {
   b.uu = a.take<double>(2 * (size_t)b.mp);
   b.pp = a.take<double>(2 * (size_t)b.mp);
   b.hist = a.take<double>(2 * 256);
+  b.gkpart = a.take<double>(3 * 2 * (size_t)gk_parts(b.mp));
   b.norms = a.take<double>(2 + 2 * 1024 + 16);
   b.splitws = a.take<double>((size_t)kMaxSplit * S);
   b.dinfo = a.take<int>(16);
@@ -302,15 +305,20 @@ void gk_estimate(hipStream_t s, Buffers& b, const double* mats, const double* ma
   const int mp = b.mp;
   const long long S = (long long)b.S;
   gk_init(s, b.vv, b.m, mp, 2, 0);
+  // half-step h writes the partial norms of its vector to generation h % 3; the unit
+  // start vector's are generation 2
+  const size_t np2 = 2 * (size_t)gk_parts(mp);
+  auto part = [&](int h) { return b.gkpart + (size_t)((h + 3) % 3) * np2; };
+  gk_seed(s, part(-1), mp, 2);
   for (int k = 0; k < steps; ++k) {
-    // u_k = M v_k - beta_{k-1} u_{k-1}   (M x = column dots of M^T)
-    coldots(s, mats_t, S, b.vv, mp, b.pp, mp, mp, 2);
-    gk_update(s, b.pp, mp, b.uu, mp, k > 0 ? b.uu : nullptr, mp, b.hist, 2 * k - 1, 2 * k, 256,
-              mp, 2);
-    // v_{k+1} = M^T u_k - alpha_k v_k
-    coldots(s, mats, S, b.uu, mp, b.pp, mp, mp, 2);
-    gk_update(s, b.pp, mp, b.vv, mp, b.vv, mp, b.hist, 2 * k, 2 * k + 1, 256, mp, 2);
+    // u_k = M v_k - beta_{k-1} u_{k-1}   (M x = column dots of M^T; beta_{k-1} = ||v~_k||)
+    gk_step(s, mats_t, S, b.vv, mp, part(2 * k - 1), b.uu, mp, k > 0 ? b.uu : nullptr, mp,
+            part(2 * k - 2), part(2 * k), b.hist, 2 * k - 1, 256, mp, 2);
+    // v_{k+1} = M^T u_k - alpha_k v_k   (alpha_k = ||u~_k||)
+    gk_step(s, mats, S, b.uu, mp, part(2 * k), b.vv, mp, b.vv, mp, part(2 * k - 1),
+            part(2 * k + 1), b.hist, 2 * k, 256, mp, 2);
   }
+  gk_finish(s, part(2 * steps - 1), mp, b.hist, 2 * steps - 1, 256, 2);
   PS_HIP(hipMemcpyAsync(pinned, b.hist, 2 * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
   for (int q = 0; q < 2; ++q) {
@@ -801,9 +809,11 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     }
     h->kflops.assign(cap, 0.0);
     h->kcls.assign(cap, -1);
+    h->knl.assign(cap, 1);
     grec.ev = h->kev.data();
     grec.flops = h->kflops.data();
     grec.cls = h->kcls.data();
+    grec.nl = h->knl.data();
     grec.cap = cap;
     kernel_set_recorder(&grec);
   }
@@ -1023,7 +1033,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     if (c < 0 || c >= kKcCount) continue;
     float t = 0.f;
     PS_HIP(hipEventElapsedTime(&t, grec.ev[2 * q], grec.ev[2 * q + 1]));
-    inf.kclass_launches[c] += 1;
+    inf.kclass_launches[c] += h->knl.empty() ? 1 : h->knl[q];
     inf.kclass_ms[c] += t;
     inf.kclass_flops[c] += grec.flops[q];
   }
@@ -1715,6 +1725,7 @@ struct ClassBufs {
   double *mk, *wmk, *y, *yt, *x0, *x1, *x2, *g, *z, *w, *nmat, *t1, *t2, *s12, *p11, *wc, *top,
       *qbot, *hp, *vv, *uu, *pp, *hist, *norms, *scal;
   int *dinfo, *mdev;
+  double* gkpart;    // partial norms of the bidiagonalization vectors (3 generations)
 };
 
 constexpr int kClassScal = 64;   // per-problem scalar slots (see run_class)
@@ -1748,6 +1759,7 @@ void carve_class(Arena& a, ClassBufs& c, int nb, int mp, int r) {
   c.uu = a.take<double>(2 * n * mp);
   c.pp = a.take<double>(2 * n * mp);
   c.hist = a.take<double>(2 * n * 256);
+  c.gkpart = a.take<double>(3 * 2 * (size_t)n * gk_parts(mp));
   c.norms = a.take<double>(2 * n);
   c.scal = a.take<double>(n * kClassScal);
   c.dinfo = a.take<int>(16);
@@ -1871,13 +1883,16 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
   const int steps = std::max(4, std::min(o.lanczos_steps, 120));
   transpose(s, c.y, c.yt, mp, S, 2 * nb);
   gk_init_b(s, c.vv, c.mdev, mp, 2 * nb, 2);
+  const size_t np2 = 2 * (size_t)nb * gk_parts(mp);
+  auto part = [&](int h) { return c.gkpart + (size_t)((h + 3) % 3) * np2; };
+  gk_seed(s, part(-1), mp, 2 * nb);
   for (int k = 0; k < steps; ++k) {
-    coldots(s, c.yt, S, c.vv, mp, c.pp, mp, mp, 2 * nb);
-    gk_update(s, c.pp, mp, c.uu, mp, k > 0 ? c.uu : nullptr, mp, c.hist, 2 * k - 1, 2 * k, 256,
-              mp, 2 * nb);
-    coldots(s, c.y, S, c.uu, mp, c.pp, mp, mp, 2 * nb);
-    gk_update(s, c.pp, mp, c.vv, mp, c.vv, mp, c.hist, 2 * k, 2 * k + 1, 256, mp, 2 * nb);
+    gk_step(s, c.yt, S, c.vv, mp, part(2 * k - 1), c.uu, mp, k > 0 ? c.uu : nullptr, mp,
+            part(2 * k - 2), part(2 * k), c.hist, 2 * k - 1, 256, mp, 2 * nb);
+    gk_step(s, c.y, S, c.uu, mp, part(2 * k), c.vv, mp, c.vv, mp, part(2 * k - 1),
+            part(2 * k + 1), c.hist, 2 * k, 256, mp, 2 * nb);
   }
+  gk_finish(s, part(2 * steps - 1), mp, c.hist, 2 * steps - 1, 256, 2 * nb);
   const size_t hist_n = (size_t)2 * nb * 256;
   if (hist_n + 16 > (size_t)kPinned) return fail_all();
   PS_HIP(hipMemcpyAsync(pin, c.hist, hist_n * sizeof(double), hipMemcpyDeviceToHost, s));

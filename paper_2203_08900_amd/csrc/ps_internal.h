@@ -109,16 +109,19 @@ enum KernelClass : int {
 };
 struct KernelRecorder {
   hipEvent_t* ev = nullptr;   // pairs (start, stop)
-  double* flops = nullptr;    // per recorded launch
-  int* cls = nullptr;         // class per recorded launch
+  double* flops = nullptr;    // per recorded window
+  int* cls = nullptr;         // class per recorded window
+  int* nl = nullptr;          // launches per recorded window
   int cap = 0;                // number of pairs available
   int n = 0;                  // pairs used
 };
 void kernel_set_recorder(KernelRecorder* r);
 KernelRecorder* kernel_recorder();
-// start / stop of one recorded launch on stream s (no-ops without a recorder or room)
+// start / stop of one recorded window on stream s (no-ops without a recorder or room):
+// one launch, or a run of back-to-back launches of one class (a Cholesky chain), so that
+// no event separates them
 int krec_begin(hipStream_t s);
-void krec_end(hipStream_t s, int slot, int cls, double flops);
+void krec_end(hipStream_t s, int slot, int cls, double flops, int launches = 1);
 template <class T>
 double gemm_algorithmic_flops(const GemmProblemT<T>& p);
 
@@ -263,6 +266,18 @@ void basis_mix_b(hipStream_t s, const double* c, const double* qbot, double* top
 void mask_pad_b(hipStream_t s, double* x, const int* m_dev, int mp, int per, int count);
 void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
              long long xstride, double* y, long long ystride, int mp, int batch);
+// Bidiagonalization half-steps with unnormalized vectors and per-workgroup partial
+// sums of squares (gk_parts(mp) per batch item): gk_seed writes the partials of a unit
+// vector, gk_step forms w~ = M x / ||x~|| - ||x~|| wprev~ / ||wprev~|| (wprev null: none)
+// and stores ||x~|| at hist[hist_x], gk_finish stores the norm of the last vector.
+int gk_parts(int mp);
+void gk_seed(hipStream_t s, double* part, int mp, int batch);
+void gk_step(hipStream_t s, const double* mat, long long mstride, const double* x,
+             long long xstride, const double* xpart, double* w, long long wstride,
+             const double* wprev, long long wpstride, const double* wppart, double* wpart,
+             double* hist, int hist_x, int hist_ld, int mp, int batch);
+void gk_finish(hipStream_t s, const double* part, int mp, double* hist, int hist_out, int hist_ld,
+               int batch);
 void gk_update(hipStream_t s, const double* p, long long pstride, double* w,
                long long wstride, const double* wprev, long long wpstride,
                double* hist, int hist_prev, int hist_out, int hist_ld, int m, int batch);
