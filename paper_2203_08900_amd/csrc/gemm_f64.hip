@@ -20,7 +20,7 @@ struct GemmGroup {
 // with different transposes (each workgroup branches once, uniformly).
 template <class T, int BM, int BN, int WM, int WN, bool kUseC>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g) {
-  __shared__ T smem[2 * GemmLds<BM, BN>::ASZ + 2 * GemmLds<BM, BN>::BSZ];
+  __shared__ __attribute__((aligned(16))) T smem[2 * GemmLds<BM, BN>::ASZ + 2 * GemmLds<BM, BN>::BSZ];
   int bid = blockIdx.x;
   if (g.remap) {
     // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
@@ -252,6 +252,14 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
       throw HipError{hipErrorInvalidValue, "gemm_f64: bad split-K setup"};
     if (p.ksplit > 1 && (p.alpha_b || p.beta_b))
       throw HipError{hipErrorInvalidValue, "gemm_f64: per-entry scalars with split-K"};
+    // the tiles move every operand as 16-byte vectors
+    constexpr long long vw = 16 / sizeof(T);
+    auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) % 16) == 0; };
+    bool ok = al(p.A) && al(p.B) && al(p.D) && (!p.C || al(p.C)) && (!p.ws || al(p.ws)) &&
+              p.lda % vw == 0 && p.ldb % vw == 0 && p.ldc % vw == 0 && p.ldd % vw == 0;
+    for (int d = 0; d < 2; ++d)
+      ok = ok && p.sA[d] % vw == 0 && p.sB[d] % vw == 0 && p.sC[d] % vw == 0 && p.sD[d] % vw == 0;
+    if (!ok) throw HipError{hipErrorInvalidValue, "gemm: operands not 16-byte aligned"};
     if (p.M % 128 || p.N % 128 || std::min(p.M, p.N) < 512) big = false;
     const long long tm = p.M / 128, tn = p.N / 128;
     tiles128 += ((p.flags & (kOutUpper | kOutLower)) ? tm * (tm + 1) / 2 : tm * tn) *

@@ -8,13 +8,17 @@
 // tiles fill the chip, and 64 x 64 with 4 waves of 32 x 32 for the others.  A group of up to four
 // independent problems (any operand transposes) shares one launch, so that problems
 // whose tile counts alone would leave compute units idle fill the machine together.
-// K advances in steps of 16 through two LDS buffers (one barrier per step); the global
-// loads run two steps ahead of the MFMAs, through two register slots.
+// K advances in steps of 32 through two LDS buffers (one barrier per step); the global
+// loads run two steps ahead of the MFMAs, through two register slots.  Every global
+// access is a 16-byte vector along the operand's contiguous dimension (all operands,
+// leading dimensions and batch strides are 16-byte aligned; the launcher checks), and
+// the epilogue goes through LDS so that C, D, the mirrored stores and split-K partial
+// tiles move as coalesced vectors too.
 //
 // LDS layouts per operand keep global loads coalesced along the contiguous
 // dimension and fragment reads on distinct banks:
-//   op(A) = A   : [k][i], stride BM+16       op(A) = A^T : [i][k], stride 16+1
-//   op(B) = B   : [j][k], stride 16+1        op(B) = B^T : [k][j], stride BN+16
+//   op(A) = A   : [k][i], stride BM+16       op(A) = A^T : [i][k], stride 32+1
+//   op(B) = B   : [j][k], stride 32+1        op(B) = B^T : [k][j], stride BN+16
 // Structure flags restrict each tile's K loop to the non-zero band of triangular
 // operands and restrict / mirror the stored output of symmetric results.  Split-K
 // writes per-split partial tiles that a second kernel sums in a fixed order.
@@ -55,7 +59,7 @@ struct Mfma<float> {
 
 namespace {
 
-constexpr int BK = 16;
+constexpr int BK = 32;
 constexpr int LDIK = BK + 1;
 
 __device__ inline void tri_index(int t, int& hi, int& lo) {
@@ -88,8 +92,11 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
   constexpr int LDKM = GemmLds<BM, BN>::LDKM;
   constexpr int LDKN = GemmLds<BM, BN>::LDKN;
-  constexpr int APT = BM * BK / NT;
-  constexpr int BPT = BN * BK / NT;
+  constexpr int VW = 16 / sizeof(T);            // elements per 16-byte access
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  constexpr int AV = BM * BK / (VW * NT);       // operand vectors per thread and K step
+  constexpr int BV = BN * BK / (VW * NT);
+  static_assert(AV * VW * NT == BM * BK && BV * VW * NT == BN * BK, "tile / thread mismatch");
   const int local = bid - P.tile_begin;
   // Triangular operands make the K extent differ from tile to tile.  Such problems (with
   // a full output) are launched without the XCD remap (dispatch is round-robin over the
@@ -187,60 +194,67 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
 
   // Two register slots for the global loads of the next two K steps: the loads of step
   // kt + 2 are issued before the matrix-core work of step kt and land in LDS only after
-  // that of step kt + 1, so two steps of compute cover their latency (a single step of
-  // a 64 x 64 tile is shorter than a trip to memory).
-  T ra0[APT], rb0[BPT], ra1[APT], rb1[BPT];
+  // that of step kt + 1, so two steps of compute cover their latency.  Vector p of a
+  // thread: op(A) = A takes VW consecutive rows i of one column k, op(A) = A^T VW
+  // consecutive k of one row i (likewise for B).
+  vec_t ra0[AV], rb0[BV], ra1[AV], rb1[BV];
   double rsc0 = 1.0, rsc1 = 1.0;   // segment scale of the A values in each slot
 
-  auto load = [&](int kt, T* ra, T* rb, double& rsc) {
+  auto load = [&](int kt, vec_t* ra, vec_t* rb, double& rsc) {
     const int s = kt / per;
     const int k0 = s * segK + kb + (kt - s * per) * BK;
     rsc = P.kseg > 0 ? (P.kscale_b ? P.kscale_b[z * P.nseg + s] : P.kscale[s]) : 1.0;
 #pragma unroll
-    for (int p = 0; p < APT; ++p) {
+    for (int p = 0; p < AV; ++p) {
       const int idx = tid + p * NT;
       if (!tA) {
-        const int i = idx % BM, k = idx / BM;
-        ra[p] = A[(i0 + i) + (long long)(k0 + k) * lda];
+        const int iv = idx % (BM / VW), k = idx / (BM / VW);
+        ra[p] = *reinterpret_cast<const vec_t*>(A + (i0 + VW * iv) + (long long)(k0 + k) * lda);
       } else {
-        const int k = idx % BK, i = idx / BK;
-        ra[p] = A[(k0 + k) + (long long)(i0 + i) * lda];
+        const int kv = idx % (BK / VW), i = idx / (BK / VW);
+        ra[p] = *reinterpret_cast<const vec_t*>(A + (k0 + VW * kv) + (long long)(i0 + i) * lda);
       }
     }
 #pragma unroll
-    for (int p = 0; p < BPT; ++p) {
+    for (int p = 0; p < BV; ++p) {
       const int idx = tid + p * NT;
       if (!tB) {
-        const int k = idx % BK, j = idx / BK;
-        rb[p] = B[(k0 + k) + (long long)(j0 + j) * ldb];
+        const int kv = idx % (BK / VW), j = idx / (BK / VW);
+        rb[p] = *reinterpret_cast<const vec_t*>(B + (k0 + VW * kv) + (long long)(j0 + j) * ldb);
       } else {
-        const int j = idx % BN, k = idx / BN;
-        rb[p] = B[(j0 + j) + (long long)(k0 + k) * ldb];
+        const int jv = idx % (BN / VW), k = idx / (BN / VW);
+        rb[p] = *reinterpret_cast<const vec_t*>(B + (j0 + VW * jv) + (long long)(k0 + k) * ldb);
       }
     }
   };
-  auto store = [&](int buf, const T* ra, const T* rb, double rsc) {
+  auto store = [&](int buf, const vec_t* ra, const vec_t* rb, double rsc) {
 #pragma unroll
-    for (int p = 0; p < APT; ++p) {
+    for (int p = 0; p < AV; ++p) {
       const int idx = tid + p * NT;
-      const T v = P.kseg > 0 ? (T)((double)ra[p] * rsc) : ra[p];
+      vec_t v = ra[p];
+      if (P.kseg > 0) {
+#pragma unroll
+        for (int u = 0; u < VW; ++u) v[u] = (T)((double)v[u] * rsc);
+      }
       if (!tA) {
-        const int i = idx % BM, k = idx / BM;
-        As[buf][k * LDKM + i] = v;
+        const int iv = idx % (BM / VW), k = idx / (BM / VW);
+        *reinterpret_cast<vec_t*>(&As[buf][k * LDKM + VW * iv]) = v;
       } else {
-        const int k = idx % BK, i = idx / BK;
-        As[buf][i * LDIK + k] = v;
+        const int kv = idx % (BK / VW), i = idx / (BK / VW);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) As[buf][i * LDIK + VW * kv + u] = v[u];
       }
     }
 #pragma unroll
-    for (int p = 0; p < BPT; ++p) {
+    for (int p = 0; p < BV; ++p) {
       const int idx = tid + p * NT;
       if (!tB) {
-        const int k = idx % BK, j = idx / BK;
-        Bs[buf][j * LDIK + k] = rb[p];
+        const int kv = idx % (BK / VW), j = idx / (BK / VW);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) Bs[buf][j * LDIK + VW * kv + u] = rb[p][u];
       } else {
-        const int j = idx % BN, k = idx / BN;
-        Bs[buf][k * LDKN + j] = rb[p];
+        const int jv = idx % (BN / VW), k = idx / (BN / VW);
+        *reinterpret_cast<vec_t*>(&Bs[buf][k * LDKN + VW * jv]) = rb[p];
       }
     }
   };
@@ -266,23 +280,24 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
     }
   };
 
-  // 64 x 64 tiles (short-K trailing updates of the factorizations among them) load their
-  // C values before the K loop, so that trip to memory overlaps the loop instead of
-  // following it; the large tiles keep their registers for occupancy and prefetch C
-  // row by row in the epilogue.
+  // The output tile moves through LDS as [j][i] (row length LDD) and between LDS and
+  // memory as coalesced vectors: vector q of a thread holds rows [VW (e % (BM/VW)), + VW)
+  // of column e / (BM/VW), e = tid + q NT.  64 x 64 tiles load their C values before
+  // the K loop, so that trip to memory overlaps the loop instead of following it; the
+  // large tiles keep their registers for occupancy and read C in the epilogue.
+  constexpr int LDD = BM + VW;
+  constexpr int OV = BM * BN / (VW * NT);
+  static_assert(BN * LDD <= 2 * (GemmLds<BM, BN>::ASZ + GemmLds<BM, BN>::BSZ), "output tile LDS");
   constexpr bool kEarlyC = (BM == 64) && kUseC;
-  T cpre[kEarlyC ? FM : 1][FN][4];
-  if (kEarlyC && (P.beta_b ? P.beta_b[z] : P.beta) != 0.0) {
+  const long long ldc = P.ldc, ldd = P.ldd;
+  const double beta_z = kUseC ? (P.beta_b ? P.beta_b[z] : P.beta) : 0.0;
+  vec_t cpre[kEarlyC ? OV : 1];
+  if (kEarlyC && beta_z != 0.0 && P.ksplit <= 1) {
 #pragma unroll
-    for (int a = 0; a < (kEarlyC ? FM : 1); ++a)
-#pragma unroll
-      for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
-          const int j = j0 + wn * FN * 16 + b * 16 + li;
-          cpre[a][b][v] = C[i + j * (long long)P.ldc];
-        }
+    for (int q = 0; q < (kEarlyC ? OV : 1); ++q) {
+      const int e = tid + q * NT, iv = e % (BM / VW), j = e / (BM / VW);
+      cpre[q] = *reinterpret_cast<const vec_t*>(C + (i0 + VW * iv) + (long long)(j0 + j) * ldc);
+    }
   }
 
   // Steps alternate between (LDS buffer 0, slot 0 refilled) and (buffer 1, slot 1): the
@@ -308,61 +323,92 @@ __device__ __forceinline__ void gemm_tile(const GemmProblemT<T>& P, int bid, T* 
   }
 
   const double alpha = P.alpha_b ? P.alpha_b[z] : P.alpha;
-  const double beta = kUseC ? (P.beta_b ? P.beta_b[z] : P.beta) : 0.0;
+  const double beta = beta_z;
+  // the tile to LDS (the operand buffers are free: the K loop ended on a barrier)
+  T* Ds = smem;
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ds[(wn * FN * 16 + b * 16 + li) * LDD + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v)] =
+            acc[a][b][v];
+  __syncthreads();
   if (P.ksplit > 1) {
     // partial tile of split ks (batch extent is 1 for split problems)
     T* W = P.ws + (long long)ks * P.M * P.N;
-    const long long M = P.M;
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+    for (int q = 0; q < OV; ++q) {
+      const int e = tid + q * NT, iv = e % (BM / VW), j = e / (BM / VW);
+      vec_t x;
 #pragma unroll
-      for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
-          const int j = j0 + wn * FN * 16 + b * 16 + li;
-          W[i + j * M] = (T)(alpha * acc[a][b][v]);
-        }
+      for (int u = 0; u < VW; ++u) x[u] = (T)(alpha * (double)Ds[j * LDD + VW * iv + u]);
+      *reinterpret_cast<vec_t*>(W + (i0 + VW * iv) + (long long)(j0 + j) * P.M) = x;
+    }
     return;
   }
-  const long long ldc = P.ldc, ldd = P.ldd;
-  // C may be D itself (in-place updates), so the compiler cannot move a C load above an
-  // earlier D store: loaded one by one, every element would wait a full memory latency.
-  // The C values of fragment row a + 1 are therefore loaded before the stores of row a
-  // (they are other elements, so the order is safe whether or not C aliases D).
-  T cur[FN][4], nxt[FN][4];
-  auto load_c = [&](int a, T (*dst)[4]) {
+  const bool up = flags & kOutUpper, lo = flags & kOutLower, mir = flags & kMirror;
+  // C may be D itself (in-place updates): every element is read and written by one
+  // thread, in that order
 #pragma unroll
-    for (int b = 0; b < FN; ++b)
+  for (int q = 0; q < OV; ++q) {
+    const int e = tid + q * NT, iv = e % (BM / VW), j = e / (BM / VW);
+    const int i = i0 + VW * iv, jj = j0 + j;
+    vec_t cv;
+    if (beta != 0.0) {
+      if constexpr (kEarlyC)
+        cv = cpre[q];
+      else
+        cv = *reinterpret_cast<const vec_t*>(C + i + (long long)jj * ldc);
+    }
+    vec_t out;
+    bool all = true;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
-        const int j = j0 + wn * FN * 16 + b * 16 + li;
-        dst[b][v] = C[i + j * ldc];
+    for (int u = 0; u < VW; ++u) {
+      double val = alpha * (double)Ds[j * LDD + VW * iv + u];
+      if (beta != 0.0) val += beta * (double)cv[u];
+      out[u] = (T)val;
+      all = all && !((up && i + u > jj) || (lo && i + u < jj));
+    }
+    if (mir) {
+#pragma unroll
+      for (int u = 0; u < VW; ++u) Ds[j * LDD + VW * iv + u] = out[u];
+    }
+    if (all) {
+      *reinterpret_cast<vec_t*>(D + i + (long long)jj * ldd) = out;
+    } else {
+#pragma unroll
+      for (int u = 0; u < VW; ++u)
+        if (!((up && i + u > jj) || (lo && i + u < jj))) D[i + u + (long long)jj * ldd] = out[u];
+    }
+  }
+  if (!mir) return;
+  // D(j, i) = D(i, j) for the stored entries off the diagonal, as vectors along j
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < OV; ++q) {
+    const int e = tid + q * NT, jv = e % (BN / VW), il = e / (BN / VW);
+    const int ii = i0 + il, jb = j0 + VW * jv;
+    vec_t out;
+    bool any = false, all = true;
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      const int jj = jb + u;
+      const bool st = up ? ii < jj : (lo ? ii > jj : ii != jj);
+      out[u] = Ds[(VW * jv + u) * LDD + il];
+      any = any || st;
+      all = all && st;
+    }
+    if (all) {
+      *reinterpret_cast<vec_t*>(D + jb + (long long)ii * ldd) = out;
+    } else if (any) {
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        const int jj = jb + u;
+        if (up ? ii < jj : (lo ? ii > jj : ii != jj)) D[jj + (long long)ii * ldd] = out[u];
       }
-  };
-  if (!kEarlyC && beta != 0.0) load_c(0, cur);
-#pragma unroll
-  for (int a = 0; a < FM; ++a) {
-    if (!kEarlyC && beta != 0.0 && a + 1 < FM) load_c(a + 1, nxt);
-#pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wm * FM * 16 + a * 16 + Mfma<T>::row(lk, v);
-        const int j = j0 + wn * FN * 16 + b * 16 + li;
-        if ((flags & kOutUpper) && i > j) continue;
-        if ((flags & kOutLower) && i < j) continue;
-        double val = alpha * acc[a][b][v];
-        if (beta != 0.0)
-          val += beta * (double)(kEarlyC ? cpre[kEarlyC ? a : 0][b][v] : cur[b][v]);
-        D[i + j * ldd] = (T)val;
-        if ((flags & kMirror) && i != j) D[j + i * ldd] = (T)val;
-      }
-#pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) cur[b][v] = nxt[b][v];
+    }
   }
 }
 
