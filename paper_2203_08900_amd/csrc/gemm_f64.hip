@@ -42,6 +42,97 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g)
     gemm_tile<T, BM, BN, WM, WN, 1, 1, kUseC>(P, bid, smem);
 }
 
+// Stream-K schedule for single problems whose tiles cannot share the machine evenly
+// (symmetric outputs, triangular operands, fewer tiles than compute units): the K steps
+// of all tiles, in tile order, are cut into gridDim.x equal ranges, one per workgroup.
+// A workgroup finishes the tiles its range covers whole; of a tile it covers in part it
+// writes alpha times the partial product to its slot (2w for the first tile of its
+// range, 2w + 1 for the last).  The reduction then sums, per tile, the slots of the
+// workgroups that covered it, in workgroup order (deterministic), and applies the
+// epilogue; no workgroup waits for another.
+template <class T, int BM, int BN, int WM, int WN, int TA, int TB, bool kUseC>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_streamk_kernel(GemmProblemT<T> P, long long U,
+                                                                    T* slots) {
+  __shared__ __attribute__((aligned(16))) T smem[2 * GemmLds<BM, BN>::ASZ + 2 * GemmLds<BM, BN>::BSZ];
+  const int w = blockIdx.x, nw = gridDim.x;
+  const long long u0 = U * w / nw, u1 = U * (w + 1) / nw;
+  const int nseg = P.kseg > 0 ? P.nseg : 1;
+  long long c = 0;
+  for (int t = 0; t < P.tiles && c < u1; ++t) {
+    int I, J, kb;
+    tile_coords<BM, BN>(P, t, I, J);
+    const long long n = (long long)tile_band<BM, BN>(P, I, J, kb) * nseg;
+    if (n > 0 && c + n > u0) {
+      const int a = (int)((u0 > c ? u0 : c) - c), b = (int)((u1 < c + n ? u1 : c + n) - c);
+      T* part = (a == 0 && b == n) ? nullptr
+                                   : slots + (long long)(u0 >= c ? 2 * w : 2 * w + 1) * BM * BN;
+      gemm_tile_run<T, BM, BN, WM, WN, TA, TB, kUseC>(P, 0, I, J, a, b, 0, part, smem);
+    }
+    c += n;
+  }
+}
+
+// One tile per workgroup: tiles that one workgroup finished are skipped; the others are
+// the sum of their partial tiles (none for a tile with no K steps) plus beta C.
+template <class T, int BM, int BN, int NT>
+__global__ __launch_bounds__(NT) void gemm_streamk_reduce_kernel(GemmProblemT<T> P, long long U,
+                                                                 const T* slots, int nwg) {
+  constexpr int VW = VecT<T>::VW;
+  using vec_t = typename VecT<T>::type;
+  constexpr int LDD = BM + VW;
+  constexpr int OV = BM * BN / (VW * NT);
+  __shared__ __attribute__((aligned(16))) T Ds[BN * LDD];
+  const int t = blockIdx.x;
+  const int nseg = P.kseg > 0 ? P.nseg : 1;
+  // K steps before this tile, counted by the threads together
+  long long part_c = 0;
+  for (int tt = threadIdx.x; tt < t; tt += blockDim.x) {
+    int I, J, kb;
+    tile_coords<BM, BN>(P, tt, I, J);
+    part_c += (long long)tile_band<BM, BN>(P, I, J, kb) * nseg;
+  }
+  __shared__ long long red[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) part_c += __shfl_down(part_c, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part_c;
+  __syncthreads();
+  long long c = 0;
+  for (int i = 0; i < NT / 64; ++i) c += red[i];
+  int I, J, kb;
+  tile_coords<BM, BN>(P, t, I, J);
+  const long long n = (long long)tile_band<BM, BN>(P, I, J, kb) * nseg;
+  auto owner = [&](long long x) {
+    long long w = x * nwg / U;
+    while (w + 1 < nwg && U * (w + 1) / nwg <= x) ++w;
+    while (w > 0 && U * w / nwg > x) --w;
+    return (int)w;
+  };
+  int wf = 0, wl = -1;
+  if (n > 0) {
+    wf = owner(c);
+    wl = owner(c + n - 1);
+    if (wf == wl) return;   // finished by one workgroup
+  }
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int qv = 0; qv < OV; ++qv) {
+    const int e = tid + qv * NT, iv = e % (BM / VW), j = e / (BM / VW);
+    double sum[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) sum[u] = 0.0;
+    for (int w = wf; w <= wl; ++w) {
+      const int slot = (U * w / nwg >= c) ? 2 * w : 2 * w + 1;
+      const vec_t x = *reinterpret_cast<const vec_t*>(slots + (long long)slot * BM * BN + VW * iv + (long long)j * BM);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) sum[u] += (double)x[u];
+    }
+#pragma unroll
+    for (int u = 0; u < VW; ++u) Ds[j * LDD + VW * iv + u] = (T)sum[u];
+  }
+  __syncthreads();
+  const vec_t none[1] = {};
+  tile_epilogue<T, BM, BN, NT>(P, 0, I, J, Ds, 1.0, P.beta, false, none);
+}
+
 // D = sum_s partial_s + beta C with the triangle / mirror conventions of the GEMM
 template <class T>
 __global__ void gemm_split_reduce_kernel(GemmProblemT<T> P) {
@@ -156,6 +247,89 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
     const int cls = std::is_same<T, float>::value ? kKcGemm32 : (BM == 128 ? kKcGemm128 : kKcGemm64);
     krec_end(s, slot, cls, f);
   }
+}
+
+// Large tiles on a stream-K schedule (see gemm_streamk_kernel), one launch pair per
+// problem, for groups of single problems with a symmetric output (too few tiles for the
+// machine) and a long K, when a problem's workspace can hold the partial tiles: each
+// workgroup then gets a long K range, and the schedule replaces a uniform split-K whose
+// partial tiles cost more traffic.  With short ranges (a few dozen K steps per
+// workgroup) the staggered K positions of the workgroups share the caches worse than
+// the full tiles in lockstep do, and triangular operands (K differing per tile) measure
+// faster on the small tiles, so those stay on the regular schedule.  Returns false
+// (nothing launched) when the schedule does not apply.
+template <class T, int TA, int TB>
+void streamk_one(hipStream_t s, const GemmProblemT<T>& p, long long units, T* slots, int nwg) {
+  constexpr int BM = 128, BN = 128;
+  if (p.beta != 0.0)
+    hipLaunchKernelGGL((gemm_streamk_kernel<T, BM, BN, 4, 4, TA, TB, true>), dim3(nwg), dim3(1024), 0,
+                       s, p, units, slots);
+  else
+    hipLaunchKernelGGL((gemm_streamk_kernel<T, BM, BN, 4, 4, TA, TB, false>), dim3(nwg), dim3(1024),
+                       0, s, p, units, slots);
+  PS_HIP(hipGetLastError());
+  hipLaunchKernelGGL((gemm_streamk_reduce_kernel<T, BM, BN, 1024>), dim3(p.tiles), dim3(1024), 0, s,
+                     p, units, slots, nwg);
+  PS_HIP(hipGetLastError());
+}
+
+template <class T>
+bool launch_streamk(hipStream_t s, const GemmProblemT<T>* probs, int count) {
+  constexpr int BM = 128, BN = 128, NWG = 256;   // one 16-wave workgroup per compute unit
+  GemmProblemT<T> ps[kMaxGroup];
+  long long units[kMaxGroup];
+  int n = 0, total = 0;
+  bool skew = false;
+  T* ws = nullptr;
+  long long ws_elems = 0;
+  for (int q = 0; q < count; ++q) {
+    GemmProblemT<T> p = probs[q];
+    if (p.M <= 0 || p.N <= 0) continue;
+    if (p.nb1 * p.nb2 != 1 || p.alpha_b || p.beta_b) return false;
+    if (!ws && p.ws && p.ws_slots > 0) {
+      ws = p.ws;
+      ws_elems = (long long)p.ws_slots * p.M * p.N;
+    }
+    if (p.flags & (kAUpper | kALower | kBUpper | kBLower)) return false;
+    if (p.flags & (kOutUpper | kOutLower)) skew = true;
+    p.ksplit = 1;
+    p.tm = p.M / BM;
+    p.tn = p.N / BN;
+    p.tiles = (p.flags & (kOutUpper | kOutLower)) ? p.tm * (p.tm + 1) / 2 : p.tm * p.tn;
+    p.tiles_per_batch = p.tiles;
+    p.tile_begin = 0;
+    total += p.tiles;
+    const int nseg = p.kseg > 0 ? p.nseg : 1;
+    long long u = 0;
+    for (int t = 0; t < p.tiles; ++t) {
+      int I, J, kb;
+      tile_coords<BM, BN>(p, t, I, J);
+      u += (long long)tile_band<BM, BN>(p, I, J, kb) * nseg;
+    }
+    if (u < 128LL * NWG) return false;   // K steps per workgroup
+    units[n] = u;
+    ps[n++] = p;
+  }
+  if (n == 0 || !(skew || total < NWG)) return false;
+  if (!ws || ws_elems < 2LL * NWG * BM * BN) return false;
+  const int slot = krec_begin(s);
+  for (int q = 0; q < n; ++q) {
+    const int v = ps[q].tA * 2 + ps[q].tB;
+    if (v == 0)
+      streamk_one<T, 0, 0>(s, ps[q], units[q], ws, NWG);
+    else if (v == 1)
+      streamk_one<T, 0, 1>(s, ps[q], units[q], ws, NWG);
+    else if (v == 2)
+      streamk_one<T, 1, 0>(s, ps[q], units[q], ws, NWG);
+    else
+      streamk_one<T, 1, 1>(s, ps[q], units[q], ws, NWG);
+  }
+  if (slot >= 0) {
+    double f = 0.0;
+    for (int q = 0; q < n; ++q) f += gemm_algorithmic_flops(ps[q]);
+    krec_end(s, slot, std::is_same<T, float>::value ? kKcGemm32 : kKcGemm128, f);
+  }
+  return true;
 }
 
 }  // namespace
@@ -278,6 +452,7 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
     skew = std::max(skew, na + nb);
   }
   const long long skew_max = skew == 2 ? 2048 : (skew == 1 ? 512 : 0);
+  if (big && launch_streamk<T>(s, probs, count)) return;
   if (big && tiles128 >= 256 && tiles128 >= skew_max)
     launch_group<T, 128, 128, 4, 4>(s, probs, count);
   else

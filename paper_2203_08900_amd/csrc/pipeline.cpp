@@ -103,6 +103,9 @@ constexpr int kMaxSplit = 8;
 // ones), so the factor that fills the last round best wins, less 2 % per extra split
 // for the partial sums' traffic and the shorter K loops (at least 8 steps of 16).
 void auto_split(GemmProblem& p, double* ws, int maxsplit = kMaxSplit) {
+  // the workspace also serves a stream-K schedule, which the launcher may choose
+  p.ws = ws;
+  p.ws_slots = kMaxSplit;
   const bool big = p.M % 128 == 0 && p.N % 128 == 0 && std::min(p.M, p.N) >= 512;
   const int T = big ? 128 : 64;
   const long long slots = big ? 256 : 512;
@@ -126,6 +129,13 @@ void auto_split(GemmProblem& p, double* ws, int maxsplit = kMaxSplit) {
     p.ksplit = best;
     p.ws = ws;
   }
+}
+
+// Hand the split workspace (kMaxSplit * M * N elements) to a problem that is launched
+// without auto_split, so that the launcher may give it a stream-K schedule.
+void with_ws(GemmProblem& p, double* ws) {
+  p.ws = ws;
+  p.ws_slots = kMaxSplit;
 }
 
 void carve(Arena& a, Buffers& b, int m, int r, int what, bool mixed = false) {
@@ -828,6 +838,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
                          kAUpper | kBLower);
     pg[1] = gemm_problem(mp, mp, mp, b.wmk + S, mp, 1, b.wmk, mp, 0, b.y + S, mp, 1.0, 0.0,
                          nullptr, 0, kALower | kBUpper);
+    with_ws(pg[0], b.splitws);
     gemm_f64(s, pg, 2);
   }
   mask_pad(s, b.y, m, mp, S, 2);
@@ -947,6 +958,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
                            kBUpper);                              // R_M^{-1} U R_G^{-1}
       pe[1] = gemm_problem(mp, mp, mp, b.wmk + S, mp, 0, b.wc, mp, 0, b.s12, mp, 1.0, 0.0,
                            nullptr, 0, kAUpper | kBUpper);        // R_K^{-1} R_G^{-1}
+      with_ws(pe[0], b.splitws);
       gemm_f64(s, pe, 2);
       sum_diff_scaled(s, b.t2, b.s12, b.top, b.qbot, M_SQRT1_2, mp);
     }
@@ -969,11 +981,13 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
                          kBUpper);
     pg[1] = gemm_problem(mp, mp, mp, U, mp, 0, b.wmk + S, mp, 1, b.t2, mp, 1.0, 0.0, nullptr, 0,
                          kBLower);
+    with_ws(pg[0], b.splitws);
     gemm_f64(s, pg, 2);
     pg[0] = gemm_problem(mp, mp, mp, b.wmk, mp, 0, b.t1, mp, 0, b.s12, mp, 1.0, 0.0, nullptr, 0,
                          kAUpper);
     pg[1] = gemm_problem(mp, mp, mp, b.mk, mp, 1, b.t2, mp, 0, b.s21, mp, 1.0, 0.0, nullptr, 0,
                          kALower);
+    with_ws(pg[0], b.splitws);
     gemm_f64(s, pg, 2);
     sign_blocks(s, b.s12, b.s21, b.as, b.bs, mp);
   }
@@ -1108,6 +1122,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
                          kAUpper | kBLower | kOutUpper | kMirror);
     pg[1] = gemm_problem(np, np, np, W, np, 1, b.t2, np, 0, b.y + S, np, 1.0, 0.0, nullptr, 0,
                          kALower | kBUpper | kOutUpper | kMirror);
+    with_ws(pg[0], b.splitws);
     gemm_f64(s, pg, 2);
   }
   tm.mark(0);

@@ -74,6 +74,8 @@ struct GemmProblemT {
   double alpha, beta;
   double kscale[kMaxSeg];
   T* ws;            // ksplit * M * N elements per batch entry (only when ksplit > 1)
+  int ws_slots;     // ws holds ws_slots * M * N elements (0: unknown); the launcher may
+                    // then use it for the partial tiles of a stream-K schedule
   // optional per-batch-entry scalars in device memory (entry z = z1 + nb1 * z2); when
   // set they replace alpha, beta and kscale (kscale_b[z * nseg + s])
   const double* alpha_b;
