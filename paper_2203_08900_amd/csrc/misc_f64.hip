@@ -395,81 +395,6 @@ void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned) {
   PS_HIP(hipGetLastError());
 }
 
-// y_b[j] = sum_i M_b(i, j) x_b[i]: one wave per column.  Each lane takes 16-byte pairs
-// of the column and of x, eight pairs per round with all sixteen loads issued before
-// the first multiply, so a wave keeps 8 KB of the column in flight instead of one
-// dependent load per iteration (mp is a multiple of 64, the buffers 16-byte aligned).
-__global__ void coldots_kernel(const double* mat, long long mstride, const double* x,
-                               long long xstride, double* y, long long ystride, int mp) {
-  constexpr int U = 8;
-  const int b = blockIdx.y;
-  const int col = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (col >= mp) return;
-  const double2* Mc = reinterpret_cast<const double2*>(mat + b * mstride + (size_t)col * mp);
-  const double2* X = reinterpret_cast<const double2*>(x + b * xstride);
-  const int n2 = mp / 2;
-  double acc0 = 0.0, acc1 = 0.0;
-  for (int base = 0; base < n2; base += 64 * U) {
-    double2 a[U], v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + lane + 64 * u;
-      a[u] = i < n2 ? Mc[i] : double2{0.0, 0.0};
-      v[u] = i < n2 ? X[i] : double2{0.0, 0.0};
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      acc0 += a[u].x * v[u].x;
-      acc1 += a[u].y * v[u].y;
-    }
-  }
-  const double acc = warp_sum(acc0 + acc1);
-  if (lane == 0) y[b * ystride + col] = acc;
-}
-
-void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
-             long long xstride, double* y, long long ystride, int mp, int batch) {
-  hipLaunchKernelGGL(coldots_kernel, dim3((mp + 3) / 4, batch), dim3(NT), 0, s, mat, mstride, x,
-                     xstride, y, ystride, mp);
-  PS_HIP(hipGetLastError());
-}
-
-// w = p - hist[prev] * wprev;  hist[out] = ||w||;  w /= ||w||   (one block per batch item)
-__global__ void gk_update_kernel(const double* p, long long pstride, double* w,
-                                 long long wstride, const double* wprev, long long wpstride,
-                                 double* hist, int hist_prev, int hist_out, int hist_ld, int m) {
-  __shared__ double sh[1024 / 64];
-  __shared__ double tot;
-  const int b = blockIdx.x;
-  const double* P = p + b * pstride;
-  double* Wv = w + b * wstride;
-  const double* Wp = wprev ? wprev + b * wpstride : nullptr;
-  double* Hs = hist + (size_t)b * hist_ld;
-  const double g = (Wp && hist_prev >= 0) ? Hs[hist_prev] : 0.0;
-  double q = 0.0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    double v = P[i];
-    if (Wp) v -= g * Wp[i];
-    Wv[i] = v;
-    q += v * v;
-  }
-  // block_sum for blockDim 1024
-  double v = warp_sum(q);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = 0.0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
-    tot = sqrt(r);
-    Hs[hist_out] = tot;
-  }
-  __syncthreads();
-  const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) Wv[i] *= inv;
-}
-
 // One half-step of the bidiagonalization per launch, with the vectors kept unnormalized
 // (w~ = ||w~|| w): w~ = M x / ||x~|| - ||x~|| wprev~ / ||wprev~||, where x~ is the previous
 // half-step's vector and wprev~ the one before (the coefficient of the recurrence is the
@@ -577,14 +502,6 @@ void gk_finish(hipStream_t s, const double* part, int mp, double* hist, int hist
                int batch) {
   hipLaunchKernelGGL(gk_finish_kernel, dim3(batch), dim3(NT), 0, s, part, gk_parts(mp), hist,
                      hist_out, hist_ld);
-  PS_HIP(hipGetLastError());
-}
-
-void gk_update(hipStream_t s, const double* p, long long pstride, double* w, long long wstride,
-               const double* wprev, long long wpstride, double* hist, int hist_prev,
-               int hist_out, int hist_ld, int m, int batch) {
-  hipLaunchKernelGGL(gk_update_kernel, dim3(batch), dim3(1024), 0, s, p, pstride, w, wstride,
-                     wprev, wpstride, hist, hist_prev, hist_out, hist_ld, m);
   PS_HIP(hipGetLastError());
 }
 

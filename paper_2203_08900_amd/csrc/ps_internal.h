@@ -266,8 +266,6 @@ void half_shift_upper_b(hipStream_t s, const double* as, double* p11, int mp, in
 void basis_mix_b(hipStream_t s, const double* c, const double* qbot, double* top_out, double* ab,
                  int mp, int nb);
 void mask_pad_b(hipStream_t s, double* x, const int* m_dev, int mp, int per, int count);
-void coldots(hipStream_t s, const double* mat, long long mstride, const double* x,
-             long long xstride, double* y, long long ystride, int mp, int batch);
 // Bidiagonalization half-steps with unnormalized vectors and per-workgroup partial
 // sums of squares (gk_parts(mp) per batch item): gk_seed writes the partials of a unit
 // vector, gk_step forms w~ = M x / ||x~|| - ||x~|| wprev~ / ||wprev~|| (wprev null: none)
@@ -280,8 +278,5 @@ void gk_step(hipStream_t s, const double* mat, long long mstride, const double* 
              double* hist, int hist_x, int hist_ld, int mp, int batch);
 void gk_finish(hipStream_t s, const double* part, int mp, double* hist, int hist_out, int hist_ld,
                int batch);
-void gk_update(hipStream_t s, const double* p, long long pstride, double* w,
-               long long wstride, const double* wprev, long long wpstride,
-               double* hist, int hist_prev, int hist_out, int hist_ld, int m, int batch);
 
 }  // namespace ps
