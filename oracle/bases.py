@@ -13,6 +13,15 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 * ``alg7_ldl_bases``: Alg. 7, the truncated pivoted LDL^T variant: ldl(Sigma P_+)
   = L D L^T, diagonalize the 1x1/2x2 blocks of D, keep the p largest entries,
   Q_+ = Sigma L V(:,1:p) D(1:p,1:p)^{1/2}; likewise with ldl(-Sigma P_-).
+* ``pivoted_ldl_factor`` / ``alg7_pivoted_bases``: Alg. 7 with the LDL^T of Sigma P_+
+  (and of -Sigma P_-) taken with 1x1 pivots and diagonal pivoting.  Both matrices are
+  positive semidefinite with known rank (Thm. DefDivConq, Thm. EVREalSigmaOrth), so D
+  is diagonal, its eigen-decomposition in step 4 is the identity, and the pivots come
+  out in the order the truncation keeps.  Pivot rule (the paper leaves the pivoting to
+  its ldl): per panel of `panel` columns, the `cand` largest diagonal entries of the
+  current Schur complement (ties: lower index) are the candidates, and each pivot is
+  the largest Schur diagonal among the remaining candidates (ties: lower index).  With
+  `cand` at least the matrix size this is complete diagonal pivoting (LAPACK xPSTRF).
 * ``alg4_orthogonal_bases``: Alg. 4 for a symmetric matrix: r_+ = trace(P_+),
   lower Cholesky factor of the leading r_+ block of P_+ extended by
   P_+(r_++1:n,1:r_+) Q_{1,+}^{-T}; the second half uses P_- throughout (the
@@ -124,6 +133,77 @@ def alg7_ldl_bases(s: np.ndarray, sigma: np.ndarray):
     q_plus = _truncated_ldl_basis(sigma[:, None] * pp, p, sigma)
     q_minus = _truncated_ldl_basis(-(sigma[:, None] * pm), q, sigma)
     return q_plus, q_minus
+
+
+def pivoted_ldl_factor(z: np.ndarray, keep: int, panel: int = 64, cand: int = 128):
+    """Truncated LDL^T with 1x1 pivots of the symmetric positive semidefinite z (Alg. 7
+    steps 3-5): returns (C, piv) with C = L D^{1/2} restricted to the first `keep`
+    pivots, rows in the original order (so z ~ C C^T when z has rank `keep`), and the
+    pivot indices in the order taken.  Pivot rule as in the module docstring."""
+    if cand < panel:
+        raise ValueError("a panel needs at least as many candidates as pivots")
+    z = 0.5 * (np.array(z, dtype=np.float64) + np.array(z, dtype=np.float64).T)
+    n = z.shape[0]
+    c = np.zeros((n, keep))
+    piv = []
+    free = np.ones(n, dtype=bool)
+    for t0 in range(0, keep, panel):
+        nb = min(panel, keep - t0)
+        d = np.diag(z).copy()
+        idx = np.flatnonzero(free)
+        order = np.lexsort((idx, -d[idx]))          # largest first, then lower index
+        cands = idx[order[:min(cand, idx.size)]]
+        # greedy pivoting inside the candidate block (right-looking, one column a pivot)
+        cd = d[cands].copy()
+        cfree = np.ones(cands.size, dtype=bool)
+        cb = np.zeros((cands.size, nb))
+        slots = []
+        for jj in range(nb):
+            live = np.flatnonzero(cfree)
+            if live.size == 0:
+                raise np.linalg.LinAlgError("pivoted LDL^T: no candidate left")
+            best = live[np.lexsort((cands[live], -cd[live]))[0]]
+            if not cd[best] > 0.0:
+                raise np.linalg.LinAlgError("pivoted LDL^T: non-positive retained pivot")
+            sq = np.sqrt(cd[best])
+            col = (z[cands, cands[best]] - cb[:, :jj] @ cb[best, :jj]) / sq
+            col[best] = sq
+            col[~cfree] = 0.0
+            cb[:, jj] = col
+            cfree[best] = False
+            cd[cfree] -= col[cfree] ** 2
+            slots.append(best)
+        pp = cands[slots]
+        lpp = cb[slots, :]                           # nb x nb, lower triangular
+        # the panel for every row: z(:, pivots) L_pp^{-T}; rows pivoted earlier are zero,
+        # the pivot rows are L_pp itself
+        cp = sla.solve_triangular(lpp, z[:, pp].T, lower=True).T
+        cp[~free] = 0.0
+        cp[pp] = lpp
+        c[:, t0:t0 + nb] = cp
+        z = z - cp @ cp.T
+        free[pp] = False
+        piv.extend(int(i) for i in pp)
+    return c, np.array(piv, dtype=np.int64)
+
+
+def ldl_matrices(s: np.ndarray, sigma: np.ndarray):
+    """Sigma P_+ = (Sigma S + Sigma)/2 and -Sigma P_- = (Sigma S - Sigma)/2, symmetrized
+    (Sigma S is symmetric for the sign of a Sigma-self-adjoint matrix)."""
+    ss = sigma[:, None] * s
+    ss = 0.5 * (ss + ss.T)
+    return 0.5 * (ss + np.diag(sigma)), 0.5 * (ss - np.diag(sigma))
+
+
+def alg7_pivoted_bases(s: np.ndarray, sigma: np.ndarray, panel: int = 64, cand: int = 128):
+    """Alg. 7 with the pivoted 1x1 LDL^T above: Q_+ = Sigma C_+ with C_+ C_+^T = Sigma P_+
+    (rank p), Q_- = Sigma C_- with C_- C_-^T = -Sigma P_- (rank n - p).  Returns (Q_+, Q_-)."""
+    p = int(np.sum(sigma > 0))
+    q = s.shape[0] - p
+    zp, zm = ldl_matrices(s, sigma)
+    cp, _ = pivoted_ldl_factor(zp, p, panel, cand) if p else (np.zeros((s.shape[0], 0)), None)
+    cm, _ = pivoted_ldl_factor(zm, q, panel, cand) if q else (np.zeros((s.shape[0], 0)), None)
+    return sigma[:, None] * cp, sigma[:, None] * cm
 
 
 def alg4_orthogonal_bases(s: np.ndarray):

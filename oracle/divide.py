@@ -50,6 +50,8 @@ def divide_casida(a: np.ndarray, b: np.ndarray, r: int = 8, alpha=None, beta=Non
             qm = bs.alg7_ldl_bases(s, sigma)[1]
     elif basis == "alg7":
         qp, qm = bs.alg7_ldl_bases(s, sigma)
+    elif basis == "alg7-pivoted":
+        qp, qm = bs.alg7_pivoted_bases(s, sigma)
     else:
         raise ValueError(basis)
     hp, hm, bwd = decouple(h, sigma, qp, qm)
@@ -58,13 +60,19 @@ def divide_casida(a: np.ndarray, b: np.ndarray, r: int = 8, alpha=None, beta=Non
 
 
 def divide_general(h: np.ndarray, sigma: np.ndarray, r: int = 8, alpha=None, beta=None,
-                   max_restarts: int = 2):
+                   max_restarts: int = 2, basis: str = "alg6"):
     """Spectral division of a definite pseudosymmetric H for any signature Sigma
     (Sigma H symmetric positive definite; Sec. 5 and the matrices of Sec. 6.1): sign(H)
     by Alg. 8 with LDL^T solves on H, bases by Alg. 6 as printed (leading indices,
-    Q_- with the sign of Thm. HRisLDL), decoupled blocks and backward error."""
+    Q_- with the sign of Thm. HRisLDL) or by Alg. 7 with the pivoted 1x1 LDL^T
+    (basis = "alg7-pivoted"), decoupled blocks and backward error."""
     s, rec = sg.zolo_pd(h, sigma, r=r, alpha=alpha, beta=beta, max_restarts=max_restarts)
-    qp, qm = bs.alg6_bases_general(s, sigma)
+    if basis == "alg6":
+        qp, qm = bs.alg6_bases_general(s, sigma)
+    elif basis == "alg7-pivoted":
+        qp, qm = bs.alg7_pivoted_bases(s, sigma)
+    else:
+        raise ValueError(basis)
     hp, hm, bwd = decouple(h, sigma, qp, qm)
     return {"H": h, "sigma": sigma, "S": s, "Q_plus": qp, "Q_minus": qm,
             "H_plus": hp, "H_minus": hm, "backward_error": bwd, "record": rec}
