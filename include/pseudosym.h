@@ -57,7 +57,8 @@ enum {
   PS_NOT_CONVERGED = 3,    /* the stopping test of Alg. 8 failed after max_restarts restarts */
   PS_HIP_ERROR = 4,        /* a HIP runtime call failed */
   PS_NO_WORKSPACE = 5,     /* the caller-provided workspace is too small */
-  PS_BASIS_BREAKDOWN = 6   /* Cholesky of the leading block of P_+ failed (Alg. 6) */
+  PS_BASIS_BREAKDOWN = 6   /* Cholesky of the leading block of P_+ failed (Alg. 6), or
+                              a non-positive pivot among the retained ones (Alg. 7) */
 };
 
 /* arithmetic of the Zolotarev steps */
@@ -79,8 +80,18 @@ enum {
  *                 Y0^{-1} U + (Y0^{-1} U)^T = R_G^T R_G, Q_+ = Z R_G^{-1} and
  *                 H_+ = 2 R_G^{-T} R_G^{-1}.  It needs neither the sign blocks nor the
  *                 Alg. 6 decoupling products; Q_+ differs from the Alg. 6 basis by an
- *                 orthogonal factor G (H_+ by G^T H_+ G). */
-enum { PS_BASIS_ALG6 = 0, PS_BASIS_CORE = 1 };
+ *                 orthogonal factor G (H_+ by G^T H_+ G).
+ *  PS_BASIS_LDL:  Alg. 7, the robust variant: Sigma P_+ = (Sigma S + Sigma)/2 (2m x 2m,
+ *                 positive semidefinite of rank m) = C C^T by a truncated LDL^T with
+ *                 1x1 pivots and diagonal pivoting (D diagonal, C = L D^{1/2}), and
+ *                 Q_+ = Sigma C.  Pivots: per panel of 64, the 128 largest diagonal
+ *                 entries of the Schur complement (ties: lower index) are candidates and
+ *                 each pivot is the largest remaining one among them (ties: lower index).
+ *                 It avoids the leading-block Cholesky that Alg. 6 needs; Q_+ differs
+ *                 from the Alg. 6 basis by an orthogonal factor.  Padded 2m up to 16384;
+ *                 pseudosym_divide and pseudosym_divide_general only.  A non-positive
+ *                 retained pivot returns PS_BASIS_BREAKDOWN. */
+enum { PS_BASIS_ALG6 = 0, PS_BASIS_CORE = 1, PS_BASIS_LDL = 2 };
 
 typedef struct {
   int precision;       /* PS_PREC_*                                               */
@@ -105,7 +116,8 @@ typedef struct {
                        /* series in Delta = X^T X - I instead of r factorizations   */
                        /* (the same rational function to below 1e-17)               */
   int basis;           /* pseudosym_divide / pseudosym_eig: PS_BASIS_ALG6 (default) */
-                       /* or PS_BASIS_CORE, see below                             */
+                       /* or PS_BASIS_CORE, see below; PS_BASIS_LDL for           */
+                       /* pseudosym_divide and pseudosym_divide_general          */
   int iteration;       /* PS_ITER_ZOLO (Alg. 8, default) or one of the comparison  */
                        /* iterations of Sec. 6, see below (FP64 only)             */
   int refine;          /* what follows the iteration, PS_REFINE_*:               */
@@ -269,7 +281,10 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
  * condition number of M exceeds about 1e7 (the shifted T^2 + c I then have condition
  * numbers near 1/u); the leading blocks of Alg. 6 can be ill-conditioned for an
  * unlucky Sigma, which PS_BASIS_BREAKDOWN reports when their Cholesky fails.
- * opts->max_steps must be 0; opts->basis is ignored. */
+ * opts->basis = PS_BASIS_LDL takes Alg. 7 instead (truncated LDL^T with diagonal
+ * pivoting of Sigma P_+ and -Sigma P_-, Q_+- = Sigma C_+-; padded n up to 16384, else
+ * -16), which needs no leading block to be well conditioned; any other value gives
+ * Alg. 6.  opts->max_steps must be 0. */
 int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const double* sigma,
                              double* S, int lds, double* Qp, int ldqp, double* Qm, int ldqm,
                              double* Hp, int ldhp, double* Hm, int ldhm, const ps_opts* opts,

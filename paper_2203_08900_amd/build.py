@@ -24,6 +24,7 @@ SOURCES = [
     "eig_f64.hip",
     "mixed.hip",
     "general.hip",
+    "ldl_f64.hip",
     "static_scratch.hip",
     "zolo_host.cpp",
     "pipeline.cpp",

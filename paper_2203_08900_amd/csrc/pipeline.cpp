@@ -144,7 +144,9 @@ void carve(Arena& a, Buffers& b, int m, int r, int what, bool mixed = false) {
   b.r = r;
   const size_t S = (size_t)b.mp * b.mp;
   b.S = S;
-  const int rr = std::max(r, what >= 2 ? 8 : 2);   // the eig subproblems use 8 slots
+  // the eig subproblems use 8 slots; a division at least 4 (the 2m x 2m matrix of the
+  // Alg. 7 factorization goes there)
+  const int rr = std::max(r, what >= 2 ? 8 : (what == 1 ? 4 : 2));
   b.mk = a.take<double>(2 * S);
   b.wmk = a.take<double>(2 * S);
   b.tmp = a.take<double>((size_t)rr * b.mp * kNb);
@@ -997,6 +999,16 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     copy_out(s, b.as, mp, out1, ld1, m, m);
     copy_out(s, b.bs, mp, out2, ld2, m, m);
   } else {
+    if (o.basis == PS_BASIS_LDL) {
+    // ---- Alg. 7: Sigma P_+ = (Sigma S + Sigma)/2 (2m x 2m, rank m) = C C^T by the
+    // truncated LDL^T with diagonal pivoting, Q_+ = Sigma C
+    const int np = pad_to(2 * m);
+    int* iw = reinterpret_cast<int*>(b.t2);
+    const LdlScratch lw{b.F, b.p11, b.wc, iw, iw + mp};
+    ldl_form_casida(s, b.as, b.bs, m, mp, np, 1.0, b.z);
+    ldl_factor(s, b.z, 2 * m, np, m, b.w, lw, b.dinfo + 4);
+    ldl_casida_out(s, b.w, np, m, mp, b.top, b.qbot, b.ab);
+    } else {
     // ---- Alg. 6: C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
     half_shift_upper(s, b.as, b.p11, mp);
     potrf_inv_f64(s, b.p11, S, b.wc, S, b.tmp, mp, 1, b.dinfo + 4, true, nullptr, b.t1, S);
@@ -1008,6 +1020,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     }
     mask_pad(s, b.qbot, m, mp, S, 1);
     basis_mix(s, b.p11, b.qbot, b.top, b.ab, mp);
+    }
     mask_pad(s, b.ab, m, mp, S, 2);
     tm.mark(6);
     // ---- decoupling: H_+ = (R_M a)^T (R_M a) + (R_K b)^T (R_K b)
@@ -1178,10 +1191,19 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
                    int ldho, int slot) {
     if (k == 0) return;
     const int kp = pad_to(k), rp = pad_to(std::max(n - k, 1));
+    double* Q = b.ab;   // np x kp, ld np
+    if (o.basis == PS_BASIS_LDL) {
+      // Alg. 7: a Sigma P_a = (Sigma S + a Sigma)/2 (rank k) = C C^T by the truncated
+      // LDL^T with diagonal pivoting, Q = Sigma C
+      int* iw = reinterpret_cast<int*>(b.t2);
+      const LdlScratch lw{b.F, b.p11, b.wc, iw, iw + kp};
+      ldl_form_general(s, Sg, sg, n, np, a, b.z);
+      ldl_factor(s, b.z, n, np, k, b.w, lw, b.dinfo + slot);
+      ldl_scale_rows(s, b.w, np, kp, sg, n, Q);
+    } else {
     lead_block(s, Sg, np, sg, k, kp, a, b.p11);
     potrf_inv_f64(s, b.p11, 0, b.wc, 0, b.tmp, kp, 1, b.dinfo + slot, true, nullptr, b.t2, 0);
     chol_top(s, b.p11, kp, sg, k, t, b.top);
-    double* Q = b.ab;   // np x kp, ld np
     copy_pad(s, b.top, kp, k, k, Q, np, k, kp);
     if (n > k) {
       copy_pad(s, Sg + k, np, n - k, k, b.qbot, rp, rp, kp);
@@ -1191,6 +1213,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
       copy_pad(s, b.t1, rp, n - k, k, Q + k, np, np - k, kp);
     } else if (np > k) {
       copy_pad(s, b.t1, rp, 0, 0, Q + k, np, np - k, kp);   // zero padding rows
+    }
     }
     GemmProblem pf = gemm_problem(np, kp, np, R, np, 0, Q, np, 0, b.F, np, 1.0, 0.0, nullptr, 0,
                                   kAUpper);
@@ -1695,7 +1718,9 @@ int check_common(ps_handle h, int m, const double* A, int lda, const double* B, 
   if (ldb < m) return -6;
   if (o && (o->r < 0 || o->r > 8 || o->max_restarts < 0 || o->max_steps < 0 ||
             o->max_steps > 1 || (o->precision != PS_PREC_FP64 && o->precision != PS_PREC_MIXED) ||
-            (o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE) ||
+            (o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE &&
+             o->basis != PS_BASIS_LDL) ||
+            (o->basis == PS_BASIS_LDL && pad_to(2 * m) > kLdlMaxN) ||
             o->iteration < PS_ITER_ZOLO || o->iteration > PS_ITER_NEWTON ||
             o->refine < PS_REFINE_NONE || o->refine > PS_REFINE_NS ||
             (o->iteration != PS_ITER_ZOLO &&
@@ -2440,7 +2465,8 @@ int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const
   if (q > 0 && ldhm < q) return -15;
   if (n > kPinned) return -2;
   if (opts && (opts->r < 0 || opts->r > 8 || opts->max_restarts < 0 || opts->max_steps != 0 ||
-               (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED)))
+               (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED) ||
+               (opts->basis == PS_BASIS_LDL && pad_to(n) > kLdlMaxN)))
     return -16;
   ps_opts o;
   ps_opts_default(&o);
@@ -2455,6 +2481,7 @@ int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B,
                   double* lambda, double* V, int ldv, const ps_opts* opts, ps_info* info) {
   int chk = check_common(h, m, A, lda, B, ldb, opts);
   if (chk) return chk;
+  if (opts && opts->basis == PS_BASIS_LDL) return -11;   // the recursion takes Alg. 4 bases
   if (!lambda) return -7;
   if (V && ldv < 2 * m) return -9;
   ps_opts o;
@@ -2494,7 +2521,8 @@ int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double*
   }
   if (opts && (opts->r < 0 || opts->r > 8 || opts->max_restarts < 0 || opts->max_steps < 0 ||
                opts->max_steps > 1 ||
-               (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED)))
+               (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED) ||
+               (opts->basis != PS_BASIS_ALG6 && opts->basis != PS_BASIS_CORE)))
     return -12;
   ps_opts o;
   ps_opts_default(&o);

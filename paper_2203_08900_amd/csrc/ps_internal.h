@@ -279,4 +279,33 @@ void gk_step(hipStream_t s, const double* mat, long long mstride, const double* 
 void gk_finish(hipStream_t s, const double* part, int mp, double* hist, int hist_out, int hist_ld,
                int batch);
 
+// ----------------------------------------------------------------- Alg. 7 (ldl_f64.hip)
+// Truncated LDL^T with 1x1 pivots and diagonal pivoting of a positive semidefinite Z of
+// rank k (upper triangle, n x n in np x np, np a multiple of 64 up to kLdlMaxN), by
+// panels of kLdlPanel pivots chosen greedily among the kLdlCand largest Schur diagonals.
+// C (np x pad(k), ld np) gets L D^{1/2} in the original row order; Z is overwritten by
+// Schur complements.  info[0] = 1 on a non-positive pivot.
+constexpr int kLdlPanel = 64;
+constexpr int kLdlCand = 128;
+constexpr int kLdlMaxN = 16384;
+struct LdlScratch {
+  double* G;   // np x 64: the panel's pivot columns
+  double* W;   // 64 x 64: L_pp^{-T}
+  double* L;   // 64 x 64: L_pp
+  int* piv;    // pad(k): pivots in the order taken
+  int* mask;   // np: rows pivoted so far
+};
+void ldl_factor(hipStream_t s, double* Z, int n, int np, int k, double* C, const LdlScratch& w,
+                int* info);
+// Z = (Sigma S + a Sigma)/2 (upper triangle): a = +1 gives Sigma P_+, a = -1 gives
+// -Sigma P_-.  Casida form from the sign blocks (n = 2m), or any signature from S.
+void ldl_form_casida(hipStream_t s, const double* as, const double* bs, int m, int mp, int np,
+                     double a, double* Z);
+void ldl_form_general(hipStream_t s, const double* S, const double* sg, int n, int np, double a,
+                      double* Z);
+void ldl_casida_out(hipStream_t s, const double* C, int np, int m, int mp, double* top,
+                    double* qbot, double* ab);
+void ldl_scale_rows(hipStream_t s, const double* C, int np, int kp, const double* sg, int n,
+                    double* Q);
+
 }  // namespace ps

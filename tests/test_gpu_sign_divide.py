@@ -255,6 +255,17 @@ def test_full_size_parity_fp64(m, seed):
     assert np.abs(pq - pref).max() < 1e-11 * max(1.0, np.abs(pref).max())
     w = np.linalg.eigvalsh(0.5 * (Hc + Hc.T))
     assert np.max(np.abs(w - ref["lam"]) / ref["lam"]) < 1e-12
+    print(f"[full size] m={m} divide (Alg. 7, pivoted LDL^T)", flush=True)
+    Ql, Hl, info = api.divide(dev(a), dev(b), basis="ldl")
+    assert info["status"] == 0
+    Ql, Hl = Ql.cpu().numpy(), Hl.cpu().numpy()
+    cref, _ = bs.pivoted_ldl_factor(bs.ldl_matrices(s, sigma)[0], m)
+    qref = sigma[:, None] * cref
+    assert rel(Ql, qref) < 1e-9
+    assert rel(Hl, qref.T @ ((sigma[:, None] * ref["h"]) @ qref)) < 1e-9
+    assert np.abs(Ql.T @ (sigma[:, None] * Ql) - np.eye(m)).max() < 1e-11
+    w = np.linalg.eigvalsh(0.5 * (Hl + Hl.T))
+    assert np.max(np.abs(w - ref["lam"]) / ref["lam"]) < 1e-12
 
 
 @pytest.mark.timeout(600)
