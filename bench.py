@@ -11,7 +11,8 @@ already resident in device memory.  Prints one JSON line (rank 0, one GPU).
                                 eig_n4096|adjoint_n2048]
 
 modes      : fp64 / mixed (precision of the Zolotarev steps) x basis (Alg. 6, or
-             "-core": the basis from the half-size core); all are timed and reported,
+             "-core": the basis from the half-size core, or "-ldl": Alg. 7 with the
+             pivoted LDL^T); all are timed and reported,
              the primary one (the first of mixed-core, mixed, fp64-core, fp64 that was
              run) gives `value`.
 value      : TFLOP/s of the primary mode = nominal algorithmic flops of the executed
@@ -59,7 +60,12 @@ def nominal_flops(m: int, r: int, step2_terms: int, basis: str = "alg6") -> floa
         tail = m3 + m3 + 2 * m3 / 3 + m3 + m3 / 3 + m3 / 3
     else:
         assemble = 4 * m3                                     # S12 = W_M U R_K, S21 = R_M^T U W_K^T
-        bases = 2 * m3 / 3 + m3                               # chol+inverse of (I+A_s)/2, B_s C^{-1}
+        if basis == "ldl":
+            # Alg. 7: rank-m pivoted LDL^T of the 2m x 2m Sigma P_+, sum over pivots j of
+            # (2m - j)^2 for j < m = 7m^3/3
+            bases = 7 * m3 / 3
+        else:
+            bases = 2 * m3 / 3 + m3                           # chol+inverse of (I+A_s)/2, B_s C^{-1}
         decouple = 2 * m3 + 2 * m3                            # R_M a, R_K b, F^T F (K = 2m)
         tail = assemble + bases + decouple
     return setup + step1 + step2 + tail
@@ -111,10 +117,12 @@ def gpu_leg(args, a, b):
 
 
 def mode_options(mode: str, r: int):
-    """precision[-core][-norefine]: FP64 or mixed steps, Alg. 6 or the core basis, and the
-    FP64 refinement (default) or none (the mixed path's result before refinement)."""
+    """precision[-core|-ldl][-norefine]: FP64 or mixed steps, Alg. 6, the core basis or
+    Alg. 7, and the FP64 refinement (default) or none (the mixed path's result before
+    refinement)."""
     parts = mode.split("-")
-    return dict(precision=parts[0], r=r, basis="core" if "core" in parts else "alg6",
+    return dict(precision=parts[0], r=r,
+                basis="core" if "core" in parts else ("ldl" if "ldl" in parts else "alg6"),
                 refine="none" if "norefine" in parts else "rr")
 
 
@@ -132,6 +140,8 @@ def batched_leg(args):
     out = {}
     for mode in args.modes:
         kw = mode_options(mode, args.r)
+        if kw["basis"] == "ldl":   # the batched call offers Alg. 6 and the core basis
+            continue
         for _ in range(args.warmup):
             api.divide_batched(As, Bs, **kw)
         torch.cuda.synchronize()
@@ -309,6 +319,7 @@ _CSRC = os.path.join(ROOT, "paper_2203_08900_amd", "csrc")
 TRAFFIC_PROFILES = {
     0: ("chol_step_wide_f64_traffic_casida_n4096.txt", ["chol_f64.hip", "chol_block.h", "gemm_tile.h"]),
     3: ("gemm_f64_128x128_traffic_casida_n4096.txt", ["gemm_f64.hip", "gemm_tile.h"]),
+    4: ("gemm_f64_64x64_traffic_casida_n4096.txt", ["gemm_f64.hip", "gemm_tile.h"]),
 }
 CLASS_DTYPE = ["f64", "f64", "f32", "f64", "f64", "f32"]
 
@@ -397,7 +408,8 @@ def main():
                              "eig_n4096", "adjoint_n2048", "general_n5000"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
     ap.add_argument("--r", type=int, default=8)
-    ap.add_argument("--modes", default="fp64,mixed,fp64-core,mixed-core,mixed-core-norefine")
+    ap.add_argument("--modes",
+                    default="fp64,mixed,fp64-core,mixed-core,mixed-core-norefine,mixed-ldl")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain device copy of 512 MiB three times (calibrates the "

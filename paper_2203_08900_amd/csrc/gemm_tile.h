@@ -93,7 +93,8 @@ struct GemmLds {
 // a full output) enumerate their tiles longest first, so the long tiles start in the
 // first wave of workgroups and the short ones fill in behind them; triangular outputs
 // go by columns ascending, which already puts the long tiles of the usual lower-K-bound
-// operands first.
+// operands first (their launches are mostly a single round of workgroups, where the
+// start order only moves tiles between the XCDs' caches).
 template <int BM, int BN, class Prob>
 __host__ __device__ inline void tile_coords(const Prob& P, int t, int& I, int& J) {
   const int tri_ops = (P.flags & (kOutUpper | kOutLower))
@@ -131,6 +132,26 @@ __host__ __device__ inline void tile_coords(const Prob& P, int t, int& I, int& J
     if (tri_ops == (kALower | kBUpper)) {
       I = P.tm - 1 - I;
       J = P.tn - 1 - J;
+    }
+  } else if ((tri_ops == (kAUpper | kBUpper) || tri_ops == (kALower | kBLower)) && P.tm == P.tn) {
+    // K from i0 to j0 + BN (resp. from j0 to i0 + BM): diagonals of the nonzero triangle,
+    // the far corner first (longest K), then the empty tiles of the other triangle
+    const int T = P.tm, ntri = T * (T + 1) / 2;
+    if (t < ntri) {
+      int e, r;
+      tri_index(t, e, r);   // diagonal e from the far corner, position r along it
+      I = r;
+      J = r + (T - 1 - e);
+    } else {
+      int a, b;
+      tri_index(t - ntri, a, b);   // strictly below the diagonal: (a + 1, b)
+      I = a + 1;
+      J = b;
+    }
+    if (tri_ops == (kALower | kBLower)) {
+      const int x = I;
+      I = J;
+      J = x;
     }
   } else {
     I = t % P.tm;
