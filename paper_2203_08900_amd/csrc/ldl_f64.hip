@@ -7,11 +7,11 @@
 // would make every pivot a dependency across the whole matrix; instead one workgroup
 // picks the panel's candidates, the 128 largest diagonal entries of the current Schur
 // complement (ties: lower index), gathers their 128 x 128 block into LDS and takes the 64
-// pivots greedily inside it (largest remaining Schur diagonal, ties: lower index), and
-// inverts the panel's 64 x 64 pivot factor L_pp.  The panel of every row is then one
-// matrix-core product, C(:, panel) = Z(:, pivots) L_pp^{-T}, and the Schur complement
-// takes a rank-64 update.  C keeps the original row order; Z is stored as its upper
-// triangle only.
+// pivots greedily inside it (largest remaining Schur diagonal, ties: lower index), which
+// gives the panel's 64 x 64 pivot factor L_pp.  Every other row then solves
+// C(i, panel) L_pp^T = Z(i, pivots) by forward substitution (one thread per row, L_pp
+// broadcast from LDS), and the Schur complement takes a rank-64 update on the matrix
+// cores.  C keeps the original row order; Z is stored as its upper triangle only.
 #include "ps_internal.h"
 
 namespace ps {
@@ -77,13 +77,13 @@ __device__ inline int block_excl_scan(int v, int* wsum, int* total) {
 // One panel's pivots.  Inputs: Z (upper triangle of the Schur complement), mask (1 for
 // rows already pivoted and for padding rows), nb <= 64 pivots wanted.  Outputs:
 // piv[0:64] (global row of pivot q, -1 where none), L (64 x 64, column-major: L_pp,
-// identity rows beyond the pivots taken), W = L^{-T} (64 x 64, column-major), and on a
-// non-positive pivot or too few rows info[0] = 1.
+// identity rows beyond the pivots taken), and on a non-positive pivot or too few rows
+// info[0] = 1.
 __global__ void __launch_bounds__(kThr) ldl_panel_kernel(const double* Z, int np, int n,
                                                          const int* mask, int nb, int* piv,
-                                                         double* Lout, double* Wout, int* info) {
+                                                         double* Lout, int* info) {
   __shared__ double tri[kTri];                  // the candidate block, packed lower triangle
-  __shared__ double cb[kCand][kPanel + 1];      // panel columns of the candidate rows
+  __shared__ double cbT[kPanel][kCand];         // panel columns of the candidate rows
   __shared__ int cand[kCand];                   // global row of each candidate slot
   __shared__ int pslot[kPanel];                 // candidate slot of pivot q, -1: none
   __shared__ int hist[256];
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kThr) ldl_panel_kernel(const double* Z, int np
     if (tid == 0) info[0] = 1;
     for (int e = tid; e < kPanel * kPanel; e += kThr) {
       const int i = e % kPanel, j = e / kPanel;
-      Lout[e] = Wout[e] = (i == j) ? 1.0 : 0.0;
+      Lout[e] = (i == j) ? 1.0 : 0.0;
     }
     return;
   }
@@ -163,23 +163,30 @@ __global__ void __launch_bounds__(kThr) ldl_panel_kernel(const double* Z, int np
     eqcount = sel[2];
     __syncthreads();
   }
-  (void)eqcount;
   // ---- candidates: every key above the threshold, and the `want` lowest-index rows
   // whose key equals it (T of them; the count is capped and re-read, so a slot is only
-  // used once written)
+  // used once written).  The ranks among equal keys need a scan only when some of them
+  // are left out (uniform branch).
   if (tid == 0) sel[3] = 0;
   if (tid < kCand) cand[tid] = -1;
+  const bool all_eq = want == eqcount;
+  const int kpt = (np + kThr - 1) / kThr;
   int eqbase = 0;
 #pragma unroll
   for (int u = 0; u < kKeysPerThread; ++u) {
-    const int eq = key[u] == prefix ? 1 : 0;
-    int tot;
-    const int rank = eqbase + block_excl_scan(eq, wsum, &tot);
-    eqbase += tot;
-    const bool take = key[u] > prefix || (eq && rank < want);
-    if (take) {
-      const int slot = atomicAdd(&sel[3], 1);
-      if (slot < kCand) cand[slot] = tid + kThr * u;
+    if (u < kpt) {
+      const int eq = key[u] == prefix ? 1 : 0;
+      int rank = 0;
+      if (!all_eq) {
+        int tot;
+        rank = eqbase + block_excl_scan(eq, wsum, &tot);
+        eqbase += tot;
+      }
+      const bool take = key[u] > prefix || (eq && rank < want);
+      if (take) {
+        const int slot = atomicAdd(&sel[3], 1);
+        if (slot < kCand) cand[slot] = tid + kThr * u;
+      }
     }
   }
   __syncthreads();
@@ -220,20 +227,30 @@ __global__ void __launch_bounds__(kThr) ldl_panel_kernel(const double* Z, int np
       const int p = bs;
       const double sq = sqrt(bd), inv = 1.0 / sq;
       double c0 = 0.0, c1 = 0.0;
+      // both slots' dot products with the pivot row in one pass over the earlier
+      // columns (consecutive lanes read consecutive candidates: no bank conflicts), two
+      // partial sums per slot
+      double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+      int j = 0;
+#pragma unroll 2
+      for (; j + 1 < jj; j += 2) {
+        const double pj = cbT[j][p], pk = cbT[j + 1][p];
+        s0 += cbT[j][a0] * pj;
+        s1 += cbT[j][a1] * pj;
+        t0 += cbT[j + 1][a0] * pk;
+        t1 += cbT[j + 1][a1] * pk;
+      }
+      if (j < jj) {
+        const double pj = cbT[j][p];
+        s0 += cbT[j][a0] * pj;
+        s1 += cbT[j][a1] * pj;
+      }
       if (a0 == p) c0 = sq;
-      else if (f0) {
-        double acc = tri[tri_at(a0, p)];
-        for (int j = 0; j < jj; ++j) acc -= cb[a0][j] * cb[p][j];
-        c0 = acc * inv;
-      }
+      else if (f0) c0 = (tri[tri_at(a0, p)] - (s0 + t0)) * inv;
       if (a1 == p) c1 = sq;
-      else if (f1) {
-        double acc = tri[tri_at(a1, p)];
-        for (int j = 0; j < jj; ++j) acc -= cb[a1][j] * cb[p][j];
-        c1 = acc * inv;
-      }
-      cb[a0][jj] = c0;
-      if (a1 < kCand) cb[a1][jj] = c1;
+      else if (f1) c1 = (tri[tri_at(a1, p)] - (s1 + t1)) * inv;
+      cbT[jj][a0] = c0;
+      cbT[jj][a1] = c1;
       if (a0 == p) f0 = false;
       else if (f0) d0 -= c0 * c0;
       if (a1 == p) f1 = false;
@@ -254,53 +271,53 @@ __global__ void __launch_bounds__(kThr) ldl_panel_kernel(const double* Z, int np
   for (int e = tid; e < kPanel * kPanel; e += kThr) {
     const int i = e % kPanel, j = e / kPanel;
     const int ps = pslot[i];
-    Lout[e] = ps >= 0 ? (j <= i ? cb[ps][j] : 0.0) : (i == j ? 1.0 : 0.0);
-  }
-  // ---- W = L_pp^{-T}: lane c of wave 0 solves L x = e_c by forward substitution (the
-  // entries of L broadcast from LDS, x kept in the candidate block's area, which the
-  // chain no longer needs), W(c, r) = x_r
-  if (wave == 0) {
-    const int c = lane;
-    double* X = tri;   // [kPanel][kPanel + 1]
-    for (int r = 0; r < kPanel; ++r) {
-      const int ps = pslot[r];
-      double acc = 0.0;
-      if (ps >= 0)
-        for (int k = 0; k < r; ++k) acc += cb[ps][k] * X[k * (kPanel + 1) + c];
-      const double lrr = ps >= 0 ? cb[ps][r] : 1.0;
-      const double v = (r == c) ? 1.0 / lrr : (r > c ? -acc / lrr : 0.0);
-      X[r * (kPanel + 1) + c] = v;
-      Wout[c + (size_t)kPanel * r] = v;
-    }
+    Lout[e] = ps >= 0 ? (j <= i ? cbT[j][ps] : 0.0) : (i == j ? 1.0 : 0.0);
   }
 }
 
-// G(i, q) = Z(i, piv[q]) for the panel's pivots, zero columns where there is none
-__global__ void ldl_gather_kernel(const double* Z, int np, const int* piv, double* G) {
-  const int q = blockIdx.y;
-  const int p = piv[q];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x)
-    G[i + (size_t)q * np] = p >= 0 ? zsym(Z, np, i, p) : 0.0;
-}
-
-// Rows pivoted in earlier panels get zeros, the panel's pivot rows get L_pp exactly, and
-// those rows are marked pivoted.  One thread per row, its 64 entries of the panel.
-__global__ void ldl_fix_kernel(double* Cp, int np, int* mask, const int* piv, const double* L) {
+// The panel's columns of every row: rows pivoted in earlier panels get zeros, the
+// panel's pivot rows get L_pp, and every other row i solves c L_pp^T = Z(i, pivots) by
+// forward substitution (one thread per row, c in registers, L_pp and the reciprocals of
+// its diagonal broadcast from LDS); the pivot rows are marked pivoted.
+__global__ void __launch_bounds__(64) ldl_rows_kernel(const double* Z, int np, double* Cp,
+                                                      int* mask, const int* piv,
+                                                      const double* L) {
+  __shared__ double Ls[kPanel][kPanel + 1];
+  __shared__ double rd[kPanel];
   __shared__ int pv[kPanel];
-  if (threadIdx.x < kPanel) pv[threadIdx.x] = piv[threadIdx.x];
+  for (int e = threadIdx.x; e < kPanel * kPanel; e += blockDim.x)
+    Ls[e % kPanel][e / kPanel] = L[e];
+  pv[threadIdx.x] = piv[threadIdx.x];
+  __syncthreads();
+  rd[threadIdx.x] = 1.0 / Ls[threadIdx.x][threadIdx.x];
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   int q = -1;
   for (int t = 0; t < kPanel; ++t)
     if (pv[t] == i) q = t;
-  const bool earlier = mask[i] != 0;
-  for (int j = 0; j < kPanel; ++j) {
-    double* e = Cp + i + (size_t)j * np;
-    if (q >= 0) *e = j <= q ? L[q + (size_t)kPanel * j] : 0.0;
-    else if (earlier || pv[j] < 0) *e = 0.0;
+  double* out = Cp + i;
+  if (q >= 0) {
+    for (int j = 0; j < kPanel; ++j) out[(size_t)j * np] = j <= q ? Ls[q][j] : 0.0;
+    mask[i] = 1;
+    return;
   }
-  if (q >= 0) mask[i] = 1;
+  if (mask[i] != 0) {
+    for (int j = 0; j < kPanel; ++j) out[(size_t)j * np] = 0.0;
+    return;
+  }
+  double c[kPanel];
+#pragma unroll
+  for (int j = 0; j < kPanel; ++j) c[j] = pv[j] >= 0 ? zsym(Z, np, i, pv[j]) : 0.0;
+#pragma unroll
+  for (int j = 0; j < kPanel; ++j) {
+    double sacc = c[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) sacc -= c[k] * Ls[j][k];
+    c[j] = pv[j] >= 0 ? sacc * rd[j] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < kPanel; ++j) out[(size_t)j * np] = c[j];
 }
 
 __global__ void ldl_mask_kernel(int* mask, int n, int np) {
@@ -389,16 +406,10 @@ void ldl_factor(hipStream_t s, double* Z, int n, int np, int k, double* C, const
     const int nb = std::min(kPanel, k - t0);
     int* pv = w.piv + t0;
     hipLaunchKernelGGL(ldl_panel_kernel, dim3(1), dim3(kThr), 0, s, Z, np, n, w.mask, nb, pv, w.L,
-                       w.W, info);
-    PS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(ldl_gather_kernel, dim3((np + NT - 1) / NT, kPanel), dim3(NT), 0, s, Z, np,
-                       pv, w.G);
+                       info);
     PS_HIP(hipGetLastError());
     double* Cp = C + (size_t)t0 * np;
-    GemmProblem pp = gemm_problem(np, kPanel, kPanel, w.G, np, 0, w.W, kPanel, 0, Cp, np, 1.0, 0.0,
-                                  nullptr, 0, kBUpper);
-    gemm_f64(s, pp);
-    hipLaunchKernelGGL(ldl_fix_kernel, dim3((np + NT - 1) / NT), dim3(NT), 0, s, Cp, np, w.mask,
+    hipLaunchKernelGGL(ldl_rows_kernel, dim3((np + 63) / 64), dim3(64), 0, s, Z, np, Cp, w.mask,
                        pv, w.L);
     PS_HIP(hipGetLastError());
     if (t0 + kPanel < k) {   // Schur complement, upper triangle, in place

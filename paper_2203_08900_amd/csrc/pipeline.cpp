@@ -1004,7 +1004,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     // truncated LDL^T with diagonal pivoting, Q_+ = Sigma C
     const int np = pad_to(2 * m);
     int* iw = reinterpret_cast<int*>(b.t2);
-    const LdlScratch lw{b.F, b.p11, b.wc, iw, iw + mp};
+    const LdlScratch lw{b.wc, iw, iw + mp};
     ldl_form_casida(s, b.as, b.bs, m, mp, np, 1.0, b.z);
     ldl_factor(s, b.z, 2 * m, np, m, b.w, lw, b.dinfo + 4);
     ldl_casida_out(s, b.w, np, m, mp, b.top, b.qbot, b.ab);
@@ -1196,7 +1196,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
       // Alg. 7: a Sigma P_a = (Sigma S + a Sigma)/2 (rank k) = C C^T by the truncated
       // LDL^T with diagonal pivoting, Q = Sigma C
       int* iw = reinterpret_cast<int*>(b.t2);
-      const LdlScratch lw{b.F, b.p11, b.wc, iw, iw + kp};
+      const LdlScratch lw{b.wc, iw, iw + kp};
       ldl_form_general(s, Sg, sg, n, np, a, b.z);
       ldl_factor(s, b.z, n, np, k, b.w, lw, b.dinfo + slot);
       ldl_scale_rows(s, b.w, np, kp, sg, n, Q);

@@ -289,9 +289,7 @@ constexpr int kLdlPanel = 64;
 constexpr int kLdlCand = 128;
 constexpr int kLdlMaxN = 16384;
 struct LdlScratch {
-  double* G;   // np x 64: the panel's pivot columns
-  double* W;   // 64 x 64: L_pp^{-T}
-  double* L;   // 64 x 64: L_pp
+  double* L;   // 64 x 64: the panel's pivot factor L_pp
   int* piv;    // pad(k): pivots in the order taken
   int* mask;   // np: rows pivoted so far
 };
