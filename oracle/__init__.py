@@ -22,4 +22,7 @@ eig         Plain-definition eigen-decomposition (simultaneous diagonalization
             of Sigma*H and Sigma, Thm. EVREalSigmaOrth), canonical ordering, and
             Alg. 2 (symmetric spectral divide-and-conquer) for the recursion.
 grad        Daleckii-Krein reference gradient of trace(W P_+).
+hermitian   The complex Bethe-Salpeter forms Eq:BSE1 and Eq:BSE2: sign(H) by the
+            definite pencil and by the general eigensolver, Alg. 6 and H_+ in
+            complex arithmetic.
 """

@@ -30,6 +30,10 @@ Workload families (draw order matters for reproducibility and is fixed here):
 * ``general_sigma(n, seed, kappa)`` - H = Sigma Q D Q^T with a random signature Sigma,
   Q orthonormalized from U[0, 1) entries and D equally spaced in [1, kappa]: the
   random definite pseudosymmetric matrices of the paper's experiments (Sec. 6.1).
+* ``bse2_like(m, seed)`` / ``bse1_like(m, seed)`` - complex blocks of the
+  Bethe-Salpeter forms (Sec. 5): A = U diag(U[1,10]) U^H with U Haar-unitary, and B
+  Hermitian (Eq:BSE2) or complex symmetric (Eq:BSE1) from a complex Gaussian, scaled to
+  ||B||_2 = 0.5 lambda_min(A), so that Sigma H is Hermitian positive definite.
 """
 from __future__ import annotations
 
@@ -44,6 +48,8 @@ __all__ = [
     "ill_separated",
     "gradient_weight",
     "general_sigma",
+    "bse2_like",
+    "bse1_like",
     "workload",
     "WORKLOADS",
 ]
@@ -144,6 +150,32 @@ def general_sigma(n: int, seed: int, kappa: float):
     m = _sym((q * d[None, :]) @ q.T)
     h = sigma[:, None] * m
     return np.ascontiguousarray(h), sigma
+
+
+def _complex_blocks(m: int, seed: int, hermitian_b: bool):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    q, r = np.linalg.qr(g)
+    q = q * (np.diag(r) / np.abs(np.diag(r)))[None, :].conj()
+    d = rng.uniform(1.0, 10.0, m)
+    a = (q * d[None, :]) @ q.conj().T
+    a = 0.5 * (a + a.conj().T)
+    g2 = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    b = 0.5 * (g2 + (g2.conj().T if hermitian_b else g2.T))
+    lam_min = float(np.linalg.eigvalsh(a)[0])
+    b *= 0.5 * lam_min / float(np.linalg.norm(b, 2))
+    return np.ascontiguousarray(a), np.ascontiguousarray(b)
+
+
+def bse2_like(m: int, seed: int):
+    """Complex Casida form (Eq:BSE2): A, B Hermitian, A +- B Hermitian positive definite."""
+    return _complex_blocks(m, seed, True)
+
+
+def bse1_like(m: int, seed: int):
+    """Bethe-Salpeter form (Eq:BSE1): A Hermitian, B complex symmetric, with
+    [[A, B], [conj(B), conj(A)]] Hermitian positive definite."""
+    return _complex_blocks(m, seed, False)
 
 
 def gradient_weight(m: int, seed: int) -> np.ndarray:
