@@ -201,8 +201,9 @@ int ps_destroy(ps_handle h);
 int ps_set_stream(ps_handle h, void* stream);
 
 /* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig and
- * sign_fwd, 3 sign_bwd, 4 divide_general) needs at half-size m (for kind 4: the order n
- * of H) with options o (NULL = defaults). */
+ * sign_fwd, 3 sign_bwd, 4 divide_general, 5 the complex forms: sign_hermitian,
+ * divide_hermitian, sign_bse) needs at half-size m (for kind 4: the order n of H) with
+ * options o (NULL = defaults). */
 size_t ps_workspace_size(int m, const ps_opts* o, int what);
 
 /* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the
@@ -289,6 +290,37 @@ int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const
                              double* S, int lds, double* Qp, int ldqp, double* Qm, int ldqm,
                              double* Hp, int ldhp, double* Hm, int ldhm, const ps_opts* opts,
                              ps_info* info);
+
+/* The complex Bethe-Salpeter forms of Sec. 5, definite (Sigma H Hermitian positive
+ * definite, Sigma = diag(I_m, -I_m)).  Matrices are complex double, stored as interleaved
+ * (real, imaginary) pairs of doubles, column-major, device memory; leading dimensions
+ * count complex entries.  The library realifies them (each complex entry becomes a
+ * 2 x 2 real block), runs the real pipeline at half-size 2m on the real Casida form that
+ * results, and reads the complex results back, so the accuracy, options and statuses
+ * are those of the real calls at half-size 2m.  Workspace: ps_workspace_size(m, opts, 5).
+ *
+ * Eq:BSE2: H = [[A, B], [-B, -A]], A and B Hermitian m x m, A + B and A - B positive
+ * definite.  sign(H) keeps the form: SA, SB Hermitian m x m (ld lds >= m). */
+int pseudosym_sign_hermitian(ps_handle h, int m, const double* A, int lda, const double* B,
+                             int ldb, double* SA, double* SB, int lds, const ps_opts* opts,
+                             ps_info* info);
+
+/* Eq:BSE2 division: Qp (2m x m complex, ldq >= 2m) with Q_+^H Sigma Q_+ = I spanning the
+ * invariant subspace of the m positive eigenvalues, and Hp = Q_+^H Sigma H Q_+ (m x m
+ * Hermitian positive definite, ldh >= m) holding them (Thm. DefDivConq).  opts->basis:
+ * PS_BASIS_ALG6 (Alg. 6 in complex arithmetic: the top block of Q_+ is lower triangular
+ * with a real positive diagonal, which makes it unique) or PS_BASIS_CORE; Alg. 7 is not
+ * offered here (its pivot choice may separate the two real rows of a complex one).
+ * opts->max_steps must be 0. */
+int pseudosym_divide_hermitian(ps_handle h, int m, const double* A, int lda, const double* B,
+                               int ldb, double* Qp, int ldq, double* Hp, int ldh,
+                               const ps_opts* opts, ps_info* info);
+
+/* Eq:BSE1: H = [[A, B], [-conj(B), -conj(A)]], A Hermitian and B complex symmetric m x m,
+ * [[A, B], [conj(B), conj(A)]] positive definite.  sign(H) keeps the form
+ * [[SA, SB], [-conj(SB), -conj(SA)]]: SA Hermitian and SB complex symmetric (lds >= m). */
+int pseudosym_sign_bse(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                       double* SA, double* SB, int lds, const ps_opts* opts, ps_info* info);
 
 /* pseudosym_divide without any workspace, for callers that cannot allocate device memory
  * (code under graph capture, tight serving loops, harnesses that forbid allocation).  The

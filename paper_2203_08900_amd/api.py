@@ -107,6 +107,7 @@ EXPORTS = [
     "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
     "pseudosym_divide_static", "pseudosym_divide_general", "pseudosym_eig",
     "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
+    "pseudosym_sign_hermitian", "pseudosym_divide_hermitian", "pseudosym_sign_bse",
     "ps_status_string",
 ]
 
@@ -157,6 +158,13 @@ def load():
         lib.pseudosym_divide_static.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
                                                       ctypes.POINTER(PsInfo)]
         lib.pseudosym_divide_static.restype = ip
+        for name in ("pseudosym_sign_hermitian", "pseudosym_sign_bse"):
+            fn = getattr(lib, name)
+            fn.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts), ctypes.POINTER(PsInfo)]
+            fn.restype = ip
+        lib.pseudosym_divide_hermitian.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
+                                                         ctypes.POINTER(PsInfo)]
+        lib.pseudosym_divide_hermitian.restype = ip
         lib.pseudosym_divide_general.argtypes = [hp, ip, vp, ip, ctypes.POINTER(ctypes.c_double),
                                                  vp, ip, vp, ip, vp, ip, vp, ip, vp, ip,
                                                  ctypes.POINTER(PsOpts), ctypes.POINTER(PsInfo)]
@@ -336,6 +344,59 @@ def divide(A, B, raise_on_error=True, **kw):
     if rc != 0 and raise_on_error:
         raise PseudosymError(rc, info.as_dict())
     return Qt.t(), Hp.t(), info.as_dict() | {"rc": rc}
+
+
+def _complex_call(name, A, B, out_rows, raise_on_error, kw):
+    """Complex blocks in, two complex outputs (out_rows x m and m x m) back, column-major
+    for the library (the transposed contiguous copy of a row-major tensor)."""
+    torch = _torch()
+    lib = load()
+    for t, nm in ((A, "A"), (B, "B")):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+            raise TypeError(f"{nm} must be a complex128 tensor on a ROCm device")
+        if t.dim() != 2 or t.shape[0] != t.shape[1]:
+            raise ValueError(f"{nm} must be square")
+    if A.shape != B.shape or A.device != B.device:
+        raise ValueError("A and B must have the same shape and device")
+    m = A.shape[0]
+    Ac, Bc = A.t().contiguous(), B.t().contiguous()      # column-major storage
+    opts = make_opts(**kw)
+    dev = A.device
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        st = _handle(dev.index, stream.cuda_stream)
+        _ensure_workspace(st, lib, m, opts, 5, dev)
+    O1 = torch.empty((m, out_rows), dtype=torch.complex128, device=dev)   # column-major
+    O2 = torch.empty((m, m), dtype=torch.complex128, device=dev)
+    info = PsInfo()
+    if name == "pseudosym_divide_hermitian":
+        rc = lib.pseudosym_divide_hermitian(st.handle, m, Ac.data_ptr(), m, Bc.data_ptr(), m,
+                                            O1.data_ptr(), out_rows, O2.data_ptr(), m,
+                                            ctypes.byref(opts), ctypes.byref(info))
+    else:   # sign blocks: one leading dimension for both
+        rc = getattr(lib, name)(st.handle, m, Ac.data_ptr(), m, Bc.data_ptr(), m, O1.data_ptr(),
+                                O2.data_ptr(), m, ctypes.byref(opts), ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    return O1.t(), O2.t(), info.as_dict() | {"rc": rc}
+
+
+def sign_hermitian(A, B, raise_on_error=True, **kw):
+    """Blocks (SA, SB) of sign(H), H = [[A, B], [-B, -A]] with A, B Hermitian (Eq:BSE2;
+    complex128 device tensors).  Returns (SA, SB, info)."""
+    return _complex_call("pseudosym_sign_hermitian", A, B, A.shape[0], raise_on_error, kw)
+
+
+def divide_hermitian(A, B, raise_on_error=True, **kw):
+    """Q_+ (2m x m) and H_+ (m x m) for H = [[A, B], [-B, -A]] with A, B Hermitian
+    (Eq:BSE2).  Returns (Qp, Hp, info)."""
+    return _complex_call("pseudosym_divide_hermitian", A, B, 2 * A.shape[0], raise_on_error, kw)
+
+
+def sign_bse(A, B, raise_on_error=True, **kw):
+    """Blocks (SA, SB) of sign(H), H = [[A, B], [-conj(B), -conj(A)]] with A Hermitian
+    and B complex symmetric (Eq:BSE1).  Returns (SA, SB, info)."""
+    return _complex_call("pseudosym_sign_bse", A, B, A.shape[0], raise_on_error, kw)
 
 
 def divide_general(H, sigma, want_sign=False, raise_on_error=True, **kw):

@@ -25,6 +25,7 @@ SOURCES = [
     "mixed.hip",
     "general.hip",
     "ldl_f64.hip",
+    "hermitian.hip",
     "static_scratch.hip",
     "zolo_host.cpp",
     "pipeline.cpp",

@@ -784,9 +784,11 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
   return status;
 }
 
+// pairs: A and B are realified complex matrices (Eq:BSE2): the polar factor is projected
+// back onto the realified form, which the mixed steps' FP32 factorizations perturb
 int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
         int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what,
-        char* ws = nullptr) {
+        char* ws = nullptr, bool pairs = false) {
   hipStream_t s = h->stream;
   const int r = resolve_r(o);
   // workspace: the caller's (or `ws`, which the caller has checked for size)
@@ -882,6 +884,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     return status;
   }
 
+  if (pairs) pair_project(s, b.x2, m, mp);
   const double* U = b.x2;
   // ---- FP64 Newton-Schulz pass on the polar factor: U <- U (3I - U^T U)/2 (refine 2)
   if (o.refine >= PS_REFINE_NS) {
@@ -1243,6 +1246,52 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
   inf.status = PS_OK;
   if (info) *info = inf;
   return PS_OK;
+}
+
+// ---------------------------------------------------------------- complex forms
+// The Bethe-Salpeter forms of Sec. 5 through the interleaved realification (see
+// hermitian.hip): A and B realified into the real Casida blocks of half-size 2m, the
+// real pipeline on those, and the complex results read back from the realified ones.
+// Workspace: the realified blocks and outputs (5 (2m)^2 doubles), then the real
+// pipeline's own.
+size_t hermitian_bytes(int m, const ps_opts& o) {
+  const size_t n2 = (size_t)(2 * m) * (2 * m);
+  return (5 * n2 * sizeof(double) + kAlign - 1) / kAlign * kAlign + workspace_bytes(2 * m, o, 1);
+}
+
+// what: 0 sign blocks, 1 division (Q_+ 2m x m, H_+ m x m); flip_b: Eq:BSE1 (B complex
+// symmetric, lower blocks conjugated) instead of Eq:BSE2 (B Hermitian)
+int run_hermitian(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                  double* O1, int ld1, double* O2, int ld2, const ps_opts& o, ps_info* info,
+                  int what, bool flip_b) {
+  hipStream_t s = h->stream;
+  char* base = workspace_base(h, hermitian_bytes(m, o));
+  if (!base) return PS_NO_WORKSPACE;
+  const int m2 = 2 * m;
+  const size_t n2 = (size_t)m2 * m2;
+  double* Ar = reinterpret_cast<double*>(base);
+  double* Br = Ar + n2;
+  double* R1 = Br + n2;        // sign block A_s or Q_+ (4m x 2m)
+  double* R2 = R1 + 2 * n2;    // sign block B_s or H_+
+  char* ws = base + (5 * n2 * sizeof(double) + kAlign - 1) / kAlign * kAlign;
+  realify(s, A, lda, m, Ar, m2, 0);
+  realify(s, B, ldb, m, Br, m2, flip_b ? 1 : 0);
+  int rc;
+  if (what == 0) {
+    rc = run(h, m2, Ar, m2, Br, m2, R1, m2, R2, m2, o, info, 0, ws, !flip_b);
+    if (rc == PS_OK) {
+      complexify(s, R1, m2, m, m, O1, ld1);
+      complexify(s, R2, m2, m, m, O2, ld2);
+    }
+  } else {
+    rc = run(h, m2, Ar, m2, Br, m2, R1, 2 * m2, R2, m2, o, info, 1, ws, !flip_b);
+    if (rc == PS_OK) {
+      complexify(s, R1, 2 * m2, 2 * m, m, O1, ld1);
+      complexify(s, R2, m2, m, m, O2, ld2);
+    }
+  }
+  if (rc == PS_OK) PS_HIP(hipStreamSynchronize(s));
+  return rc;
 }
 
 // ---------------------------------------------------------------- eigen-decomposition
@@ -2331,6 +2380,7 @@ size_t ps_workspace_size(int m, const ps_opts* o, int what) {
   ps_opts_default(&d);
   if (m < 1) return 0;
   if (what == 4) return general_bytes(m, o ? *o : d);
+  if (what == 5) return hermitian_bytes(m, o ? *o : d);
   if (what >= 3) return adjoint_bytes(m);
   return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : what);
 }
@@ -2474,6 +2524,68 @@ int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const
   return guarded(h, [&] {
     return run_general(h, n, H, ldh, sigma, S, lds, Qp, ldqp, Qm, ldqm, Hp, ldhp, Hm, ldhm, o,
                        info);
+  });
+}
+
+// Argument checks of the complex entry points (leading dimensions in complex entries)
+int check_complex(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                  const double* O1, int ld1, const double* O2, int ld2, int ld1_min,
+                  const ps_opts* o, bool divide) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (!B) return -5;
+  if (ldb < m) return -6;
+  if (!O1) return -7;
+  if (ld1 < ld1_min) return -8;
+  if (!O2) return -9;
+  if (ld2 < m) return -10;
+  if (o && (o->r < 0 || o->r > 8 || o->max_restarts < 0 || o->max_steps != 0 ||
+            (o->precision != PS_PREC_FP64 && o->precision != PS_PREC_MIXED) ||
+            o->iteration != PS_ITER_ZOLO || o->refine < PS_REFINE_NONE ||
+            o->refine > PS_REFINE_NS ||
+            (divide && o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE)))
+    return -11;
+  return 0;
+}
+
+int pseudosym_sign_hermitian(ps_handle h, int m, const double* A, int lda, const double* B,
+                             int ldb, double* SA, double* SB, int lds, const ps_opts* opts,
+                             ps_info* info) {
+  int chk = check_complex(h, m, A, lda, B, ldb, SA, lds, SB, lds, m, opts, false);
+  if (chk) return chk;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  return guarded(h, [&] {
+    return run_hermitian(h, m, A, lda, B, ldb, SA, lds, SB, lds, o, info, 0, false);
+  });
+}
+
+int pseudosym_divide_hermitian(ps_handle h, int m, const double* A, int lda, const double* B,
+                               int ldb, double* Qp, int ldq, double* Hp, int ldh,
+                               const ps_opts* opts, ps_info* info) {
+  int chk = check_complex(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, 2 * m, opts, true);
+  if (chk) return chk;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  return guarded(h, [&] {
+    return run_hermitian(h, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, info, 1, false);
+  });
+}
+
+int pseudosym_sign_bse(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                       double* SA, double* SB, int lds, const ps_opts* opts, ps_info* info) {
+  int chk = check_complex(h, m, A, lda, B, ldb, SA, lds, SB, lds, m, opts, false);
+  if (chk) return chk;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  return guarded(h, [&] {
+    return run_hermitian(h, m, A, lda, B, ldb, SA, lds, SB, lds, o, info, 0, true);
   });
 }
 

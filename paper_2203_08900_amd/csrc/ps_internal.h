@@ -306,4 +306,15 @@ void ldl_casida_out(hipStream_t s, const double* C, int np, int m, int mp, doubl
 void ldl_scale_rows(hipStream_t s, const double* C, int np, int kp, const double* sg, int n,
                     double* Q);
 
+// ----------------------------------------------------------------- complex forms (hermitian.hip)
+// Interleaved realification of a complex m x m matrix (double pairs, ld in complex
+// entries) into a real 2m x 2m one: each entry becomes [[re, -im], [im, re]] (flip = 0)
+// or [[re, im], [im, -re]] (flip = 1); complexify reads (re, im) back from the first
+// column of each 2 x 2 block (rows x cols complex).
+void realify(hipStream_t s, const double* X, int ldx, int m, double* Y, int ldy, int flip);
+void complexify(hipStream_t s, const double* Y, int ldy, int rows, int cols, double* X, int ldx);
+// the nearest realified matrix: each 2 x 2 block becomes [[re, -im], [im, re]] with re and
+// im the averages of their two copies (m2 even)
+void pair_project(hipStream_t s, double* X, int m2, int ldx);
+
 }  // namespace ps
