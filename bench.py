@@ -8,7 +8,7 @@ already resident in device memory.  Prints one JSON line (rank 0, one GPU).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes ...] [--no-cpu]
                     [--workload casida_n4096|ill_separated_n16384|batched_256|eig_n128|
-                                eig_n4096|adjoint_n2048]
+                                eig_n4096|adjoint_n2048|general_n5000|bse2_n2048]
 
 modes      : fp64 / mixed (precision of the Zolotarev steps) x basis (Alg. 6, or
              "-core": the basis from the half-size core, or "-ldl": Alg. 7 with the
@@ -293,6 +293,45 @@ def general_leg(args):
             "backward_error_n250": sweep}
 
 
+def bse_leg(args):
+    """The complex Casida form Eq:BSE2 (A, B Hermitian) at complex m = 1024 (n = 2048):
+    sign + division in FP64 and mixed precision, Alg. 6 and the core basis.  The rate
+    counts the complex algorithm's flops (one complex multiply-add = 8 real flops, 4x the
+    real count at the same m); the library computes it on the realified real form at
+    half-size 2m, whose real flops are twice that.  Relative eigenvalue error of H_+
+    against the positive eigenvalues of H from LAPACK's complex eigensolver on the host."""
+    import numpy as np
+    import torch
+    from paper_2203_08900_amd import api, inputs
+
+    m = args.m or 1024
+    a, b = inputs.bse2_like(m, 1)
+    A = torch.tensor(a, dtype=torch.complex128, device="cuda:0")
+    B = torch.tensor(b, dtype=torch.complex128, device="cuda:0")
+    h = np.block([[a, b], [-b, -a]])
+    lam = np.linalg.eigvals(h).real
+    lam = np.sort(lam[lam > 0])
+    modes = {}
+    for mode in ("fp64", "mixed", "fp64-core", "mixed-core"):
+        kw = mode_options(mode, args.r)
+        ms, (Qp, Hp, info) = _timed(lambda: api.divide_hermitian(A, B, **kw), args.steps,
+                                    args.warmup)
+        Hh = Hp.cpu().numpy()
+        w = np.sort(np.linalg.eigvalsh(0.5 * (Hh + Hh.conj().T)))
+        flops = 4.0 * nominal_flops(m, info["r"], info["step2_terms"], kw["basis"])
+        modes[mode] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                       "rel_eig_err": float(np.max(np.abs(w - lam) / lam))}
+    primary = modes["mixed-core"]
+    return {"metric": "sign-fn+divide time & TFLOP/s, complex Casida form (Eq:BSE2)",
+            "value": primary["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": primary["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"bse2_like m={m} (n={2 * m}) seed 1: A = U diag(U[1,10]) U^H, "
+                                   "B Hermitian Gaussian, ||B|| = 0.5 lambda_min(A)",
+                       "n": 2 * m, "m": m, "precision": "mixed-core"},
+            "rel_eig_err": primary["rel_eig_err"], "modes": modes}
+
+
 def copy_probe(nbytes: int = 512 << 20):
     """A plain streaming kernel of known size: y = -x over nbytes of FP64 (reads and
     writes nbytes each)."""
@@ -405,7 +444,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="casida_n4096",
                     choices=["casida_n4096", "ill_separated_n16384", "batched_256", "eig_n128",
-                             "eig_n4096", "adjoint_n2048", "general_n5000"])
+                             "eig_n4096", "adjoint_n2048", "general_n5000", "bse2_n2048"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--modes",
@@ -438,6 +477,9 @@ def main():
         return
     if args.workload == "general_n5000":
         print(json.dumps(general_leg(args)), flush=True)
+        return
+    if args.workload == "bse2_n2048":
+        print(json.dumps(bse_leg(args)), flush=True)
         return
     if args.workload == "casida_n4096":
         args.m = args.m or 2048
