@@ -200,6 +200,16 @@ int ps_create(ps_handle* h, void* stream);
 int ps_destroy(ps_handle h);
 int ps_set_stream(ps_handle h, void* stream);
 
+/* Batched division (the benchmark spec batching, Alg. 2's independent problems): after the bounds
+ * and coefficients of a class are known, its launch sequence (both Zolotarev steps, the
+ * stopping-test norms, the bases and the decoupled blocks) is captured once as a HIP
+ * graph and replayed when a class with the same sizes, options and workspace comes again
+ * (up to 32 graphs kept per handle and worker; the runtime holds their resources until
+ * ps_destroy).  enable = 1 (default) or 0 (every launch issued directly, as on the first
+ * call); results are identical either way.  Applies to the handle and its workers.
+ * Returns 0, -1 (no handle) or -2 (enable not 0 or 1). */
+int ps_set_graphs(ps_handle h, int enable);
+
 /* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig and
  * sign_fwd, 3 sign_bwd, 4 divide_general, 5 the complex forms: sign_hermitian,
  * divide_hermitian, sign_bse) needs at half-size m (for kind 4: the order n of H) with

@@ -104,7 +104,7 @@ class PsInfo(ctypes.Structure):
 EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
     "ps_set_workspace", "ps_workspace_size_batched", "ps_set_worker_streams",
-    "ps_zolotarev_coeffs", "pseudosym_sign", "pseudosym_divide",
+    "ps_zolotarev_coeffs", "ps_set_graphs", "pseudosym_sign", "pseudosym_divide",
     "pseudosym_divide_static", "pseudosym_divide_general", "pseudosym_eig",
     "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
     "pseudosym_sign_hermitian", "pseudosym_divide_hermitian", "pseudosym_sign_bse",
@@ -149,6 +149,8 @@ def load():
         lib.ps_set_worker_streams.restype = ip
         lib.ps_zolotarev_coeffs.argtypes = [ctypes.c_double, ip, dp, dp, dp, dp]
         lib.ps_zolotarev_coeffs.restype = ip
+        lib.ps_set_graphs.argtypes = [hp, ip]
+        lib.ps_set_graphs.restype = ip
         mat = [hp, ip, vp, ip, vp, ip]
         lib.pseudosym_sign.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts), ctypes.POINTER(PsInfo)]
         lib.pseudosym_sign.restype = ip
@@ -490,6 +492,20 @@ def divide_batched(As, Bs, raise_on_error=True, **kw):
         raise PseudosymError(rc)
     return ([q.t() for q in Qts], [h.t() for h in Hps],
             [infos[i].as_dict() | {"rc": rc} for i in range(n)])
+
+
+def set_graphs(enable=True, device=None):
+    """Capture and replay the batched pipeline's class launch sequences as HIP graphs
+    (default on) or issue every launch directly; applies to the handle of the current
+    stream on `device` and its workers."""
+    torch = _torch()
+    lib = load()
+    dev = torch.device("cuda", device if device is not None else torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        st = _handle(dev.index, torch.cuda.current_stream(dev).cuda_stream)
+    rc = lib.ps_set_graphs(st.handle, 1 if enable else 0)
+    if rc != 0:
+        raise PseudosymError(rc)
 
 
 def _colmajor(x):

@@ -52,6 +52,14 @@ struct ps_handle_s {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   std::vector<ps_handle_s*> workers;   // one per worker stream (batched calls, recursion)
+  // captured launch sequences of the batched pipeline, replayed when a class with the
+  // same key comes again (ps_set_graphs; oldest dropped beyond kGraphCache)
+  struct GraphEntry {
+    std::vector<long long> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool use_graphs = true;
 };
 
 namespace ps {
@@ -63,6 +71,7 @@ constexpr int kPinned = 1 << 16;  // doubles (host staging: up to m = 32768 valu
 // stream hand-offs than its arithmetic saves (measured on 256 problems of 32..512): such
 // problems run in FP64
 constexpr int kMixedMin = 1024;
+constexpr int kGraphCache = 32;   // captured class pipelines kept per handle
 
 // whether a problem of half-size m runs the mixed-precision steps (and needs their FP32
 // buffers)
@@ -585,6 +594,7 @@ int ensure_workers(ps_handle h, int n) {
   while ((int)h->workers.size() < n) {
     ps_handle w = nullptr;
     if (ps_create(&w, h->wstreams[h->workers.size()]) != PS_OK) return -1;
+    w->use_graphs = h->use_graphs;
     h->workers.push_back(w);
   }
   return n;
@@ -2062,59 +2072,161 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
     q.sD[0] = sd;
     return q;
   };
-  // ---- step 1 (a3): X1 = hat C X0 (I + sum_j a_j (X0^T X0 + c_j I)^{-1})
-  scale_b(s, c.y, 2 * S, c.x0, S, d_inva, (size_t)S, nb);
-  {
-    GemmProblem pg = batched(gemm_problem(mp, mp, mp, c.x0, mp, 1, c.x0, mp, 0, c.g, mp, 1.0, 0.0,
-                                          nullptr, 0, kOutUpper), S, S, S);
-    gemm_f64(s, pg);
-    form_shifts_b(s, c.g, c.z, mp, d_c1, r, nb);
-    potrf_inv_f64(s, c.z, S, c.w, S, nullptr, mp, r * nb, c.dinfo + 1);
-    GemmProblem pn = batched(gemm_problem(mp, mp, r * mp, c.w, mp, 0, c.w, mp, 1, c.nmat, mp, 1.0,
-                                          0.0, nullptr, 0,
-                                          kAUpper | kBLower | kOutUpper | kMirror),
-                             r * S, r * S, S);
-    pn.kseg = mp;
-    pn.nseg = r;
-    pn.kscale_b = d_a1;
-    gemm_f64(s, pn);
-    GemmProblem px = batched(gemm_problem(mp, mp, mp, c.x0, mp, 0, c.nmat, mp, 0, c.x1, mp, 1.0,
-                                          1.0, c.x0, mp, 0),
-                             S, S, S);
-    px.alpha_b = d_chat1;
-    px.beta_b = d_chat1;
-    gemm_f64(s, px);
-  }
-  // ---- step 2 (a3) by the series: X2 = hat C X1 T(Delta), Delta = X1^T X1 - I
-  {
-    GemmProblem pg = batched(gemm_problem(mp, mp, mp, c.x1, mp, 1, c.x1, mp, 0, c.g, mp, 1.0, 0.0,
-                                          nullptr, 0, kOutUpper | kMirror), S, S, S);
-    gemm_f64(s, pg);
-    axpb_identity_b(s, c.g, c.g, d_one, d_mone, mp, nb);   // Delta
-    double* T = c.nmat;
-    double* T2 = c.t1;
-    if (P == 1) {
-      axpb_identity_b(s, c.g, T, d_zero, d_h(0), mp, nb);   // T = (1 + gam_0) I
-    } else {
-      axpb_identity_b(s, c.g, T, d_h(P - 1), d_h(P - 2), mp, nb);
-      for (int q = P - 3; q >= 0; --q) {
-        GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.g, mp, 0, T, mp, 0, T2, mp, 1.0, 0.0,
-                                              nullptr, 0, kOutUpper | kMirror),
-                                 S, S, S);   // symmetric (Delta and T commute)
-        gemm_f64(s, ph);
-        axpb_identity_b(s, T2, T, d_one, d_h(q), mp, nb);
-      }
+  // ---- steps 1 and 2, the stopping-test norms, bases and decoupling: launches only (the
+  // coefficients are device arrays), captured once per class key as a graph and replayed
+  auto body = [&]() {
+    // ---- step 1 (a3): X1 = hat C X0 (I + sum_j a_j (X0^T X0 + c_j I)^{-1})
+    scale_b(s, c.y, 2 * S, c.x0, S, d_inva, (size_t)S, nb);
+    {
+      GemmProblem pg = batched(gemm_problem(mp, mp, mp, c.x0, mp, 1, c.x0, mp, 0, c.g, mp, 1.0, 0.0,
+                                            nullptr, 0, kOutUpper), S, S, S);
+      gemm_f64(s, pg);
+      form_shifts_b(s, c.g, c.z, mp, d_c1, r, nb);
+      potrf_inv_f64(s, c.z, S, c.w, S, nullptr, mp, r * nb, c.dinfo + 1);
+      GemmProblem pn = batched(gemm_problem(mp, mp, r * mp, c.w, mp, 0, c.w, mp, 1, c.nmat, mp, 1.0,
+                                            0.0, nullptr, 0,
+                                            kAUpper | kBLower | kOutUpper | kMirror),
+                               r * S, r * S, S);
+      pn.kseg = mp;
+      pn.nseg = r;
+      pn.kscale_b = d_a1;
+      gemm_f64(s, pn);
+      GemmProblem px = batched(gemm_problem(mp, mp, mp, c.x0, mp, 0, c.nmat, mp, 0, c.x1, mp, 1.0,
+                                            1.0, c.x0, mp, 0),
+                               S, S, S);
+      px.alpha_b = d_chat1;
+      px.beta_b = d_chat1;
+      gemm_f64(s, px);
     }
-    GemmProblem px = batched(gemm_problem(mp, mp, mp, c.x1, mp, 0, T, mp, 0, c.x2, mp), S, S, S);
-    px.alpha_b = d_chat2;
-    gemm_f64(s, px);
+    // ---- step 2 (a3) by the series: X2 = hat C X1 T(Delta), Delta = X1^T X1 - I
+    {
+      GemmProblem pg = batched(gemm_problem(mp, mp, mp, c.x1, mp, 1, c.x1, mp, 0, c.g, mp, 1.0, 0.0,
+                                            nullptr, 0, kOutUpper | kMirror), S, S, S);
+      gemm_f64(s, pg);
+      axpb_identity_b(s, c.g, c.g, d_one, d_mone, mp, nb);   // Delta
+      double* T = c.nmat;
+      double* T2 = c.t1;
+      if (P == 1) {
+        axpb_identity_b(s, c.g, T, d_zero, d_h(0), mp, nb);   // T = (1 + gam_0) I
+      } else {
+        axpb_identity_b(s, c.g, T, d_h(P - 1), d_h(P - 2), mp, nb);
+        for (int q = P - 3; q >= 0; --q) {
+          GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.g, mp, 0, T, mp, 0, T2, mp, 1.0, 0.0,
+                                                nullptr, 0, kOutUpper | kMirror),
+                                   S, S, S);   // symmetric (Delta and T commute)
+          gemm_f64(s, ph);
+          axpb_identity_b(s, T2, T, d_one, d_h(q), mp, nb);
+        }
+      }
+      GemmProblem px = batched(gemm_problem(mp, mp, mp, c.x1, mp, 0, T, mp, 0, c.x2, mp), S, S, S);
+      px.alpha_b = d_chat2;
+      gemm_f64(s, px);
+    }
+    // ---- stopping test (a4) per problem: the norms now, the decision after the bases
+    diff_norms_b(s, c.x1, c.x2, (size_t)S, c.norms, nb);
+    const double* U = c.x2;
+    if (o.basis == PS_BASIS_CORE) {
+      // ---- core basis (a7, a8): Q_+ = Z R_G^{-1}, H_+ = 2 R_G^{-T} R_G^{-1}
+      GemmProblem pt = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, U, mp, 0, c.t1, mp, 1.0, 0.0,
+                                            nullptr, 0, kAUpper), 2 * S, S, S);
+      gemm_f64(s, pt);
+      GemmProblem pv = batched(gemm_problem(mp, mp, mp, c.wmk + S, mp, 1, c.t1, mp, 0, c.t2, mp, 1.0,
+                                            0.0, nullptr, 0, kALower), 2 * S, S, S);
+      gemm_f64(s, pv);
+      for (int b = 0; b < nb; ++b)
+        sym_scale_upper(s, c.t2 + b * S, c.p11 + b * S, m[idx[b]], mp, 1.0);
+      potrf_inv_f64(s, c.p11, S, c.wc, S, nullptr, mp, nb, c.dinfo + 4);
+      GemmProblem pe[2];
+      pe[0] = batched(gemm_problem(mp, mp, mp, c.t1, mp, 0, c.wc, mp, 0, c.t2, mp, 1.0, 0.0, nullptr,
+                                   0, kBUpper), S, S, S);
+      pe[1] = batched(gemm_problem(mp, mp, mp, c.wmk + S, mp, 0, c.wc, mp, 0, c.s12, mp, 1.0, 0.0,
+                                   nullptr, 0, kAUpper | kBUpper), 2 * S, S, S);
+      gemm_f64(s, pe, 2);
+      for (int b = 0; b < nb; ++b)   // (sum_diff_scaled takes the matrix edge, not a length)
+        sum_diff_scaled(s, c.t2 + b * S, c.s12 + b * S, c.top + b * S, c.qbot + b * S, M_SQRT1_2,
+                        mp);
+      GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.wc, mp, 1, c.wc, mp, 0, c.hp, mp, 2.0, 0.0,
+                                            nullptr, 0, kALower | kBUpper | kOutUpper | kMirror),
+                               S, S, S);
+      gemm_f64(s, ph);
+    } else {
+      // ---- blocks of sign(H) (a6): S12 = W_M U R_K, S21 = R_M^T U W_K^T (S21 in p11 until
+      // the sign blocks are formed; A_s, B_s in the first matrices of z and w, free since
+      // step 1)
+      double* as = c.z;
+      double* bs = c.w;
+      GemmProblem pg[2];
+      pg[0] = batched(gemm_problem(mp, mp, mp, U, mp, 0, c.mk + S, mp, 0, c.t1, mp, 1.0, 0.0,
+                                   nullptr, 0, kBUpper), S, 2 * S, S);
+      pg[1] = batched(gemm_problem(mp, mp, mp, U, mp, 0, c.wmk + S, mp, 1, c.t2, mp, 1.0, 0.0,
+                                   nullptr, 0, kBLower), S, 2 * S, S);
+      gemm_f64(s, pg, 2);
+      pg[0] = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, c.t1, mp, 0, c.s12, mp, 1.0, 0.0,
+                                   nullptr, 0, kAUpper), 2 * S, S, S);
+      pg[1] = batched(gemm_problem(mp, mp, mp, c.mk, mp, 1, c.t2, mp, 0, c.p11, mp, 1.0, 0.0,
+                                   nullptr, 0, kALower), 2 * S, S, S);
+      gemm_f64(s, pg, 2);
+      sign_blocks_b(s, c.s12, c.p11, as, bs, mp, nb);
+      // ---- Alg. 6 (a7): C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
+      half_shift_upper_b(s, as, c.p11, mp, nb);
+      potrf_inv_f64(s, c.p11, S, c.wc, S, nullptr, mp, nb, c.dinfo + 4);
+      GemmProblem pq = batched(gemm_problem(mp, mp, mp, bs, mp, 0, c.wc, mp, 0, c.qbot, mp, -0.5, 0.0,
+                                            nullptr, 0, kBUpper), S, S, S);
+      gemm_f64(s, pq);
+      mask_pad_b(s, c.qbot, c.mdev, mp, 1, nb);
+      double* ab = c.yt;   // [a_b, b_b] per problem (stride 2 S), free since the estimator
+      basis_mix_b(s, c.p11, c.qbot, c.top, ab, mp, nb);
+      mask_pad_b(s, ab, c.mdev, mp, 2, 2 * nb);
+      // ---- decoupling (a8): H_+ = F^T F, F = [R_M a; R_K b] (2 mp x mp, ld 2 mp; in y)
+      double* F = c.y;
+      GemmProblem pf = gemm_problem(mp, mp, mp, c.mk, mp, 0, ab, mp, 0, F, 2 * mp, 1.0, 0.0, nullptr,
+                                    0, kAUpper);
+      pf.nb1 = 2;
+      pf.sA[0] = pf.sB[0] = S;
+      pf.sC[0] = pf.sD[0] = mp;
+      pf.nb2 = nb;
+      pf.sA[1] = pf.sB[1] = pf.sC[1] = pf.sD[1] = 2 * S;
+      gemm_f64(s, pf);
+      GemmProblem ph = batched(gemm_problem(mp, mp, 2 * mp, F, 2 * mp, 1, F, 2 * mp, 0, c.hp, mp,
+                                            1.0, 0.0, nullptr, 0, kOutUpper | kMirror),
+                               2 * S, 2 * S, S);
+      gemm_f64(s, ph);
+    }
+  };
+  if (h->use_graphs) {
+    std::vector<long long> key = {(long long)(uintptr_t)base, nb, mp, r, P, o.basis};
+    for (int b = 0; b < nb; ++b) key.push_back(m[idx[b]]);
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : h->graphs)
+      if (g.key == key) exec = g.exec;
+    if (!exec) {
+      hipGraph_t graph = nullptr;
+      PS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        body();
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      PS_HIP(hipStreamEndCapture(s, &graph));
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      PS_HIP(e);
+      if ((int)h->graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        h->graphs.erase(h->graphs.begin());
+      }
+      h->graphs.push_back({key, exec});
+    }
+    PS_HIP(hipGraphLaunch(exec, s));
+  } else {
+    body();
   }
-  // ---- stopping test (a4) per problem
-  diff_norms_b(s, c.x1, c.x2, (size_t)S, c.norms, nb);
   PS_HIP(hipMemcpyAsync(pin, c.norms, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
   PS_HIP(hipMemcpyAsync(pin + 2 * nb, c.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
-  if (((int*)(pin + 2 * nb))[1] != 0) return fail_all();
+  if (((int*)(pin + 2 * nb))[1] != 0 || ((int*)(pin + 2 * nb))[4] != 0) return fail_all();
   const double tol = std::pow(std::ldexp(1.0, -53), 1.0 / (2 * r + 1));
   std::vector<char> ok(nb, 1);
   std::vector<double> change(nb);
@@ -2122,77 +2234,6 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
     change[b] = std::sqrt(pin[2 * b]) / std::sqrt(pin[2 * b + 1]);
     if (!(change[b] <= tol)) ok[b] = 0;
   }
-  const double* U = c.x2;
-  if (o.basis == PS_BASIS_CORE) {
-    // ---- core basis (a7, a8): Q_+ = Z R_G^{-1}, H_+ = 2 R_G^{-T} R_G^{-1}
-    GemmProblem pt = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, U, mp, 0, c.t1, mp, 1.0, 0.0,
-                                          nullptr, 0, kAUpper), 2 * S, S, S);
-    gemm_f64(s, pt);
-    GemmProblem pv = batched(gemm_problem(mp, mp, mp, c.wmk + S, mp, 1, c.t1, mp, 0, c.t2, mp, 1.0,
-                                          0.0, nullptr, 0, kALower), 2 * S, S, S);
-    gemm_f64(s, pv);
-    for (int b = 0; b < nb; ++b)
-      sym_scale_upper(s, c.t2 + b * S, c.p11 + b * S, m[idx[b]], mp, 1.0);
-    potrf_inv_f64(s, c.p11, S, c.wc, S, nullptr, mp, nb, c.dinfo + 4);
-    GemmProblem pe[2];
-    pe[0] = batched(gemm_problem(mp, mp, mp, c.t1, mp, 0, c.wc, mp, 0, c.t2, mp, 1.0, 0.0, nullptr,
-                                 0, kBUpper), S, S, S);
-    pe[1] = batched(gemm_problem(mp, mp, mp, c.wmk + S, mp, 0, c.wc, mp, 0, c.s12, mp, 1.0, 0.0,
-                                 nullptr, 0, kAUpper | kBUpper), 2 * S, S, S);
-    gemm_f64(s, pe, 2);
-    for (int b = 0; b < nb; ++b)   // (sum_diff_scaled takes the matrix edge, not a length)
-      sum_diff_scaled(s, c.t2 + b * S, c.s12 + b * S, c.top + b * S, c.qbot + b * S, M_SQRT1_2,
-                      mp);
-    GemmProblem ph = batched(gemm_problem(mp, mp, mp, c.wc, mp, 1, c.wc, mp, 0, c.hp, mp, 2.0, 0.0,
-                                          nullptr, 0, kALower | kBUpper | kOutUpper | kMirror),
-                             S, S, S);
-    gemm_f64(s, ph);
-  } else {
-    // ---- blocks of sign(H) (a6): S12 = W_M U R_K, S21 = R_M^T U W_K^T (S21 in p11 until
-    // the sign blocks are formed; A_s, B_s in the first matrices of z and w, free since
-    // step 1)
-    double* as = c.z;
-    double* bs = c.w;
-    GemmProblem pg[2];
-    pg[0] = batched(gemm_problem(mp, mp, mp, U, mp, 0, c.mk + S, mp, 0, c.t1, mp, 1.0, 0.0,
-                                 nullptr, 0, kBUpper), S, 2 * S, S);
-    pg[1] = batched(gemm_problem(mp, mp, mp, U, mp, 0, c.wmk + S, mp, 1, c.t2, mp, 1.0, 0.0,
-                                 nullptr, 0, kBLower), S, 2 * S, S);
-    gemm_f64(s, pg, 2);
-    pg[0] = batched(gemm_problem(mp, mp, mp, c.wmk, mp, 0, c.t1, mp, 0, c.s12, mp, 1.0, 0.0,
-                                 nullptr, 0, kAUpper), 2 * S, S, S);
-    pg[1] = batched(gemm_problem(mp, mp, mp, c.mk, mp, 1, c.t2, mp, 0, c.p11, mp, 1.0, 0.0,
-                                 nullptr, 0, kALower), 2 * S, S, S);
-    gemm_f64(s, pg, 2);
-    sign_blocks_b(s, c.s12, c.p11, as, bs, mp, nb);
-    // ---- Alg. 6 (a7): C = chol((I + A_s)/2), Q_+ = [C^T; P_{+,21} C^{-1}], P_{+,21} = -B_s/2
-    half_shift_upper_b(s, as, c.p11, mp, nb);
-    potrf_inv_f64(s, c.p11, S, c.wc, S, nullptr, mp, nb, c.dinfo + 4);
-    GemmProblem pq = batched(gemm_problem(mp, mp, mp, bs, mp, 0, c.wc, mp, 0, c.qbot, mp, -0.5, 0.0,
-                                          nullptr, 0, kBUpper), S, S, S);
-    gemm_f64(s, pq);
-    mask_pad_b(s, c.qbot, c.mdev, mp, 1, nb);
-    double* ab = c.yt;   // [a_b, b_b] per problem (stride 2 S), free since the estimator
-    basis_mix_b(s, c.p11, c.qbot, c.top, ab, mp, nb);
-    mask_pad_b(s, ab, c.mdev, mp, 2, 2 * nb);
-    // ---- decoupling (a8): H_+ = F^T F, F = [R_M a; R_K b] (2 mp x mp, ld 2 mp; in y)
-    double* F = c.y;
-    GemmProblem pf = gemm_problem(mp, mp, mp, c.mk, mp, 0, ab, mp, 0, F, 2 * mp, 1.0, 0.0, nullptr,
-                                  0, kAUpper);
-    pf.nb1 = 2;
-    pf.sA[0] = pf.sB[0] = S;
-    pf.sC[0] = pf.sD[0] = mp;
-    pf.nb2 = nb;
-    pf.sA[1] = pf.sB[1] = pf.sC[1] = pf.sD[1] = 2 * S;
-    gemm_f64(s, pf);
-    GemmProblem ph = batched(gemm_problem(mp, mp, 2 * mp, F, 2 * mp, 1, F, 2 * mp, 0, c.hp, mp,
-                                          1.0, 0.0, nullptr, 0, kOutUpper | kMirror),
-                             2 * S, 2 * S, S);
-    gemm_f64(s, ph);
-  }
-  PS_HIP(hipMemcpyAsync(pin, c.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
-  PS_HIP(hipStreamSynchronize(s));
-  if (((int*)pin)[4] != 0) return fail_all();
   for (int b = 0; b < nb; ++b) {
     const int p = idx[b];
     if (!ok[b]) {
@@ -2364,8 +2405,17 @@ int ps_destroy(ps_handle h) {
   if (h->side) (void)hipStreamSynchronize(h->side);   // borrowed: the caller's stream
   if (h->fork) (void)hipEventDestroy(h->fork);
   if (h->join) (void)hipEventDestroy(h->join);
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   for (ps_handle w : h->workers) (void)ps_destroy(w);   // their streams are the caller's
   delete h;
+  return PS_OK;
+}
+
+int ps_set_graphs(ps_handle h, int enable) {
+  if (!h) return -1;
+  if (enable != 0 && enable != 1) return -2;
+  h->use_graphs = enable != 0;
+  for (ps_handle w : h->workers) w->use_graphs = h->use_graphs;
   return PS_OK;
 }
 

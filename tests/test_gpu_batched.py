@@ -104,3 +104,30 @@ def test_batched_classes_match_single(precision, basis):
         lam = np.sort(np.sqrt(np.linalg.eigvals((a - b) @ (a + b)).real))
         w = np.sort(np.linalg.eigvalsh(0.5 * (Hs[i] + Hs[i].T).cpu().numpy()))
         assert np.max(np.abs(w - lam) / lam) < 1e-11
+
+
+@pytest.mark.parametrize("basis", ["core", "alg6"])
+def test_batched_graph_replays_match_direct_launches(basis):
+    """Classes captured as HIP graphs: the first call captures and launches, later calls
+    replay; every replay, with other device work and synchronizations in between, must
+    equal the direct launches bit for bit (the same kernels in the same order)."""
+    sizes = [70, 100, 127, 65, 200, 240, 256, 33, 40]   # classes of padded 128 and 256
+    probs = [inputs.small_dense(mi, 300 + i) for i, mi in enumerate(sizes)]
+    As = [dev(a) for a, _ in probs]
+    Bs = [dev(b) for _, b in probs]
+    print(f"[batched graphs] {basis} sizes {sizes}", flush=True)
+    api.set_graphs(False)
+    Q0, H0, i0 = api.divide_batched(As, Bs, basis=basis)
+    assert all(inf["status"] == 0 for inf in i0)
+    api.set_graphs(True)
+    try:
+        for rep in range(4):
+            Qs, Hs, infos = api.divide_batched(As, Bs, basis=basis)
+            assert all(inf["status"] == 0 for inf in infos)
+            for q0, q1, h0, h1 in zip(Q0, Qs, H0, Hs):
+                assert torch.equal(q0, q1) and torch.equal(h0, h1), rep
+            x = torch.randn(512, 512, dtype=torch.float64, device="cuda")
+            (x @ x).sum().item()                      # eager work between the replays
+            torch.cuda.synchronize()
+    finally:
+        api.set_graphs(True)
