@@ -82,6 +82,10 @@ def gpu_leg(args, a, b):
     out = {}
     for mode in args.modes:
         kw = mode_options(mode, args.r)
+        # a tuning table applies to the precision and basis it was measured on
+        t = args.tuning_table
+        api.set_gemm_tuning(t["entries"] if t and (t["precision"], t["basis"]) ==
+                            (kw["precision"], kw["basis"]) and kw["refine"] == "rr" else [])
         for _ in range(args.warmup):
             api.divide(A, B, **kw)
         torch.cuda.synchronize()
@@ -332,6 +336,31 @@ def bse_leg(args):
             "rel_eig_err": primary["rel_eig_err"], "modes": modes}
 
 
+TUNING_DIR = os.path.join(ROOT, "paper_2203_08900_amd", "tuning")
+
+
+def install_tuning(args):
+    """Load the GEMM tuning table the run asks for (args.tuning_table; the casida workload
+    installs it for the modes of its precision and basis, the others for the whole run);
+    returns its path or None."""
+    args.tuning_table = None
+    if args.tuning == "none":
+        return None
+    path = args.tuning
+    if path == "auto":
+        path = os.path.join(TUNING_DIR, f"{args.workload}.json")
+        if not os.path.exists(path):
+            return None
+        import torch
+        if json.load(open(path)).get("device") != torch.cuda.get_device_name(0):
+            return None
+    args.tuning_table = json.load(open(path))
+    if args.workload != "casida_n4096":
+        from paper_2203_08900_amd import autotune
+        autotune.load(path)
+    return os.path.relpath(path, ROOT)
+
+
 def copy_probe(nbytes: int = 512 << 20):
     """A plain streaming kernel of known size: y = -x over nbytes of FP64 (reads and
     writes nbytes each)."""
@@ -446,6 +475,10 @@ def main():
                     choices=["casida_n4096", "ill_separated_n16384", "batched_256", "eig_n128",
                              "eig_n4096", "adjoint_n2048", "general_n5000", "bse2_n2048"])
     ap.add_argument("--m", type=int, default=0, help="override the half size m")
+    ap.add_argument("--tuning", default="auto",
+                    help="GEMM tuning table (JSON of paper_2203_08900_amd.autotune) to install "
+                         "before timing; 'auto': the package's table for this workload when it "
+                         "was made on this device type; 'none': the built-in choices")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--modes",
                     default="fp64,mixed,fp64-core,mixed-core,mixed-core-norefine,mixed-ldl")
@@ -465,6 +498,7 @@ def main():
 
     if args.copy_probe:
         copy_probe()
+    tuning_used = install_tuning(args)
     exact = None
     if args.workload == "batched_256":
         print(json.dumps(batched_leg(args)), flush=True)
@@ -564,6 +598,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "rel_eig_err": rel_err.get(primary),
+        "gemm_tuning": (None if tuning_used is None else
+                        {"table": tuning_used, "precision": args.tuning_table["precision"],
+                         "basis": args.tuning_table["basis"]}),
         "rel_eig_err_before_refinement": rel_err.get("mixed-core-norefine"),
         "modes": {k: {"ms": v["ms"], "tflops": v["tflops"], "rel_eig_err": rel_err.get(k),
                       "phase_ms": [round(x, 4) for x in v["phase_ms"]],

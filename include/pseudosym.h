@@ -210,10 +210,41 @@ int ps_set_stream(ps_handle h, void* stream);
  * Returns 0, -1 (no handle) or -2 (enable not 0 or 1). */
 int ps_set_graphs(ps_handle h, int enable);
 
+/* GEMM autotuning (the benchmark spec batching: tile shapes chosen by measurement).  Every launch
+ * of the matrix-core GEMM is identified by a key hashed from the sizes, transposes, flags,
+ * batch layout and split of its problems.  A tuning entry tells the launcher which tile
+ * (64 x 64 or 128 x 128), split-K factor and schedule (stream-K or not) to use for that
+ * key; a choice a launch cannot take falls back to the nearest legal one. */
+typedef struct {
+  unsigned long long key;   /* launch key */
+  int tile;                 /* 64 or 128 */
+  int ksplit;               /* 1 (no split) .. 8 */
+  int streamk;              /* 0 or 1 */
+  float ms;                 /* autotune: time per launch of this choice */
+  float ms_default;         /* autotune: time per launch of the built-in choice */
+  int launches;             /* autotune: launches with this key in the tuned call */
+} ps_gemm_tune;
+
+/* Install a tuning table (n entries, host array, copied) on the handle and its workers;
+ * n = 0 restores the built-in choices.  Captured batched graphs are dropped.  Returns 0,
+ * -1 (no handle) or -2 (bad entry). */
+int ps_set_gemm_tuning(ps_handle h, const ps_gemm_tune* entries, int n);
+
+/* Tune the GEMM launches of one pseudosym_divide at half-size m with options opts: the
+ * division runs once with every launch logged, then every distinct launch is timed under
+ * each choice it can take (tile 64 or 128, split-K by 1 to 8, stream-K), five
+ * times after two warm-up runs, on the handle's stream; the fastest per key goes to
+ * out[0 .. min(cap, count)) with its time and the built-in choice's.  *count gets the
+ * number of distinct keys.  The trials overwrite the division's own buffers: the call
+ * returns no division result.  Workspace: ps_workspace_size(m, opts, 6).  Not for
+ * PS_BASIS_LDL (-7). */
+int ps_autotune_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                       const ps_opts* opts, ps_gemm_tune* out, int cap, int* count);
+
 /* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig and
  * sign_fwd, 3 sign_bwd, 4 divide_general, 5 the complex forms: sign_hermitian,
- * divide_hermitian, sign_bse) needs at half-size m (for kind 4: the order n of H) with
- * options o (NULL = defaults). */
+ * divide_hermitian, sign_bse, 6 autotune_divide) needs at half-size m (for kind 4: the
+ * order n of H) with options o (NULL = defaults). */
 size_t ps_workspace_size(int m, const ps_opts* o, int what);
 
 /* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the

@@ -53,6 +53,12 @@ class PsOpts(ctypes.Structure):
     ]
 
 
+class PsGemmTune(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_ulonglong), ("tile", ctypes.c_int), ("ksplit", ctypes.c_int),
+                ("streamk", ctypes.c_int), ("ms", ctypes.c_float), ("ms_default", ctypes.c_float),
+                ("launches", ctypes.c_int)]
+
+
 class PsInfo(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int),
@@ -104,7 +110,8 @@ class PsInfo(ctypes.Structure):
 EXPORTS = [
     "ps_opts_default", "ps_create", "ps_destroy", "ps_set_stream", "ps_workspace_size",
     "ps_set_workspace", "ps_workspace_size_batched", "ps_set_worker_streams",
-    "ps_zolotarev_coeffs", "ps_set_graphs", "pseudosym_sign", "pseudosym_divide",
+    "ps_zolotarev_coeffs", "ps_set_graphs", "ps_set_gemm_tuning", "ps_autotune_divide",
+    "pseudosym_sign", "pseudosym_divide",
     "pseudosym_divide_static", "pseudosym_divide_general", "pseudosym_eig",
     "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
     "pseudosym_sign_hermitian", "pseudosym_divide_hermitian", "pseudosym_sign_bse",
@@ -151,7 +158,12 @@ def load():
         lib.ps_zolotarev_coeffs.restype = ip
         lib.ps_set_graphs.argtypes = [hp, ip]
         lib.ps_set_graphs.restype = ip
+        lib.ps_set_gemm_tuning.argtypes = [hp, ctypes.POINTER(PsGemmTune), ip]
+        lib.ps_set_gemm_tuning.restype = ip
         mat = [hp, ip, vp, ip, vp, ip]
+        lib.ps_autotune_divide.argtypes = mat + [ctypes.POINTER(PsOpts), ctypes.POINTER(PsGemmTune),
+                                                 ip, ctypes.POINTER(ctypes.c_int)]
+        lib.ps_autotune_divide.restype = ip
         lib.pseudosym_sign.argtypes = mat + [vp, vp, ip, ctypes.POINTER(PsOpts), ctypes.POINTER(PsInfo)]
         lib.pseudosym_sign.restype = ip
         lib.pseudosym_divide.argtypes = mat + [vp, ip, vp, ip, ctypes.POINTER(PsOpts),
@@ -504,6 +516,42 @@ def set_graphs(enable=True, device=None):
     with torch.cuda.device(dev):
         st = _handle(dev.index, torch.cuda.current_stream(dev).cuda_stream)
     rc = lib.ps_set_graphs(st.handle, 1 if enable else 0)
+    if rc != 0:
+        raise PseudosymError(rc)
+
+
+def autotune_divide(A, B, **kw):
+    """Time every distinct GEMM launch of one pseudosym_divide under each tile, split-K and
+    schedule choice it can take.  Returns a list of dicts (key, tile, ksplit, streamk, ms,
+    ms_default, launches); no division result."""
+    opts = make_opts(**kw)
+    lib, st, A, B, m = _call_setup(A, B, opts, 6)
+    cap = 256
+    out = (PsGemmTune * cap)()
+    count = ctypes.c_int(0)
+    rc = lib.ps_autotune_divide(st.handle, m, A.data_ptr(), m, B.data_ptr(), m, ctypes.byref(opts),
+                                out, cap, ctypes.byref(count))
+    if rc != 0:
+        raise PseudosymError(rc)
+    return [{"key": f"{out[i].key:016x}", "tile": out[i].tile, "ksplit": out[i].ksplit,
+             "streamk": out[i].streamk, "ms": out[i].ms, "ms_default": out[i].ms_default,
+             "launches": out[i].launches} for i in range(min(count.value, cap))]
+
+
+def set_gemm_tuning(entries, device=None):
+    """Install a GEMM tuning table (a list of dicts as autotune_divide returns, or []) on the
+    handle of the current stream on `device` and its workers."""
+    torch = _torch()
+    lib = load()
+    dev = torch.device("cuda", device if device is not None else torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        st = _handle(dev.index, torch.cuda.current_stream(dev).cuda_stream)
+    n = len(entries)
+    arr = (PsGemmTune * max(n, 1))()
+    for i, e in enumerate(entries):
+        arr[i].key = int(e["key"], 16) if isinstance(e["key"], str) else int(e["key"])
+        arr[i].tile, arr[i].ksplit, arr[i].streamk = int(e["tile"]), int(e["ksplit"]), int(e["streamk"])
+    rc = lib.ps_set_gemm_tuning(st.handle, arr, n)
     if rc != 0:
         raise PseudosymError(rc)
 

@@ -196,6 +196,44 @@ GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, 
 
 namespace {
 thread_local KernelRecorder* g_rec = nullptr;   // per host thread (batched calls use several)
+thread_local const GemmTuneTable* g_tune = nullptr;
+thread_local const GemmChoice* g_force = nullptr;
+thread_local GemmLog* g_log = nullptr;
+
+// FNV-1a over the launch's problem shapes
+template <class T>
+unsigned long long launch_key(const GemmProblemT<T>* probs, int count) {
+  unsigned long long h = 1469598103934665603ull;
+  auto mix = [&](long long v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(sizeof(T));
+  mix(count);
+  for (int q = 0; q < count; ++q) {
+    const GemmProblemT<T>& p = probs[q];
+    for (long long v : {(long long)p.M, (long long)p.N, (long long)p.K, (long long)p.flags,
+                        (long long)p.tA, (long long)p.tB, (long long)p.nb1, (long long)p.nb2,
+                        (long long)p.kseg, (long long)p.nseg, (long long)p.ksplit,
+                        (long long)(p.alpha_b != nullptr), (long long)(p.beta_b != nullptr),
+                        (long long)(p.beta != 0.0), (long long)(p.ws_slots > 0)})
+      mix(v);
+  }
+  return h;
+}
+
+void log_launch(const GemmProblemT<double>* probs, int count, unsigned long long key) {
+  g_log->keys.push_back(key);
+  g_log->p64.emplace_back(probs, probs + count);
+  g_log->p32.emplace_back();
+}
+void log_launch(const GemmProblemT<float>* probs, int count, unsigned long long key) {
+  g_log->keys.push_back(key);
+  g_log->p64.emplace_back();
+  g_log->p32.emplace_back(probs, probs + count);
+}
 
 template <class T, int BM, int BN, int WM, int WN>
 void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
@@ -335,6 +373,10 @@ bool launch_streamk(hipStream_t s, const GemmProblemT<T>* probs, int count) {
 }  // namespace
 
 void kernel_set_recorder(KernelRecorder* r) { g_rec = r; }
+void gemm_set_tuning(const GemmTuneTable* t) { g_tune = t; }
+const GemmTuneTable* gemm_get_tuning() { return g_tune; }
+void gemm_set_force(const GemmChoice* c) { g_force = c; }
+void gemm_set_log(GemmLog* log) { g_log = log; }
 KernelRecorder* kernel_recorder() { return g_rec; }
 
 int krec_begin(hipStream_t s) {
@@ -452,6 +494,28 @@ void gemm_any(hipStream_t s, const GemmProblemT<T>* probs, int count) {
     skew = std::max(skew, na + nb);
   }
   const long long skew_max = skew == 2 ? 2048 : (skew == 1 ? 512 : 0);
+  const unsigned long long key = launch_key(probs, count);
+  if (g_log) log_launch(probs, count, key);
+  const GemmChoice* c = g_force;
+  if (!c && g_tune)
+    for (size_t i = 0; i < g_tune->keys.size(); ++i)
+      if (g_tune->keys[i] == key) c = &g_tune->choices[i];
+  if (c) {   // a tuned (or, while tuning, a trial) choice, made legal per problem
+    GemmProblemT<T> ps[kMaxGroup];
+    for (int q = 0; q < count; ++q) {
+      ps[q] = probs[q];
+      const GemmProblemT<T>& p = probs[q];
+      const bool can_split = p.nb1 * p.nb2 == 1 && p.ws && p.ws_slots >= c->ksplit &&
+                             !p.alpha_b && !p.beta_b && p.K / BK >= 4 * c->ksplit;
+      ps[q].ksplit = (c->ksplit > 1 && can_split) ? c->ksplit : (c->ksplit > 1 ? p.ksplit : 1);
+    }
+    if (c->streamk && big && launch_streamk<T>(s, ps, count)) return;
+    if (c->tile == 128 && big)
+      launch_group<T, 128, 128, 4, 4>(s, ps, count);
+    else
+      launch_group<T, 64, 64, 2, 2>(s, ps, count);
+    return;
+  }
   if (big && launch_streamk<T>(s, probs, count)) return;
   if (big && tiles128 >= 256 && tiles128 >= skew_max)
     launch_group<T, 128, 128, 4, 4>(s, probs, count);

@@ -60,6 +60,7 @@ struct ps_handle_s {
   };
   std::vector<GraphEntry> graphs;
   bool use_graphs = true;
+  ps::GemmTuneTable tuning;   // ps_set_gemm_tuning (empty: the built-in heuristic)
 };
 
 namespace ps {
@@ -595,6 +596,7 @@ int ensure_workers(ps_handle h, int n) {
     ps_handle w = nullptr;
     if (ps_create(&w, h->wstreams[h->workers.size()]) != PS_OK) return -1;
     w->use_graphs = h->use_graphs;
+    w->tuning = h->tuning;
     h->workers.push_back(w);
   }
   return n;
@@ -1304,6 +1306,146 @@ int run_hermitian(ps_handle h, int m, const double* A, int lda, const double* B,
   return rc;
 }
 
+// ---------------------------------------------------------------- GEMM autotuning
+// One division with every GEMM launch logged (the built-in choices), then each distinct
+// launch timed again under every choice it can take: 64 or 128 tiles, split-K by 1 to 8,
+// and the stream-K schedule.  The trials rerun the logged launches
+// on the division's own buffers (their contents are then garbage, which the timing does
+// not depend on).  Workspace: the division's outputs, then its own.
+size_t tune_bytes(int m, const ps_opts& o) {
+  const size_t outs = (size_t)3 * m * m * sizeof(double);
+  return (outs + kAlign - 1) / kAlign * kAlign + workspace_bytes(m, o, 1);
+}
+
+int run_autotune(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                 const ps_opts& o, ps_gemm_tune* out, int cap, int* count) {
+  hipStream_t s = h->stream;
+  char* base = workspace_base(h, tune_bytes(m, o));
+  if (!base) return PS_NO_WORKSPACE;
+  double* Qp = reinterpret_cast<double*>(base);
+  double* Hp = Qp + (size_t)2 * m * m;
+  char* ws = base + ((size_t)3 * m * m * sizeof(double) + kAlign - 1) / kAlign * kAlign;
+  GemmLog log;
+  const GemmTuneTable* prev = gemm_get_tuning();
+  gemm_set_tuning(nullptr);
+  gemm_set_log(&log);
+  ps_info inf{};
+  int rc;
+  try {
+    rc = run(h, m, A, lda, B, ldb, Qp, 2 * m, Hp, m, o, &inf, 1, ws);
+  } catch (...) {
+    gemm_set_log(nullptr);
+    gemm_set_tuning(prev);
+    throw;
+  }
+  gemm_set_log(nullptr);
+  if (rc != PS_OK) {
+    gemm_set_tuning(prev);
+    return rc;
+  }
+  if (h->side) PS_HIP(hipStreamSynchronize(h->side));
+  PS_HIP(hipStreamSynchronize(s));
+  // distinct launches: first occurrence and count
+  std::vector<int> first;
+  std::vector<int> times;
+  for (size_t i = 0; i < log.keys.size(); ++i) {
+    int f = -1;
+    for (size_t j = 0; j < first.size(); ++j)
+      if (log.keys[first[j]] == log.keys[i]) f = (int)j;
+    if (f < 0) {
+      first.push_back((int)i);
+      times.push_back(1);
+    } else {
+      ++times[f];
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PS_HIP(hipEventCreate(&e0));
+  PS_HIP(hipEventCreate(&e1));
+  auto trial = [&](int li, const GemmChoice* c) -> float {
+    gemm_set_force(c);
+    auto launch = [&] {
+      if (!log.p64[li].empty())
+        gemm_f64(s, log.p64[li].data(), (int)log.p64[li].size());
+      else
+        gemm_f32(s, log.p32[li].data(), (int)log.p32[li].size());
+    };
+    constexpr int kReps = 5;
+    launch();
+    launch();
+    PS_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < kReps; ++r) launch();
+    PS_HIP(hipEventRecord(e1, s));
+    PS_HIP(hipEventSynchronize(e1));
+    gemm_set_force(nullptr);
+    float ms = 0.f;
+    PS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms / kReps;
+  };
+  int n = 0;
+  try {
+    for (size_t u = 0; u < first.size(); ++u) {
+      const int li = first[u];
+      // what the launch can take
+      bool big = true, single = true, split_ok = true, ws_any = false;
+      int kmin = 1 << 30;
+      auto scan = [&](const auto& v) {
+        single = v.size() == 1;
+        for (const auto& p : v) {
+          if (p.M % 128 || p.N % 128 || std::min(p.M, p.N) < 512) big = false;
+          if (p.nb1 * p.nb2 != 1 || !p.ws || p.alpha_b || p.beta_b) split_ok = false;
+          if (p.ws && p.ws_slots > 0) ws_any = true;
+          kmin = std::min(kmin, p.K / 32);
+        }
+      };
+      if (!log.p64[li].empty()) scan(log.p64[li]);
+      else scan(log.p32[li]);
+      const float t_default = trial(li, nullptr);
+      GemmChoice best{0, 0, 0};
+      float t_best = 0.f;
+      bool have = false;
+      for (int tile : {64, 128}) {
+        if (tile == 128 && !big) continue;
+        for (int k = 1; k <= kMaxSplit; ++k) {
+          if (k > 1 && (!single || !split_ok || kmin < 4 * k)) continue;
+          for (int sk : {0, 1}) {
+            if (sk && (tile != 128 || !ws_any || k != 1)) continue;
+            const GemmChoice c{tile, k, sk};
+            const float t = trial(li, &c);
+            if (!have || t < t_best) {
+              best = c;
+              t_best = t;
+              have = true;
+            }
+          }
+        }
+      }
+      if (n < cap && out) {
+        ps_gemm_tune& e = out[n];
+        e.key = log.keys[li];
+        e.tile = best.tile;
+        e.ksplit = best.ksplit;
+        e.streamk = best.streamk;
+        e.ms = t_best;
+        e.ms_default = t_default;
+        e.launches = times[u];
+      }
+      ++n;
+    }
+  } catch (...) {
+    gemm_set_force(nullptr);
+    gemm_set_tuning(prev);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  gemm_set_tuning(prev);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (count) *count = n;
+  return PS_OK;
+}
+
 // ---------------------------------------------------------------- eigen-decomposition
 // Leaves of the recursion: subproblems of at most this size go to the Jacobi kernel.
 constexpr int kLeaf = 64;
@@ -1790,6 +1932,12 @@ int check_common(ps_handle h, int m, const double* A, int lda, const double* B, 
 
 template <class F>
 int guarded(ps_handle h, F&& f) {
+  // the handle's GEMM tuning table for the launches of this call on this host thread
+  struct TuneScope {
+    const GemmTuneTable* prev;
+    explicit TuneScope(const GemmTuneTable* t) : prev(gemm_get_tuning()) { gemm_set_tuning(t); }
+    ~TuneScope() { gemm_set_tuning(prev); }
+  } scope(h->tuning.keys.empty() ? nullptr : &h->tuning);
   try {
     int dev = 0;
     PS_HIP(hipGetDevice(&dev));
@@ -2419,6 +2567,30 @@ int ps_set_graphs(ps_handle h, int enable) {
   return PS_OK;
 }
 
+int ps_set_gemm_tuning(ps_handle h, const ps_gemm_tune* entries, int n) {
+  if (!h) return -1;
+  if (n < 0 || (n > 0 && !entries)) return -2;
+  ps::GemmTuneTable t;
+  for (int i = 0; i < n; ++i) {
+    const ps_gemm_tune& e = entries[i];
+    if ((e.tile != 64 && e.tile != 128) || e.ksplit < 1 || e.ksplit > ps::kMaxSplit ||
+        (e.streamk != 0 && e.streamk != 1))
+      return -2;
+    t.keys.push_back(e.key);
+    t.choices.push_back({e.tile, e.ksplit, e.streamk});
+  }
+  h->tuning = t;
+  for (ps_handle w : h->workers) w->tuning = t;
+  // captured launches follow the table in force when they were captured
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+  for (ps_handle w : h->workers) {
+    for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
+    w->graphs.clear();
+  }
+  return PS_OK;
+}
+
 int ps_set_stream(ps_handle h, void* stream) {
   if (!h) return -1;
   h->stream = (hipStream_t)stream;
@@ -2431,6 +2603,7 @@ size_t ps_workspace_size(int m, const ps_opts* o, int what) {
   if (m < 1) return 0;
   if (what == 4) return general_bytes(m, o ? *o : d);
   if (what == 5) return hermitian_bytes(m, o ? *o : d);
+  if (what == 6) return tune_bytes(m, o ? *o : d);
   if (what >= 3) return adjoint_bytes(m);
   return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : what);
 }
@@ -2598,6 +2771,20 @@ int check_complex(ps_handle h, int m, const double* A, int lda, const double* B,
             (divide && o->basis != PS_BASIS_ALG6 && o->basis != PS_BASIS_CORE)))
     return -11;
   return 0;
+}
+
+int ps_autotune_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
+                       const ps_opts* opts, ps_gemm_tune* out, int cap, int* count) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (cap < 0 || (cap > 0 && !out)) return -8;
+  if (opts && opts->basis == PS_BASIS_LDL) return -7;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  o.max_steps = 0;
+  o.timing = 0;
+  return guarded(h, [&] { return run_autotune(h, m, A, lda, B, ldb, o, out, cap, count); });
 }
 
 int pseudosym_sign_hermitian(ps_handle h, int m, const double* A, int lda, const double* B,

@@ -96,6 +96,33 @@ GemmProblemF gemm_problem(int M, int N, int K, const float* A, int lda, int tA, 
                           double beta = 0.0, const float* C = nullptr, int ldc = 0,
                           int flags = 0);
 
+// Autotuning of the GEMM launches.  A launch is identified by a key hashed from the
+// sizes, transposes, flags, batch layout and split of its problems (not their pointers).
+// A choice names the tile (64 or 128), a split-K factor (1: none) and whether to take the
+// stream-K schedule; a choice that a launch cannot take (large tiles on a shape that is
+// not a multiple of 128 of at least 512, a split without room for the partial tiles or on
+// a batch) falls back to the legal one nearest to it.  All three hooks are per host
+// thread: a table consulted by every launch, a choice forced on every launch (the
+// tuner's trials), and a log of the launches issued (the tuner's inventory).
+struct GemmChoice {
+  int tile;
+  int ksplit;
+  int streamk;
+};
+struct GemmTuneTable {
+  std::vector<unsigned long long> keys;
+  std::vector<GemmChoice> choices;
+};
+struct GemmLog {
+  std::vector<unsigned long long> keys;
+  std::vector<std::vector<GemmProblem>> p64;   // per logged launch (empty for FP32)
+  std::vector<std::vector<GemmProblemF>> p32;
+};
+void gemm_set_tuning(const GemmTuneTable* t);
+const GemmTuneTable* gemm_get_tuning();
+void gemm_set_force(const GemmChoice* c);
+void gemm_set_log(GemmLog* log);
+
 // Optional per-launch timing of the matrix-core kernels: when a recorder is set (for the
 // calling host thread), every launch of a recorded class is bracketed by a pair of
 // events on its own stream (a GEMM's window also covers its split-K reduction) and its
