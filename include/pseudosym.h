@@ -207,7 +207,8 @@ int ps_set_stream(ps_handle h, void* stream);
  * graph and replayed when a class with the same sizes, options and workspace comes again
  * (up to 32 graphs kept per handle and worker; the runtime holds their resources until
  * ps_destroy).  enable = 1 (default) or 0 (every launch issued directly, as on the first
- * call); results are identical either way.  Applies to the handle and its workers.
+ * call); results are identical either way.  Applies to the handle and its workers, on
+ * their streams other than the legacy default (NULL) stream, which cannot be captured.
  * Returns 0, -1 (no handle) or -2 (enable not 0 or 1). */
 int ps_set_graphs(ps_handle h, int enable);
 

@@ -506,10 +506,11 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
     pn.kseg = mp;
     pn.nseg = n32;
     for (int j = 0; j < n32; ++j) pn.kscale[j] = a32[j];
-    if (n32 > 1 && n32 <= kMaxSplit) {   // the FP32 factors are no longer needed: partials there
-      pn.ksplit = n32;
-      pn.ws = b.z32;
-    }
+    // the FP32 shifted matrices are no longer needed (the factors are in w32): split-K or
+    // stream-K partials there (rr slices of S)
+    pn.ws = b.z32;
+    pn.ws_slots = b.r > 2 ? b.r : 2;
+    if (n32 > 1 && n32 <= kMaxSplit) pn.ksplit = n32;
     gemm_f32(s2, pn);
     if (s2 != s) PS_HIP(hipEventRecord(mx.join, s2));
   }
@@ -2341,7 +2342,7 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
       gemm_f64(s, ph);
     }
   };
-  if (h->use_graphs) {
+  if (h->use_graphs && s != nullptr) {   // the legacy default stream cannot be captured
     std::vector<long long> key = {(long long)(uintptr_t)base, nb, mp, r, P, o.basis};
     for (int b = 0; b < nb; ++b) key.push_back(m[idx[b]]);
     hipGraphExec_t exec = nullptr;
