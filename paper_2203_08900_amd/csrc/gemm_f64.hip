@@ -11,7 +11,7 @@ namespace ps {
 template <class T>
 struct GemmGroup {
   int count;
-  int remap;   // nonzero: spread consecutive tiles over one XCD (8 XCDs, round-robin dispatch)
+  int group;   // > 0: XCD x runs groups of `group` consecutive logical tiles (see the kernel)
   int total;
   GemmProblemT<T> p[kMaxGroup];
 };
@@ -22,11 +22,16 @@ template <class T, int BM, int BN, int WM, int WN, bool kUseC>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_mfma_kernel(GemmGroup<T> g) {
   __shared__ __attribute__((aligned(16))) T smem[2 * GemmLds<BM, BN>::ASZ + 2 * GemmLds<BM, BN>::BSZ];
   int bid = blockIdx.x;
-  if (g.remap) {
-    // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8.  Give XCD x the
-    // contiguous range of logical tiles [x * total/8, (x+1) * total/8).
-    const int per = g.total >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
+  if (g.group > 0) {
+    // dispatch is round-robin over 8 XCDs: block b runs on XCD b % 8 as that XCD's
+    // (b / 8)-th block.  Deal the logical tiles to the XCDs in groups of g.group
+    // consecutive ones (group total / 8: XCD x takes [x * total/8, (x+1) * total/8));
+    // blocks past the last whole round of groups keep their own index.
+    const int gs = g.group, full = g.total / (8 * gs) * (8 * gs);
+    if (bid < full) {
+      const int x = bid & 7, q = bid >> 3;
+      bid = ((q / gs) * 8 + x) * gs + q % gs;
+    }
   }
   int pi = 0;
   while (pi + 1 < g.count && bid >= g.p[pi + 1].tile_begin) ++pi;
@@ -235,6 +240,32 @@ void log_launch(const GemmProblemT<float>* probs, int count, unsigned long long 
   g_log->p32.emplace_back(probs, probs + count);
 }
 
+// Whether the one-range-per-XCD placement (XCD x runs logical tiles [x * total/8,
+// (x+1) * total/8)) gives every XCD within 10 % of the mean number of K steps.  Only for
+// launches whose batch entries are laid out one after another (no triangular operands
+// with a full output).
+template <class T, int BM, int BN>
+bool xcd_ranges_balanced(const GemmGroup<T>& g) {
+  const int per = g.total / 8;
+  long long wx[8] = {}, sum = 0;
+  int pi = 0;
+  for (int b = 0; b < g.total; ++b) {
+    while (pi + 1 < g.count && b >= g.p[pi + 1].tile_begin) ++pi;
+    const GemmProblemT<T>& P = g.p[pi];
+    const int tz = (b - P.tile_begin) % P.tiles_per_batch;
+    const int ks = tz / P.tiles, t = tz - ks * P.tiles;
+    int I, J, kb;
+    tile_coords<BM, BN>(P, t, I, J);
+    const long long n = (long long)tile_band<BM, BN>(P, I, J, kb) * (P.kseg > 0 ? P.nseg : 1);
+    const long long w = n * (ks + 1) / P.ksplit - n * ks / P.ksplit;
+    wx[b / per] += w;
+    sum += w;
+  }
+  for (int x = 0; x < 8; ++x)
+    if (80 * wx[x] > 11 * sum) return false;
+  return true;
+}
+
 template <class T, int BM, int BN, int WM, int WN>
 void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
   GemmGroup<T> g{};
@@ -252,11 +283,24 @@ void launch_group(hipStream_t s, const GemmProblemT<T>* probs, int count) {
   }
   if (total == 0) return;
   g.total = total;
-  bool tri_ops = false;
-  for (int q = 0; q < g.count; ++q)
-    tri_ops = tri_ops || ((g.p[q].flags & (kAUpper | kALower | kBUpper | kBLower)) &&
-                          !(g.p[q].flags & (kOutUpper | kOutLower)));
-  g.remap = (!tri_ops && total % 8 == 0 && total >= 64) ? 1 : 0;
+  // XCD placement.  Tiles of equal K take one contiguous range of tiles per XCD, so each
+  // XCD's L2 serves a compact part of the operands.  Triangular operands make the K
+  // extents differ and enumerate the tiles longest first, so such ranges can differ in
+  // work several-fold (an N = W W^T product at m = 8192 ran twice as long); they keep the
+  // ranges only while those are balanced, else groups of 4 tiles go round-robin.  With a
+  // full output they interleave batch entries and take the plain round-robin dispatch.
+  bool tri_full = false, tri_any = false;
+  for (int q = 0; q < g.count; ++q) {
+    const int f = g.p[q].flags;
+    const bool tri = f & (kAUpper | kALower | kBUpper | kBLower);
+    tri_any = tri_any || tri;
+    tri_full = tri_full || (tri && !(f & (kOutUpper | kOutLower)));
+  }
+  g.group = (total % 8 == 0 && total >= 64) ? total / 8 : 0;
+  if (tri_full)
+    g.group = 0;
+  else if (tri_any && g.group > 0 && !xcd_ranges_balanced<T, BM, BN>(g))
+    g.group = 4;
   // without any C operand (beta = 0 everywhere, or split-K partials) the tiles use the
   // variant that keeps no C registers
   bool use_c = false;
