@@ -178,6 +178,14 @@ typedef struct {
   int kclass_launches[8];
   double kclass_ms[8];
   double kclass_flops[8];
+  /* Check of the bounds behind the series form of the second step (Alg. 8 with alpha,
+   * beta as given or estimated): ||X1^T X1 - I||_2 is at most 1 - l1^2 when [beta, alpha]
+   * held the singular values of the core; the largest over the attempts of its lower
+   * estimate by power steps on the device, and the attempts whose estimate exceeded that
+   * bound (plus rounding), whose second step was then redone by factorizations and
+   * followed by a restart. */
+  double delta_norm_est;
+  int bounds_rejected;
 } ps_info;
 
 /* kernel classes of ps_info.kclass_* */

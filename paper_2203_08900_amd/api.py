@@ -87,6 +87,8 @@ class PsInfo(ctypes.Structure):
         ("kclass_launches", ctypes.c_int * 8),
         ("kclass_ms", ctypes.c_double * 8),
         ("kclass_flops", ctypes.c_double * 8),
+        ("delta_norm_est", ctypes.c_double),
+        ("bounds_rejected", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -104,6 +106,7 @@ class PsInfo(ctypes.Structure):
             "eig_clusters": self.eig_clusters,
             "kclass_launches": list(self.kclass_launches),
             "kclass_ms": list(self.kclass_ms), "kclass_flops": list(self.kclass_flops),
+            "delta_norm_est": self.delta_norm_est, "bounds_rejected": self.bounds_rejected,
         }
 
 

@@ -541,4 +541,65 @@ void sum_diff_scaled(hipStream_t s, const double* e1, const double* e2, double* 
   PS_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------- power steps on a symmetric matrix
+// Start vector of the power steps: fixed, of both signs, zero past the live size m.
+__global__ void power_start_kernel(double* v, int m, int mp) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < mp; i += gridDim.x * blockDim.x) {
+    double x = 0.0;
+    if (i < m) {
+      unsigned h = (unsigned)i * 2654435761u + 0x7f4a7c15u;
+      h ^= h >> 15;
+      h *= 0x2c1b3c6du;
+      h ^= h >> 12;
+      x = (double)(int)(h & 0xffffu) / 32768.0 - 1.0;
+    }
+    v[i] = x;
+  }
+}
+
+// y = (M - shift I) x on the live block (rows and columns below m); y is zero past m.
+// M is symmetric in full storage, so row i is column i, which one wave reads
+// contiguously (NT / 64 columns per workgroup).
+__global__ void sym_apply_kernel(const double* M, int m, int mp, double shift, const double* x,
+                                 double* y) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (i >= mp) return;
+  double acc = 0.0;
+  if (i < m) {
+    const double* col = M + (size_t)i * mp;
+    for (int j = lane; j < m; j += 64) acc += col[j] * x[j];
+  }
+  acc = warp_sum(acc);
+  if (lane == 0) y[i] = i < m ? acc - shift * x[i] : 0.0;
+}
+
+__global__ void two_norms2_kernel(const double* a, const double* b, int n, double* out2) {
+  __shared__ double sh[NT / 64];
+  double qa = 0.0, qb = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    qa += a[e] * a[e];
+    qb += b[e] * b[e];
+  }
+  const double sa = block_sum(qa, sh);
+  const double sb = block_sum(qb, sh);
+  if (threadIdx.x == 0) {
+    out2[0] = sa;
+    out2[1] = sb;
+  }
+}
+
+void sym_power_norm(hipStream_t s, const double* M, int m, int mp, double shift, int steps,
+                    double* v0, double* v1, double* out2) {
+  hipLaunchKernelGGL(power_start_kernel, dim3(blocks_for(mp)), dim3(NT), 0, s, v0, m, mp);
+  double* v[2] = {v0, v1};
+  const unsigned nb = (unsigned)((mp + NT / 64 - 1) / (NT / 64));
+  for (int k = 0; k < steps; ++k)
+    hipLaunchKernelGGL(sym_apply_kernel, dim3(nb), dim3(NT), 0, s, M, m, mp, shift, v[k & 1],
+                       v[(k + 1) & 1]);
+  hipLaunchKernelGGL(two_norms2_kernel, dim3(1), dim3(NT), 0, s, v[steps & 1],
+                     v[(steps + 1) & 1], mp, out2);
+  PS_HIP(hipGetLastError());
+}
+
 }  // namespace ps

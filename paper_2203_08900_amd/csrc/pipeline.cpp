@@ -415,16 +415,41 @@ int series_terms(const ZoloHost& co, double ell_in, double gam[kMaxSeries]) {
   return 0;
 }
 
+// Check of the bounds behind the series: power steps on Delta = X^T X - I (or on X^T X
+// with the identity subtracted on the fly) on the side stream, launched from the point
+// where the step has formed that matrix in b.g, which the rest of the step only reads.
+// The caller waits for `join` before b.g is written again.
+constexpr int kPowerSteps = 6;
+
+struct SeriesCheck {
+  hipStream_t side;   // null: run in order on the step's stream
+  hipEvent_t fork, join;
+  double* v;          // 2 mp doubles
+  double* out2;       // ||v_k||^2, ||v_{k-1}||^2
+};
+
+void launch_series_check(hipStream_t s, const Buffers& b, const SeriesCheck* chk, double shift) {
+  if (!chk) return;
+  hipStream_t t = chk->side ? chk->side : s;
+  if (t != s) {
+    PS_HIP(hipEventRecord(chk->fork, s));
+    PS_HIP(hipStreamWaitEvent(t, chk->fork, 0));
+  }
+  sym_power_norm(t, b.g, b.m, b.mp, shift, kPowerSteps, chk->v, chk->v + b.mp, chk->out2);
+  if (t != s) PS_HIP(hipEventRecord(chk->join, t));
+}
+
 // Second Zolotarev step by the series: xn = hat C x (I + sum_{p<P} gam_p Delta^p),
 // Delta = x^T x - I, evaluated by Horner's rule on the right.
 void zolo_step_series(hipStream_t s, Buffers& b, const double* x, double* xn, const ZoloHost& co,
-                      int P, const double gam[kMaxSeries]) {
+                      int P, const double gam[kMaxSeries], const SeriesCheck* chk = nullptr) {
   const int mp = b.mp;
   GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
                                 kOutUpper | kMirror);
   auto_split(pg, b.splitws);
   gemm_f64(s, pg);
   axpb_identity(s, b.g, b.g, 1.0, -1.0, mp);                 // Delta
+  launch_series_check(s, b, chk, 0.0);
   // T = (1 + gam_0) I + gam_1 Delta + ... + gam_{P-1} Delta^{P-1}
   double* T = b.nmat;
   double* T2 = b.t1;
@@ -540,15 +565,20 @@ void zolo_step_mixed(hipStream_t s, const MixedCtx& mx, Buffers& b, const double
 // FP32 rounding of the correction is damped by that factor, and
 // X2 = hat C (1 + gam_0) X + hat C X T' is formed in FP64.
 void zolo_step_series_mixed(hipStream_t s, Buffers& b, const double* x, double* xn,
-                            const ZoloHost& co, int P, const double gam[kMaxSeries]) {
+                            const ZoloHost& co, int P, const double gam[kMaxSeries],
+                            const SeriesCheck* chk = nullptr) {
   const int mp = b.mp;
   GemmProblem pg = gemm_problem(mp, mp, mp, x, mp, 1, x, mp, 0, b.g, mp, 1.0, 0.0, nullptr, 0,
                                 kOutUpper | kMirror);
   auto_split(pg, b.splitws);
   gemm_f64(s, pg);
   scale_copy(s, x, xn, co.chat * (1.0 + gam[0]), b.S);
-  if (P < 2) return;
+  if (P < 2) {
+    launch_series_check(s, b, chk, 1.0);   // b.g holds X^T X
+    return;
+  }
   axpb_identity(s, b.g, b.g, 1.0, -1.0, mp);   // Delta
+  launch_series_check(s, b, chk, 0.0);
   cvt_f64_f32(s, b.g, b.d32, b.S);
   cvt_f64_f32(s, x, b.x32, b.S);
   // inner = gam_1 I + gam_2 Delta + ... + gam_{P-1} Delta^{P-2}, then T' = Delta inner
@@ -704,7 +734,7 @@ int single_step_iterate(hipStream_t s, Buffers& b, const double* y, double alpha
 // fields of inf; on PS_OK the polar factor of y is in b.x2.  Uses b.dinfo[1..3].
 int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, double beta,
                   int r_opt, const ps_opts& o, double* pin, ps_info& inf, Timer& tm,
-                  const MixedCtx* mx = nullptr) {
+                  const MixedCtx* mx = nullptr, const MixedCtx* aux = nullptr) {
   if (o.iteration != PS_ITER_ZOLO) return single_step_iterate(s, b, y, alpha, beta, o, pin, inf, tm);
   const int mp = b.mp;
   const long long S = (long long)b.S;
@@ -746,17 +776,27 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
     // the FP32 correction is damped by ||Delta|| <= 1 - l1^2; use it only while that
     // keeps its rounding below 1e-13 (else the FP64 series)
     const bool series32 = mx && (1.0 - ell1 * ell1) * 6.0e-8 <= 1e-13;
+    // The series length rests on ||Delta|| <= 1 - l1^2, i.e. on [beta, alpha] holding the
+    // singular values of the core; beta is an estimate from below of 1/sigma_max(Y0^{-1}) or
+    // the caller's.  A few singular values outside it barely move the Frobenius stopping
+    // test, so ||Delta|| is estimated on the device while the step runs.
+    const MixedCtx* sc = aux ? aux : mx;
+    SeriesCheck chk{sc ? sc->side : nullptr, sc ? sc->fork : nullptr, sc ? sc->join : nullptr,
+                    b.pp, b.norms + 2 + 2 * 1024};
+    const SeriesCheck* pc = P > 0 ? &chk : nullptr;
     if (P > 0 && series32)
-      zolo_step_series_mixed(s, b, b.x1, b.x2, c2, P, gam);
+      zolo_step_series_mixed(s, b, b.x1, b.x2, c2, P, gam, pc);
     else if (P > 0)
-      zolo_step_series(s, b, b.x1, b.x2, c2, P, gam);
+      zolo_step_series(s, b, b.x1, b.x2, c2, P, gam, pc);
     else
       zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
     inf.shifts_fp64[1] = (P > 0) ? 0 : r_run;
+    if (pc && chk.side) PS_HIP(hipStreamWaitEvent(s, chk.join, 0));
     tm.mark(3);
     inf.steps += 2;
     diff_norms(s, b.x1, b.x2, b.S, b.norms);
     PS_HIP(hipMemcpyAsync(pin, b.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (pc) PS_HIP(hipMemcpyAsync(pin + 4, chk.out2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
     PS_HIP(hipStreamSynchronize(s));
     const int* di = (const int*)(pin + 8);
@@ -766,9 +806,38 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
       inf.failed_mask = di[1] ? di[1] : (di[7] ? di[7] : di[2]);
       break;
     }
+    // Bound violated (beyond half the bound again, rounding of X^T X, and in mixed mode
+    // the FP32 group's perturbation of X1): the series may have been cut too short, and
+    // the stopping test cannot be trusted with it.  Redo the step by factorizations (its
+    // multipliers stay positive for any singular value) and restart from X2, whose
+    // bounds are then estimated afresh.
+    bool bounds_hold = true;
+    if (pc) {
+      const double rho = pin[5] > 0.0 ? std::sqrt(pin[4] / pin[5]) : 0.0;
+      inf.delta_norm_est = std::max(inf.delta_norm_est, rho);
+      const double allowed = 1.5 * (1.0 - ell1 * ell1) + 64.0 * b.m * 0x1p-53 +
+                             (mx ? 64.0 * mx->kappa * 0x1p-24 : 0.0);
+      if (!(rho <= allowed)) {
+        bounds_hold = false;
+        inf.bounds_rejected += 1;
+        zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
+        inf.step2_terms = 0;
+        inf.shifts_fp64[1] = r_run;
+        diff_norms(s, b.x1, b.x2, b.S, b.norms);
+        PS_HIP(hipMemcpyAsync(pin, b.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+        PS_HIP(hipStreamSynchronize(s));
+        if (di[2]) {
+          status = PS_SHIFT_BREAKDOWN;
+          inf.failed_step = 2;
+          inf.failed_mask = di[2];
+          break;
+        }
+      }
+    }
     const double change = std::sqrt(pin[0]) / std::sqrt(pin[1]);
     inf.step_change = change;
-    if (change <= tol) break;
+    if (bounds_hold && change <= tol) break;
     if (attempt >= o.max_restarts) {
       status = PS_NOT_CONVERGED;
       break;
@@ -888,8 +957,8 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   // ---- Zolotarev steps with the stopping test of Alg. 8
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
   const bool mixed = mixed_arith(o, m);
-  const int status =
-      polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm, mixed ? &mxc : nullptr);
+  const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm,
+                                   mixed ? &mxc : nullptr, &mxc);
   if (status != PS_OK) {
     inf.status = status;
     tm.finish(inf.phase_ms);
@@ -1179,7 +1248,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
   // ---- sign(T) by the Zolotarev iteration with the stopping test of Alg. 8
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
   const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm,
-                                   mixed_arith(o, n) ? &mxc : nullptr);
+                                   mixed_arith(o, n) ? &mxc : nullptr, &mxc);
   if (status != PS_OK) {
     inf.status = status;
     tm.finish(inf.phase_ms);

@@ -210,6 +210,11 @@ void basis_mix(hipStream_t s, const double* c, const double* qbot, double* top_o
 void copy_out(hipStream_t s, const double* x, int ldx, double* y, int ldy, int rows,
               int cols);
 void diff_norms(hipStream_t s, const double* x1, const double* x2, size_t n, double* out2);
+// Power steps on M - shift I (M symmetric, full storage, padded size mp, live size m) from
+// a fixed start vector: out2 = (||v_k||^2, ||v_{k-1}||^2) after k = steps >= 1 products, so
+// sqrt(out2[0] / out2[1]) estimates ||M - shift I||_2 from below.  v0, v1: mp doubles each.
+void sym_power_norm(hipStream_t s, const double* M, int m, int mp, double shift, int steps,
+                    double* v0, double* v1, double* out2);
 
 // z = upper(scale (x + x^T)) on the first m rows/columns, 1 on the padded diagonal
 void sym_scale_upper(hipStream_t s, const double* x, double* z, int m, int mp, double scale);

@@ -112,6 +112,35 @@ def batched(count: int = 256, seed: int = 2):
     return [small_dense(mi, i) for i, mi in enumerate(batched_sizes(count, seed))]
 
 
+def _blocks_from_factors(qm, dm, q, mu):
+    """A, B with A + B = M = qm diag(dm) qm^T and A - B = K = M^{-1/2} q diag(mu) q^T M^{-1/2},
+    so that K M, and (A - B)(A + B), have the eigenvalues mu."""
+    mmat = _sym((qm * dm[None, :]) @ qm.T)
+    m_inv_half = _sym((qm * (dm ** -0.5)[None, :]) @ qm.T)
+    kcore = _sym((q * mu[None, :]) @ q.T)
+    k = _sym(m_inv_half @ kcore @ m_inv_half)
+    a = _sym(0.5 * (mmat + k))
+    b = _sym(0.5 * (mmat - k))
+    return a, b
+
+
+def isolated_small(m: int, seed: int, small: float = 1e-3, lo: float = 0.1, hi: float = 1.0):
+    """Blocks whose H has one positive eigenvalue `small` far below the others
+    (log-uniform in [lo, hi], ends pinned): a core with an isolated smallest singular
+    value, the case where a lower bound beta that misses it leaves a single direction
+    outside [beta, alpha].  Returns (A, B, the positive eigenvalues sorted)."""
+    rng = np.random.default_rng(seed)
+    qm = haar(rng, m)
+    dm = rng.uniform(1.0, 2.0, m)
+    lam = 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), m)
+    lam[0] = small
+    lam[1] = lo
+    lam[-1] = hi
+    q = haar(rng, m)
+    a, b = _blocks_from_factors(qm, dm, q, lam ** 2)
+    return np.ascontiguousarray(a), np.ascontiguousarray(b), np.sort(lam)
+
+
 def ill_separated(m: int, seed: int, mu_lo: float = 1e-6, mu_hi: float = 1.0,
                   return_factors: bool = False):
     """Blocks whose (A-B)(A+B) has eigenvalues exactly mu (log-uniform, ends pinned).
@@ -122,16 +151,11 @@ def ill_separated(m: int, seed: int, mu_lo: float = 1e-6, mu_hi: float = 1.0,
     rng = np.random.default_rng(seed)
     qm = haar(rng, m)
     dm = rng.uniform(1.0, 2.0, m)
-    mmat = _sym((qm * dm[None, :]) @ qm.T)
     mu = 10.0 ** rng.uniform(np.log10(mu_lo), np.log10(mu_hi), m)
     mu[0] = mu_lo
     mu[-1] = mu_hi
     q = haar(rng, m)
-    m_inv_half = _sym((qm * (dm ** -0.5)[None, :]) @ qm.T)
-    kcore = _sym((q * mu[None, :]) @ q.T)
-    k = _sym(m_inv_half @ kcore @ m_inv_half)
-    a = _sym(0.5 * (mmat + k))
-    b = _sym(0.5 * (mmat - k))
+    a, b = _blocks_from_factors(qm, dm, q, mu)
     if return_factors:
         return (np.ascontiguousarray(a), np.ascontiguousarray(b), np.sort(mu),
                 (qm, dm, q, mu.copy()))

@@ -190,6 +190,49 @@ def test_restart_path():
     assert rel(SA.cpu().numpy(), s[:48, :48]) < 1e-11
 
 
+def test_misplaced_beta_caught_on_device():
+    """beta misses an isolated smallest eigenvalue (1e-3 against the others in [0.1, 1]).
+    The core iterates are orthogonal up to their singular values, so after two steps that
+    single direction (at 0.84) moves the Frobenius stopping test by only ~0.05 < u^(1/17);
+    the device estimate of ||X1^T X1 - I|| (~0.99 against 1 - l1^2 ~ 2e-9) rejects the
+    series and restarts from X2, and the result is sign(H).  (The oracle iterates on H
+    itself, whose eigenvector scaling makes its stopping test restart here as well.)"""
+    m = 256
+    a, b, lam = inputs.isolated_small(m, 3)
+    assert lam[0] == 1e-3 and lam[1] == 0.1
+    al, be = 1.01 * lam[-1], 0.99 * lam[1]
+    print(f"[misplaced beta] m={m} alpha={al} beta={be}", flush=True)
+    h = sg.casida_matrix(a, b)
+    sigma = sg.casida_sigma(m)
+    s = sg.sign_definition(h, sigma)
+    SA, SB, info = api.sign(dev(a), dev(b), alpha=al, beta=be)
+    assert info["status"] == 0
+    assert info["bounds_rejected"] >= 1 and info["restarts"] >= 1
+    assert info["delta_norm_est"] > 0.5
+    assert rel(SA.cpu().numpy(), s[:m, :m]) < 1e-11
+    assert np.abs(SB.cpu().numpy() - s[:m, m:]).max() < 1e-11 * np.abs(s).max()
+    # with bounds that hold, the check stays quiet and the series is kept
+    _, _, ok = api.sign(dev(a), dev(b), alpha=al, beta=0.99 * lam[0])
+    assert ok["bounds_rejected"] == 0 and ok["restarts"] == 0 and ok["step2_terms"] > 0
+    assert ok["delta_norm_est"] <= 1.0 - ok["ell"][1] ** 2 + 1e-12
+
+
+def test_misplaced_beta_caught_mixed():
+    """The same check on the mixed path (FP32 shift group, padded size 1024 and up):
+    H_+ has the construction's eigenvalues although beta misses the smallest one."""
+    m = 1100
+    a, b, lam = inputs.isolated_small(m, 4)
+    al, be = 1.01 * lam[-1], 0.99 * lam[1]
+    print(f"[misplaced beta, mixed] m={m}", flush=True)
+    _, Hp, info = api.divide(dev(a), dev(b), precision="mixed", basis="core", alpha=al,
+                             beta=be)
+    assert info["status"] == 0 and info["shifts_fp64"][0] < info["r"]
+    assert info["bounds_rejected"] >= 1 and info["restarts"] >= 1
+    Hh = Hp.cpu().numpy()
+    w = np.sort(np.linalg.eigvalsh(0.5 * (Hh + Hh.T)))
+    assert np.max(np.abs(w - lam) / lam) < 1e-9
+
+
 def test_bad_arguments():
     a, b = inputs.small_dense(8, 1)
     with pytest.raises(api.PseudosymError):
