@@ -559,18 +559,36 @@ __global__ void power_start_kernel(double* v, int m, int mp) {
 
 // y = (M - shift I) x on the live block (rows and columns below m); y is zero past m.
 // M is symmetric in full storage, so row i is column i, which one wave reads
-// contiguously (NT / 64 columns per workgroup).
+// contiguously as 16-byte vectors, eight in flight per lane (NT / 64 columns per
+// workgroup).  x is zero past m, so whole columns are read (padded entries of M are
+// finite).
 __global__ void sym_apply_kernel(const double* M, int m, int mp, double shift, const double* x,
                                  double* y) {
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (i >= mp) return;
-  double acc = 0.0;
+  double acc0 = 0.0, acc1 = 0.0;
   if (i < m) {
-    const double* col = M + (size_t)i * mp;
-    for (int j = lane; j < m; j += 64) acc += col[j] * x[j];
+    const double2* Mc = reinterpret_cast<const double2*>(M + (size_t)i * mp);
+    const double2* X = reinterpret_cast<const double2*>(x);
+    const int n2 = mp / 2;
+    for (int base = 0; base < n2; base += 64 * U) {
+      double2 a[U], v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = base + lane + 64 * u;
+        a[u] = j < n2 ? Mc[j] : double2{0.0, 0.0};
+        v[u] = j < n2 ? X[j] : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc0 += a[u].x * v[u].x;
+        acc1 += a[u].y * v[u].y;
+      }
+    }
   }
-  acc = warp_sum(acc);
+  const double acc = warp_sum(acc0 + acc1);
   if (lane == 0) y[i] = i < m ? acc - shift * x[i] : 0.0;
 }
 
