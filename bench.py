@@ -167,8 +167,20 @@ def batched_leg(args):
             lam = np.sort(np.sqrt(np.linalg.eigvals((a - b) @ (a + b)).real))
             w = np.sort(np.linalg.eigvalsh(0.5 * (Hs[i] + Hs[i].T).cpu().numpy()))
             err = max(err, float(np.max(np.abs(w - lam) / lam)))
+        # instrumented pass: per-class kernel times (the class pipelines then run without
+        # graphs; each reports its classes in its first problem's record)
+        nk = len(api.KERNEL_CLASSES)
+        kc = {"launches": [0] * nk, "ms": [0.0] * nk, "flops": [0.0] * nk}
+        for _ in range(args.steps):
+            _, _, tinfos = api.divide_batched(As, Bs, timing=2, **kw)
+            for ti in tinfos:
+                for c in range(nk):
+                    kc["launches"][c] += ti["kclass_launches"][c]
+                    kc["ms"][c] += ti["kclass_ms"][c]
+                    kc["flops"][c] += ti["kclass_flops"][c]
+        torch.cuda.synchronize()
         out[mode] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "ms_one_at_a_time": ms_seq,
-                     "rel_eig_err_sampled": err}
+                     "rel_eig_err_sampled": err, "kclass": kc}
     primary = next((k for k in ("mixed-core", "mixed", "fp64-core", "fp64") if k in out),
                    args.modes[0])
     return {"metric": "batched sign-fn+divide, 256 problems n_i in {64..1024}", "value":
@@ -178,7 +190,9 @@ def batched_leg(args):
             "data": "synthetic", "config": {"workload": "batched_256: m_i uniform over {32..512} "
                                             "(seed 2), small_dense(m_i, i) blocks",
                                             "problems": 256, "precision": primary},
-            "modes": out}
+            # per-class times are summed over the worker streams, which run at once
+            "roofline": roofline(out[primary]["kclass"], args.steps, out[primary]["ms"]),
+            "modes": {k: {q: v for q, v in e.items() if q != "kclass"} for k, e in out.items()}}
 
 
 def _timed(fn, steps, warmup):
@@ -392,6 +406,35 @@ TRAFFIC_PROFILES = {
 CLASS_DTYPE = ["f64", "f64", "f32", "f64", "f64", "f32"]
 
 
+def roofline(kc, steps, step_ms, traffic=None):
+    """The roofline object of a step from per-class kernel sums over `steps` instrumented
+    steps (launches, ms, algorithmic flops per class): every class's achieved rate against
+    its peak, and the class with the largest summed time as the dominant kernel.
+    traffic(cls) gives that class's HBM bytes per launch from a committed counter
+    summary of this workload, or None."""
+    kernels = []
+    for cls, name in enumerate(api_classes()):
+        if kc["launches"][cls] == 0 or kc["ms"][cls] <= 0:
+            continue
+        ach = kc["flops"][cls] / (kc["ms"][cls] * 1e-3) / 1e12
+        peak = PEAK[CLASS_DTYPE[cls]]
+        kernels.append({"kernel": name, "launches_per_step": kc["launches"][cls] / steps,
+                        "ms_per_step": kc["ms"][cls] / steps,
+                        "avg_launch_ms": kc["ms"][cls] / kc["launches"][cls],
+                        "achieved": ach, "peak": peak, "frac": ach / peak,
+                        "share_of_step": kc["ms"][cls] / steps / step_ms})
+    if not kernels:
+        return None
+    k = max(kernels, key=lambda e: e["ms_per_step"])
+    cls = api_classes().index(k["kernel"])
+    return {"bound": "mfma", "achieved": k["achieved"], "peak": k["peak"], "unit": "TFLOP/s",
+            "frac": k["frac"], "traffic": traffic(cls) if traffic else None,
+            "kernel": k["kernel"], "launches_per_step": k["launches_per_step"],
+            "avg_launch_ms": k["avg_launch_ms"],
+            "flops_per_launch": kc["flops"][cls] / kc["launches"][cls],
+            "kernels": kernels}
+
+
 def traffic_from_profile(cls):
     """HBM bytes per launch of kernel class `cls` from the committed counter summary, or
     None when there is none or the kernel sources changed since the counters were taken."""
@@ -555,28 +598,7 @@ def main():
                 "physical_cores": c["physical_cores"],
             }
 
-    kc = res["kclass"]
-    roof, kernels = None, []
-    for cls, name in enumerate(api_classes()):
-        if kc["launches"][cls] == 0 or kc["ms"][cls] <= 0:
-            continue
-        ach = kc["flops"][cls] / (kc["ms"][cls] * 1e-3) / 1e12
-        peak = PEAK[CLASS_DTYPE[cls]]
-        kernels.append({"kernel": name, "launches_per_step": kc["launches"][cls] / args.steps,
-                        "ms_per_step": kc["ms"][cls] / args.steps,
-                        "avg_launch_ms": kc["ms"][cls] / kc["launches"][cls],
-                        "achieved": ach, "peak": peak, "frac": ach / peak,
-                        "share_of_step": kc["ms"][cls] / args.steps / res["ms"]})
-    if kernels:
-        top = max(range(len(kernels)), key=lambda i: kernels[i]["ms_per_step"])
-        k = kernels[top]
-        cls = api_classes().index(k["kernel"])
-        roof = {"bound": "mfma", "achieved": k["achieved"], "peak": k["peak"], "unit": "TFLOP/s",
-                "frac": k["frac"], "traffic": traffic_from_profile(cls),
-                "kernel": k["kernel"], "launches_per_step": k["launches_per_step"],
-                "avg_launch_ms": k["avg_launch_ms"],
-                "flops_per_launch": kc["flops"][cls] / kc["launches"][cls],
-                "kernels": kernels}
+    roof = roofline(res["kclass"], args.steps, res["ms"], traffic_from_profile)
 
     line = {
         "metric": METRIC,

@@ -104,7 +104,8 @@ typedef struct {
   int lanczos_steps;   /* Golub-Kahan steps of the alpha/beta estimator (>= 4)   */
   int timing;          /* 1: fill info->phase_ms with per-phase GPU times;        */
                        /* 2: also time every launch of the matrix-core kernels   */
-                       /*    with events on its stream (info->kclass_*, gemm_*)  */
+                       /*    with events on its stream (info->kclass_*, gemm_*); */
+                       /*    pseudosym_divide_batched takes 2 only (see there)   */
   double alpha;        /* > 0: caller's upper bound of max|lambda(H)| (skips the  */
   double beta;         /* estimator); > 0: caller's lower bound of min|lambda(H)| */
   double mixed_kappa;  /* mixed precision: shifts whose condition number          */
@@ -418,7 +419,11 @@ int pseudosym_eig(ps_handle h, int m, const double* A, int lda, const double* B,
  * to rounding (the sums are split differently), not bit for bit; other problems run the
  * single-problem pipeline and match it exactly.  infos (host, length batch, may be NULL)
  * receives one record per problem; the return value is 0 or the status of the first
- * failing problem in index order.
+ * failing problem in index order.  opts->timing == 2: problems that run alone report
+ * their phases and kernel classes as in pseudosym_divide; a batched pipeline reports its
+ * kernel classes once, in the record of its first completed problem (its other records
+ * have none), and runs without HIP graphs for that call; other timing values are
+ * ignored.
  * Argument errors: -k as usual (k = 3..11 also when entry i of that array is invalid). */
 int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double* const* A,
                              const int* lda, const double* const* B, const int* ldb,

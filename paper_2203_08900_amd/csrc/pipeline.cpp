@@ -866,6 +866,50 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
   return status;
 }
 
+// Per-class kernel timing (opts.timing == 2): a recorder on the calling thread that uses
+// the handle's event pairs; collect() adds the recorded windows to inf once the handle's
+// stream has been synchronized.
+struct ClassTiming {
+  ps_handle h;
+  KernelRecorder rec;
+  bool on;
+  ClassTiming(ps_handle h_, bool on_) : h(h_), on(on_) {
+    if (!on) return;
+    const int cap = 1024;
+    while ((int)h->kev.size() < 2 * cap) {
+      hipEvent_t e;
+      PS_HIP(hipEventCreate(&e));
+      h->kev.push_back(e);
+    }
+    h->kflops.assign(cap, 0.0);
+    h->kcls.assign(cap, -1);
+    h->knl.assign(cap, 1);
+    rec.ev = h->kev.data();
+    rec.flops = h->kflops.data();
+    rec.cls = h->kcls.data();
+    rec.nl = h->knl.data();
+    rec.cap = cap;
+    kernel_set_recorder(&rec);
+  }
+  ~ClassTiming() {
+    if (on) kernel_set_recorder(nullptr);
+  }
+  void collect(ps_info& inf) const {
+    for (int q = 0; q < rec.n; ++q) {
+      const int c = rec.cls[q];
+      if (c < 0 || c >= kKcCount) continue;
+      float t = 0.f;
+      PS_HIP(hipEventElapsedTime(&t, rec.ev[2 * q], rec.ev[2 * q + 1]));
+      inf.kclass_launches[c] += rec.nl[q];
+      inf.kclass_ms[c] += t;
+      inf.kclass_flops[c] += rec.flops[q];
+    }
+    inf.gemm_launches = inf.kclass_launches[kKcGemm128];
+    inf.gemm_ms = inf.kclass_ms[kKcGemm128];
+    inf.gemm_flops = inf.kclass_flops[kKcGemm128];
+  }
+};
+
 // pairs: A and B are realified complex matrices (Eq:BSE2): the polar factor is projected
 // back onto the realified form, which the mixed steps' FP32 factorizations perturb
 int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
@@ -890,29 +934,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   inf.r = r;
   Timer tm{h, o.timing != 0};
   tm.mark(-1);
-  KernelRecorder grec;
-  struct RecGuard {
-    ~RecGuard() { kernel_set_recorder(nullptr); }
-  } rec_guard;
-  if (o.timing >= 2) {
-    const int cap = 1024;
-    if ((int)h->kev.size() < 2 * cap) {
-      while ((int)h->kev.size() < 2 * cap) {
-        hipEvent_t e;
-        PS_HIP(hipEventCreate(&e));
-        h->kev.push_back(e);
-      }
-    }
-    h->kflops.assign(cap, 0.0);
-    h->kcls.assign(cap, -1);
-    h->knl.assign(cap, 1);
-    grec.ev = h->kev.data();
-    grec.flops = h->kflops.data();
-    grec.cls = h->kcls.data();
-    grec.nl = h->knl.data();
-    grec.cap = cap;
-    kernel_set_recorder(&grec);
-  }
+  const ClassTiming ktime(h, o.timing >= 2);
 
   fill_int_zero(s, b.dinfo, 16);
   // ---- setup: M = A + B = R_M^T R_M, K = A - B = R_K^T R_K, Y0 = R_M R_K^T, Y0^{-1} = W_K^T W_M
@@ -1140,18 +1162,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     return PS_BASIS_BREAKDOWN;
   }
   tm.finish(inf.phase_ms);
-  for (int q = 0; q < grec.n; ++q) {
-    const int c = grec.cls[q];
-    if (c < 0 || c >= kKcCount) continue;
-    float t = 0.f;
-    PS_HIP(hipEventElapsedTime(&t, grec.ev[2 * q], grec.ev[2 * q + 1]));
-    inf.kclass_launches[c] += h->knl.empty() ? 1 : h->knl[q];
-    inf.kclass_ms[c] += t;
-    inf.kclass_flops[c] += grec.flops[q];
-  }
-  inf.gemm_launches = inf.kclass_launches[kKcGemm128];
-  inf.gemm_ms = inf.kclass_ms[kKcGemm128];
-  inf.gemm_flops = inf.kclass_flops[kKcGemm128];
+  ktime.collect(inf);
   inf.status = PS_OK;
   if (info) *info = inf;
   return PS_OK;
@@ -2110,7 +2121,8 @@ int class_limit(int mp, int r, size_t region) {
 // everything else, and what a class hands back, runs one problem at a time.
 std::vector<std::vector<int>> plan_batch(int batch, const int* m, const ps_opts& o,
                                          size_t region) {
-  const bool classes = o.max_steps != 1 && o.timing == 0 &&
+  // (timing: a class reports its kernel classes, not phases; see run_class)
+  const bool classes = o.max_steps != 1 &&
                        (o.precision == PS_PREC_FP64 || o.precision == PS_PREC_MIXED);
   std::vector<std::vector<int>> jobs;
   std::vector<int> order(batch);
@@ -2169,6 +2181,9 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
   carve_class(ar, c, nb, mp, rmax);
   const long long S = c.S;
   double* pin = h->pinned;
+  // timing == 2: this class's launches, reported in the record of its first problem
+  // that completes (the class then runs without graphs, whose replays record nothing)
+  const ClassTiming ktime(h, o.timing >= 2);
   auto fail_all = [&] {
     for (int p : idx) redo.push_back(p);
     return PS_OK;
@@ -2411,7 +2426,7 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
       gemm_f64(s, ph);
     }
   };
-  if (h->use_graphs && s != nullptr) {   // the legacy default stream cannot be captured
+  if (h->use_graphs && s != nullptr && !ktime.on) {   // the legacy default stream cannot be captured
     std::vector<long long> key = {(long long)(uintptr_t)base, nb, mp, r, P, o.basis};
     for (int b = 0; b < nb; ++b) key.push_back(m[idx[b]]);
     hipGraphExec_t exec = nullptr;
@@ -2480,6 +2495,12 @@ int run_class(ps_handle h, const std::vector<int>& idx, const int* m, const doub
     }
   }
   PS_HIP(hipStreamSynchronize(s));
+  if (ktime.on && infos)
+    for (int b = 0; b < nb; ++b)
+      if (ok[b]) {
+        ktime.collect(infos[idx[b]]);
+        break;
+      }
   return PS_OK;
 }
 
@@ -2947,7 +2968,7 @@ int pseudosym_divide_batched(ps_handle h, int batch, const int* m, const double*
   ps_opts_default(&o);
   if (opts) o = *opts;
   o.max_steps = 0;
-  o.timing = 0;
+  o.timing = o.timing >= 2 ? 2 : 0;
   return guarded(h, [&] {
     return run_batched(h, batch, m, A, lda, B, ldb, Qp, ldq, Hp, ldh, o, infos);
   });

@@ -131,3 +131,32 @@ def test_batched_graph_replays_match_direct_launches(basis):
             torch.cuda.synchronize()
     finally:
         api.set_graphs(True)
+
+
+def test_batched_timing_reports_each_class_once():
+    """timing == 2 on a batched call: the class pipelines run without graphs and report
+    their kernel classes in one record each (their first completed problem), problems
+    alone in their size report their own; the results equal the untimed call's bit for
+    bit (the same kernels in the same order)."""
+    sizes = [70, 100, 127, 65, 200, 240, 256, 33, 300]   # classes of 128 and 256, 300 alone
+    probs = [inputs.small_dense(mi, 400 + i) for i, mi in enumerate(sizes)]
+    As = [dev(a) for a, _ in probs]
+    Bs = [dev(b) for _, b in probs]
+    print(f"[batched timing] sizes {sizes}", flush=True)
+    Q0, H0, _ = api.divide_batched(As, Bs, basis="core")
+    Q1, H1, infos = api.divide_batched(As, Bs, basis="core", timing=2)
+    assert all(inf["status"] == 0 for inf in infos)
+    for q0, q1, h0, h1 in zip(Q0, Q1, H0, H1):
+        assert torch.equal(q0, q1) and torch.equal(h0, h1)
+    timed = [i for i, inf in enumerate(infos) if sum(inf["kclass_launches"]) > 0]
+    padded = [(mi + 63) // 64 for mi in sizes]
+    classes = {p for p in padded if padded.count(p) > 1}
+    alone = [i for i, p in enumerate(padded) if padded.count(p) == 1]
+    # one record per class plus every problem that ran alone
+    assert len(timed) == len(classes) + len(alone)
+    assert set(alone) <= set(timed)
+    assert sorted({padded[i] for i in timed if i not in alone}) == sorted(classes)
+    for i in timed:
+        inf = infos[i]
+        assert all(ms >= 0.0 for ms in inf["kclass_ms"])
+        assert sum(inf["kclass_flops"]) > 0.0
