@@ -284,6 +284,7 @@ def general_leg(args):
     H = torch.tensor(h, dtype=torch.float64, device="cuda:0")
     ms, (Qp, Qm, Hp, Hm, _, info) = _timed(lambda: api.divide_general(H, sig), args.steps,
                                            args.warmup)
+    kc = kclass_sums(lambda: api.divide_general(H, sig, timing=2)[5], args.steps)
     Hs = torch.tensor(sig[:, None] * h, dtype=torch.float64, device="cuda:0")
     bwd = float(torch.linalg.norm(Qp.T @ Hs @ Qm) / torch.linalg.norm(H))
     sweep = {}
@@ -307,6 +308,7 @@ def general_leg(args):
             "config": {"workload": f"general_sigma n={n} seed 0 kappa=1e2: H = Sigma Q D Q^T, "
                                    "random signature, D = linspace(1, kappa)", "n": n,
                        "r_plus": int(np.sum(sig > 0))},
+            "roofline": roofline(kc, args.steps, ms),
             "steps_taken": info["steps"], "restarts": info["restarts"], "backward_error": bwd,
             "backward_error_n250": sweep}
 
@@ -339,6 +341,8 @@ def bse_leg(args):
         flops = 4.0 * nominal_flops(m, info["r"], info["step2_terms"], kw["basis"])
         modes[mode] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
                        "rel_eig_err": float(np.max(np.abs(w - lam) / lam))}
+    kw = mode_options("mixed-core", args.r)
+    kc = kclass_sums(lambda: api.divide_hermitian(A, B, timing=2, **kw)[2], args.steps)
     primary = modes["mixed-core"]
     return {"metric": "sign-fn+divide time & TFLOP/s, complex Casida form (Eq:BSE2)",
             "value": primary["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -347,6 +351,7 @@ def bse_leg(args):
             "config": {"workload": f"bse2_like m={m} (n={2 * m}) seed 1: A = U diag(U[1,10]) U^H, "
                                    "B Hermitian Gaussian, ||B|| = 0.5 lambda_min(A)",
                        "n": 2 * m, "m": m, "precision": "mixed-core"},
+            "roofline": roofline(kc, args.steps, primary["ms"]),
             "rel_eig_err": primary["rel_eig_err"], "modes": modes}
 
 
@@ -404,6 +409,23 @@ TRAFFIC_PROFILES = {
     4: ("gemm_f64_64x64_traffic_casida_n4096.txt", ["gemm_f64.hip", "gemm_tile.h"]),
 }
 CLASS_DTYPE = ["f64", "f64", "f32", "f64", "f64", "f32"]
+
+
+def kclass_sums(call, steps):
+    """Per-class kernel sums (launches, ms, algorithmic flops) over `steps` calls of
+    call() -> info made with timing = 2."""
+    import torch
+    from paper_2203_08900_amd import api
+    nk = len(api.KERNEL_CLASSES)
+    kc = {"launches": [0] * nk, "ms": [0.0] * nk, "flops": [0.0] * nk}
+    for _ in range(steps):
+        ti = call()
+        for c in range(nk):
+            kc["launches"][c] += ti["kclass_launches"][c]
+            kc["ms"][c] += ti["kclass_ms"][c]
+            kc["flops"][c] += ti["kclass_flops"][c]
+    torch.cuda.synchronize()
+    return kc
 
 
 def roofline(kc, steps, step_ms, traffic=None):

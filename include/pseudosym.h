@@ -175,7 +175,8 @@ typedef struct {
                            /*   their magnitude (split without a shift)                */
   /* timing == 2, per kernel class c (PS_KC_*): launches, summed GPU time of the event
    * windows (ms) and algorithmic flops.  A Cholesky step launch counts mp^3/3 per matrix
-   * spread evenly over the mp/64 steps of its factorization. */
+   * spread evenly over the mp/64 steps of its factorization, less the updates of the
+   * outer blocks from padded size 4096 (GEMM launches, counted in their class). */
   int kclass_launches[8];
   double kclass_ms[8];
   double kclass_flops[8];

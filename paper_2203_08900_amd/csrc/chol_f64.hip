@@ -593,6 +593,12 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
     win->flops += flops;
     if (last) krec_end(st, win->slot, kcls, win->flops, win->launches);
   };
+  double outer_flops = 0.0;   // per matrix: rows [e, mp) -= K = (e - ob) outer panels
+  for (int ob = 0; ob < mp; ob += outer) {
+    const int obe = std::min(mp, ob + outer);
+    if (obe < mp) outer_flops += (double)(mp - obe) * (mp - obe) * (obe - ob);
+  }
+  const double step_flops = ((double)mp * mp * mp / 3.0 - outer_flops) / (mp / NB);
   auto step = [&](int k0, int fold, const GemmProblemT<T>* tp, int ntp) {
     const int rest = mp - k0 - NB;
     const int nt = rest > 0 ? rest / NB : 1;
@@ -637,9 +643,10 @@ void potrf_inv_t(hipStream_t s, T* z, long long sz, T* w, long long sw, int mp, 
                            sw, mp, k0, rest, nt, fold, info, t0, t1, ndiag, np, ntrail, v, sv,
                            ip);
       PS_HIP(hipGetLastError());
-      // algorithmic work of a launch: the factorization's batch mp^3 / 3 spread evenly over
-      // its mp / 64 block steps
-      rec_end(s, slot, (double)batch * mp * mp * (double)NB / 3.0, last);
+      // algorithmic work of a launch: the factorization's batch mp^3 / 3, less the outer
+      // blocks' updates (GEMM launches, counted there), spread evenly over its mp / 64
+      // block steps
+      rec_end(s, slot, (double)batch * step_flops, last);
     });
   };
   // Eight or more matrices of padded size 1024 to 4095 (no outer blocks): the trailing

@@ -1215,6 +1215,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
   inf.failed_step = -1;
   inf.r = r;
   Timer tm{h, o.timing != 0};
+  const ClassTiming ktime(h, o.timing >= 2);
   tm.mark(-1);
   fill_int_zero(s, b.dinfo, 16);
   // ---- M = Sigma H = R^T R (in mk), W = R^{-1} (in wmk)
@@ -1336,6 +1337,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
     return PS_BASIS_BREAKDOWN;
   }
   tm.finish(inf.phase_ms);
+  ktime.collect(inf);
   inf.status = PS_OK;
   if (info) *info = inf;
   return PS_OK;
