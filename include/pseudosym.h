@@ -253,10 +253,10 @@ int ps_set_gemm_tuning(ps_handle h, const ps_gemm_tune* entries, int n);
 int ps_autotune_divide(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                        const ps_opts* opts, ps_gemm_tune* out, int cap, int* count);
 
-/* Bytes of device workspace that a call of kind `what` (0 sign, 1 divide, 2 eig and
- * sign_fwd, 3 sign_bwd, 4 divide_general, 5 the complex forms: sign_hermitian,
- * divide_hermitian, sign_bse, 6 autotune_divide) needs at half-size m (for kind 4: the
- * order n of H) with options o (NULL = defaults). */
+/* Bytes of device workspace that a call of kind `what` (0 sign and sign_fwd_iter, 1 divide,
+ * 2 eig and sign_fwd, 3 sign_bwd, 4 divide_general, 5 the complex forms: sign_hermitian,
+ * divide_hermitian, sign_bse, 6 autotune_divide, 7 sign_bwd_iter) needs at half-size m
+ * (for kind 4: the order n of H) with options o (NULL = defaults). */
 size_t ps_workspace_size(int m, const ps_opts* o, int what);
 
 /* Use caller memory (device pointer, 256-byte aligned, `bytes` long) as the
@@ -451,6 +451,35 @@ int pseudosym_sign_fwd(ps_handle h, int m, const double* A, int lda, const doubl
 int pseudosym_sign_bwd(ps_handle h, int m, const double* lambda, const double* V, int ldv,
                        const double* gSA, const double* gSB, int ldg, double* gA, double* gB,
                        int ldo);
+
+/* Differentiable sign function on the iteration's own factors (no eigen-decomposition).
+ * The forward is pseudosym_sign (Alg. 8 on the core Y0 = R_M R_K^T, Sec. 4, in FP64, both
+ * steps by factorizations, no Newton-Schulz pass) that also writes into `store` (caller's
+ * device memory, 256-byte aligned, at least ps_sign_store_size(m, opts) bytes, kept by
+ * the caller until the backward): R_M, R_K, their inverses, the polar factor U, and per
+ * Zolotarev step its input X_k, the inverse Cholesky factors W_kj of X_k^T X_k + c_j I
+ * and its scalars.  The store holds 2 (1 + max_restarts) steps (max_restarts <= 3).
+ * Argument errors: -1..-9 as pseudosym_sign, -10 store null or misaligned, -11
+ * store_bytes too small, -12 options it does not take (mixed precision, another
+ * iteration, max_restarts > 3). */
+size_t ps_sign_store_size(int m, const ps_opts* opts);
+int pseudosym_sign_fwd_iter(ps_handle h, int m, const double* A, int lda, const double* B,
+                            int ldb, double* SA, double* SB, int lds, void* store,
+                            size_t store_bytes, const ps_opts* opts, ps_info* info);
+
+/* Backward of pseudosym_sign_fwd_iter: gA = dL/dA, gB = dL/dB (symmetric parts, m x m,
+ * ldo) from gSA = dL/dS_A, gSB = dL/dS_B (m x m, ldg), by reverse mode through the
+ * forward's composition with the stored factors: the sign-block products, each
+ * Zolotarev step X' = hat C X (I + sum_j a_j N_j), N_j = W_j W_j^T, whose adjoint is
+ * hat C (G (I + sum_j a_j N_j) - X (Z + Z^T)), Z = sum_j a_j N_j X^T G N_j (batched and
+ * K-segmented matrix-core products), Y0 = R_M R_K^T, the inverses, and the Cholesky
+ * factorizations (gM = sym(W Phi(R triu(gR)^T) W^T), Phi the lower triangle with its
+ * diagonal halved).  The bounds and coefficients of the forward are held fixed (sign is
+ * scale invariant; the rational approximation error of the two steps is below 1e-15).
+ * Workspace: ps_workspace_size kind 7.  Argument errors: -1 handle, -2 m, -3 store null,
+ * misaligned or not written for this m, -4/-5 gradients, -6 ldg, -7/-8 outputs, -9 ldo. */
+int pseudosym_sign_bwd_iter(ps_handle h, int m, const void* store, const double* gSA,
+                            const double* gSB, int ldg, double* gA, double* gB, int ldo);
 
 /* Human-readable name of a status code. */
 const char* ps_status_string(int status);

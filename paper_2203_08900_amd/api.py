@@ -117,6 +117,7 @@ EXPORTS = [
     "pseudosym_sign", "pseudosym_divide",
     "pseudosym_divide_static", "pseudosym_divide_general", "pseudosym_eig",
     "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
+    "ps_sign_store_size", "pseudosym_sign_fwd_iter", "pseudosym_sign_bwd_iter",
     "pseudosym_sign_hermitian", "pseudosym_divide_hermitian", "pseudosym_sign_bse",
     "ps_status_string",
 ]
@@ -200,6 +201,13 @@ def load():
         lib.pseudosym_sign_fwd.restype = ip
         lib.pseudosym_sign_bwd.argtypes = [hp, ip, vp, vp, ip, vp, vp, ip, vp, vp, ip]
         lib.pseudosym_sign_bwd.restype = ip
+        lib.ps_sign_store_size.argtypes = [ip, ctypes.POINTER(PsOpts)]
+        lib.ps_sign_store_size.restype = sz
+        lib.pseudosym_sign_fwd_iter.argtypes = mat + [vp, vp, ip, vp, sz, ctypes.POINTER(PsOpts),
+                                                      ctypes.POINTER(PsInfo)]
+        lib.pseudosym_sign_fwd_iter.restype = ip
+        lib.pseudosym_sign_bwd_iter.argtypes = [hp, ip, vp, vp, vp, ip, vp, vp, ip]
+        lib.pseudosym_sign_bwd_iter.restype = ip
         lib.ps_status_string.argtypes = [ip]
         lib.ps_status_string.restype = ctypes.c_char_p
         _lib = lib
@@ -608,6 +616,58 @@ def sign_bwd(lam, V, gSA, gSB):
     return gA.t(), gB.t()
 
 
+class SignStore:
+    """Device memory holding the factors pseudosym_sign_fwd_iter keeps for the backward
+    (a torch buffer and its 256-byte aligned address)."""
+
+    def __init__(self, nbytes, device, m):
+        torch = _torch()
+        self.buffer = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self.ptr = (self.buffer.data_ptr() + 255) // 256 * 256
+        self.nbytes = nbytes
+        self.m = m
+
+
+def sign_fwd_iter(A, B, raise_on_error=True, **kw):
+    """Sign blocks plus the iteration's stored factors, which the adjoint reuses (FP64).
+    Returns (SA, SB, store, info)."""
+    torch = _torch()
+    opts = make_opts(**kw)
+    lib, st, A, B, m = _call_setup(A, B, opts, 0)
+    store = SignStore(int(lib.ps_sign_store_size(m, ctypes.byref(opts))), A.device, m)
+    SA = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    SB = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    info = PsInfo()
+    rc = lib.pseudosym_sign_fwd_iter(st.handle, m, A.data_ptr(), m, B.data_ptr(), m,
+                                     SA.data_ptr(), SB.data_ptr(), m, ctypes.c_void_p(store.ptr),
+                                     ctypes.c_size_t(store.nbytes), ctypes.byref(opts),
+                                     ctypes.byref(info))
+    if rc != 0 and raise_on_error:
+        raise PseudosymError(rc, info.as_dict())
+    return SA.t(), SB.t(), store, info.as_dict() | {"rc": rc}
+
+
+def sign_bwd_iter(store, gSA, gSB):
+    """(dL/dA, dL/dB) from (dL/dSA, dL/dSB) and the forward's stored factors."""
+    torch = _torch()
+    lib = load()
+    m = store.m
+    dev = store.buffer.device
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        st = _handle(dev.index, stream.cuda_stream)
+        _ensure_workspace(st, lib, m, make_opts(), 7, dev)
+    ga_in = _colmajor(gSA.to(torch.float64))
+    gb_in = _colmajor(gSB.to(torch.float64))
+    gA = torch.empty((m, m), dtype=torch.float64, device=dev)
+    gB = torch.empty((m, m), dtype=torch.float64, device=dev)
+    rc = lib.pseudosym_sign_bwd_iter(st.handle, m, ctypes.c_void_p(store.ptr), ga_in.data_ptr(),
+                                     gb_in.data_ptr(), m, gA.data_ptr(), gB.data_ptr(), m)
+    if rc != 0:
+        raise PseudosymError(rc)
+    return gA.t(), gB.t()
+
+
 def _make_autograd():
     torch = _torch()
 
@@ -630,12 +690,34 @@ def _make_autograd():
                 gSB = torch.zeros_like(V[: V.shape[0] // 2, : V.shape[0] // 2])
             return sign_bwd(lam, V, gSA, gSB)
 
-    return PseudosymSign
+    class PseudosymSignIter(torch.autograd.Function):
+        """(A, B) -> (S_A, S_B) as PseudosymSign, with the backward by reverse mode through
+        the iteration on the factors its forward stored (no eigen-decomposition)."""
+
+        @staticmethod
+        def forward(ctx, A, B):
+            SA, SB, store, _ = sign_fwd_iter(A.detach(), B.detach())
+            ctx.store = store
+            return SA, SB
+
+        @staticmethod
+        def backward(ctx, gSA, gSB):
+            store = ctx.store
+            m = store.m
+            dev = store.buffer.device
+            if gSA is None:
+                gSA = torch.zeros((m, m), dtype=torch.float64, device=dev)
+            if gSB is None:
+                gSB = torch.zeros((m, m), dtype=torch.float64, device=dev)
+            return sign_bwd_iter(store, gSA, gSB)
+
+    return PseudosymSign, PseudosymSignIter
 
 
 def __getattr__(name):
-    if name == "PseudosymSign":
-        cls = _make_autograd()
-        globals()["PseudosymSign"] = cls
-        return cls
+    if name in ("PseudosymSign", "PseudosymSignIter"):
+        a, b = _make_autograd()
+        globals()["PseudosymSign"] = a
+        globals()["PseudosymSignIter"] = b
+        return globals()[name]
     raise AttributeError(name)

@@ -26,6 +26,7 @@ SOURCES = [
     "general.hip",
     "ldl_f64.hip",
     "hermitian.hip",
+    "adjoint_f64.hip",
     "static_scratch.hip",
     "zolo_host.cpp",
     "pipeline.cpp",

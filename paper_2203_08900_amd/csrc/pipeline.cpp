@@ -727,6 +727,46 @@ int single_step_iterate(hipStream_t s, Buffers& b, const double* y, double alpha
   return PS_OK;
 }
 
+// Factor store of the stored-factor adjoint (pseudosym_sign_fwd_iter): the forward keeps,
+// per Zolotarev step k, the step's input X_k and its inverse Cholesky factors
+// W_kj = R_kj^{-1} (X_k^T X_k + c_j I = R_kj^T R_kj), with the step's scalars, and run()
+// adds R_M, R_K, W_M, W_K and the polar factor U.  Layout in doubles: a header of
+// kStoreHeader values, then R_M, R_K, W_M, W_K, U (S each), then per step X_k (S) and
+// its r factors (r S).  Header: [0] layout version, [1] m, [2] mp, [3] r, [4] steps;
+// step k at 16 + 16 k: the scale from the previous step's output (or Y0) to X_k, hat C,
+// a_1..a_r.
+constexpr int kStoreHeader = 256;
+constexpr int kStoreMaxSteps = 8;
+constexpr double kStoreVersion = 1.0;
+
+size_t store_doubles(int mp, int r, int steps) {
+  return kStoreHeader + (size_t)(5 + steps * (1 + r)) * mp * mp;
+}
+
+struct StepStore {
+  double* base = nullptr;   // device, 256-byte aligned
+  int mp = 0, r = 0, max_steps = 0, n = 0;
+  double hdr[kStoreHeader] = {};
+  double* mats() const { return base + kStoreHeader; }   // R_M, R_K, W_M, W_K, U
+  double* x(int k) const { return mats() + (size_t)(5 + k * (1 + r)) * mp * mp; }
+  double* w(int k) const { return x(k) + (size_t)mp * mp; }
+  // before step k: its input and scalars (the factors follow with after_step)
+  void before_step(hipStream_t s, const double* xin, double scale, const ZoloHost& co) {
+    if (n >= max_steps) throw HipError{hipErrorInvalidValue, "factor store: too many steps"};
+    const size_t S = (size_t)mp * mp;
+    PS_HIP(hipMemcpyAsync(x(n), xin, S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double* h = hdr + 16 + 16 * n;
+    h[0] = scale;
+    h[1] = co.chat;
+    for (int j = 0; j < co.r; ++j) h[2 + j] = co.a[j];
+  }
+  void after_step(hipStream_t s, const double* wfac) {
+    const size_t S = (size_t)mp * mp;
+    PS_HIP(hipMemcpyAsync(w(n), wfac, (size_t)r * S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ++n;
+  }
+};
+
 // The Zolotarev iteration of Alg. 8 on the core matrix y (padded b.mp x b.mp, zero
 // padding): X0 = y / alpha, l = beta / alpha, two steps per attempt, the stopping
 // test ||X2 - X1||_F / ||X2||_F <= u^{1/(2r+1)} and restarts from X2 with bounds
@@ -734,7 +774,8 @@ int single_step_iterate(hipStream_t s, Buffers& b, const double* y, double alpha
 // fields of inf; on PS_OK the polar factor of y is in b.x2.  Uses b.dinfo[1..3].
 int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, double beta,
                   int r_opt, const ps_opts& o, double* pin, ps_info& inf, Timer& tm,
-                  const MixedCtx* mx = nullptr, const MixedCtx* aux = nullptr) {
+                  const MixedCtx* mx = nullptr, const MixedCtx* aux = nullptr,
+                  StepStore* keep = nullptr) {
   if (o.iteration != PS_ITER_ZOLO) return single_step_iterate(s, b, y, alpha, beta, o, pin, inf, tm);
   const int mp = b.mp;
   const long long S = (long long)b.S;
@@ -749,6 +790,7 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
   const double* xin = b.x0;
   int attempt = 0;
   int ell_slot = 0;
+  double in_scale = 1.0 / alpha;   // X0 from y (then from X2 on a restart)
   for (;; ++attempt) {
     ZoloHost c1, c2;
     if (zolotarev_host(ell, r_run, &c1)) return PS_NOT_CONVERGED;
@@ -761,7 +803,9 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
       zolo_step_mixed(s, *mx, b, xin, b.x1, c1, ell, b.dinfo + 1, b.dinfo + 7, &n64);
       inf.shifts_fp64[0] = n64;
     } else {
+      if (keep) keep->before_step(s, xin, in_scale, c1);
       zolo_step_f64(s, b, xin, b.x1, c1, b.dinfo + 1);
+      if (keep) keep->after_step(s, b.w);
       inf.shifts_fp64[0] = r_run;
     }
     tm.mark(2);
@@ -784,12 +828,15 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
     SeriesCheck chk{sc ? sc->side : nullptr, sc ? sc->fork : nullptr, sc ? sc->join : nullptr,
                     b.pp, b.norms + 2 + 2 * 1024};
     const SeriesCheck* pc = P > 0 ? &chk : nullptr;
-    if (P > 0 && series32)
+    if (P > 0 && series32) {
       zolo_step_series_mixed(s, b, b.x1, b.x2, c2, P, gam, pc);
-    else if (P > 0)
+    } else if (P > 0) {
       zolo_step_series(s, b, b.x1, b.x2, c2, P, gam, pc);
-    else
+    } else {
+      if (keep) keep->before_step(s, b.x1, 1.0, c2);
       zolo_step_f64(s, b, b.x1, b.x2, c2, b.dinfo + 2);
+      if (keep) keep->after_step(s, b.w);
+    }
     inf.shifts_fp64[1] = (P > 0) ? 0 : r_run;
     if (pc && chk.side) PS_HIP(hipStreamWaitEvent(s, chk.join, 0));
     tm.mark(3);
@@ -859,6 +906,7 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
                       est);
       // sigma_max(W_G) = 1 / sigma_min(X2)
       scale_copy(s, b.x2, b.x0, 1.0 / a2, b.S);
+      in_scale = 1.0 / a2;
       xin = b.x0;
       ell = std::min(b2 / a2, 1.0 - 1e-15);
     }
@@ -914,7 +962,7 @@ struct ClassTiming {
 // back onto the realified form, which the mixed steps' FP32 factorizations perturb
 int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, double* out1,
         int ld1, double* out2, int ld2, const ps_opts& o, ps_info* info, int what,
-        char* ws = nullptr, bool pairs = false) {
+        char* ws = nullptr, bool pairs = false, StepStore* keep = nullptr) {
   hipStream_t s = h->stream;
   const int r = resolve_r(o);
   // workspace: the caller's (or `ws`, which the caller has checked for size)
@@ -980,7 +1028,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
   const bool mixed = mixed_arith(o, m);
   const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm,
-                                   mixed ? &mxc : nullptr, &mxc);
+                                   mixed ? &mxc : nullptr, &mxc, keep);
   if (status != PS_OK) {
     inf.status = status;
     tm.finish(inf.phase_ms);
@@ -1101,6 +1149,20 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
     sign_blocks(s, b.s12, b.s21, b.as, b.bs, mp);
   }
   tm.mark(5);
+  if (keep) {   // R_M, R_K, W_M, W_K and U for the adjoint, then the header
+    double* st = keep->mats();
+    PS_HIP(hipMemcpyAsync(st, b.mk, 2 * S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PS_HIP(hipMemcpyAsync(st + 2 * S, b.wmk, 2 * S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PS_HIP(hipMemcpyAsync(st + 4 * S, U, S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    keep->hdr[0] = kStoreVersion;
+    keep->hdr[1] = m;
+    keep->hdr[2] = mp;
+    keep->hdr[3] = keep->r;
+    keep->hdr[4] = keep->n;
+    std::memcpy(pin, keep->hdr, kStoreHeader * sizeof(double));
+    PS_HIP(hipMemcpyAsync(keep->base, pin, kStoreHeader * sizeof(double), hipMemcpyHostToDevice, s));
+    PS_HIP(hipStreamSynchronize(s));   // the staging area is reused below
+  }
 
   if (what == 0) {
     copy_out(s, b.as, mp, out1, ld1, m, m);
@@ -1992,6 +2054,139 @@ int run_sign_bwd(ps_handle h, int m, const double* lam, const double* V, int ldv
   return PS_OK;
 }
 
+// Workspace of the stored-factor backward: 13 matrices and two stacks of r.
+size_t sign_bwd_iter_bytes(int m, int r) {
+  const size_t S = (size_t)pad_to(m) * pad_to(m);
+  return (13 + 2 * (size_t)r) * S * sizeof(double) + 16 * kAlign;
+}
+
+// Reverse mode through the forward that filled `store` (see StepStore):
+//   S12 = W_M U R_K, S21 = R_M^T U W_K^T, S_A = (sym S21 + sym S12)/2,
+//   S_B = (sym S21 - sym S12)/2;
+//   Zolotarev step X' = hat C X (I + sum_j a_j N_j), N_j = (X^T X + c_j I)^{-1} = W_j W_j^T:
+//   gX = hat C (G (I + sum_j a_j N_j) - X (Z + Z^T)), Z = sum_j a_j N_j X^T G N_j;
+//   X_k = scale_k (previous output or Y0), Y0 = R_M R_K^T, W = R^{-1}: gR -= W^T gW W^T;
+//   M = R^T R: gM = sym(W Phi(R triu(gR)^T) W^T), Phi = lower triangle, diagonal halved;
+//   gA = gM + gK, gB = gM - gK.
+int run_sign_bwd_iter(ps_handle h, int m, const double* store, const double* gSA,
+                      const double* gSB, int ldg, double* gA, double* gB, int ldo) {
+  hipStream_t s = h->stream;
+  double* pin = h->pinned;
+  PS_HIP(hipMemcpyAsync(pin, store, kStoreHeader * sizeof(double), hipMemcpyDeviceToHost, s));
+  PS_HIP(hipStreamSynchronize(s));
+  double hdr[kStoreHeader];
+  std::memcpy(hdr, pin, sizeof(hdr));
+  const int mp = pad_to(m);
+  const int r = (int)hdr[3], nsteps = (int)hdr[4];
+  if (hdr[0] != kStoreVersion || (int)hdr[1] != m || (int)hdr[2] != mp || r < 1 || r > 8 ||
+      nsteps < 1 || nsteps > kStoreMaxSteps)
+    return -3;
+  char* base = workspace_base(h, sign_bwd_iter_bytes(m, r));
+  if (!base) return PS_NO_WORKSPACE;
+  const size_t S = (size_t)mp * mp;
+  Arena a;
+  a.base = base;
+  a.dry = false;
+  double* g12 = a.take<double>(S);
+  double* g21 = a.take<double>(S);
+  double* gu1 = a.take<double>(S);
+  double* gu2 = a.take<double>(S);
+  double* G = a.take<double>(S);
+  double* t1 = a.take<double>(S);
+  double* t2 = a.take<double>(S);
+  double* Z = a.take<double>(S);
+  double* P = a.take<double>(S);
+  double* grm = a.take<double>(S);
+  double* grk = a.take<double>(S);
+  double* gmm = a.take<double>(S);
+  double* gkk = a.take<double>(S);
+  double* sa = a.take<double>((size_t)r * S);
+  double* sb = a.take<double>((size_t)r * S);
+  StepStore st;
+  st.base = const_cast<double*>(store);
+  st.mp = mp;
+  st.r = r;
+  const double* RM = st.mats();
+  const double* RK = RM + S;
+  const double* WM = RM + 2 * S;
+  const double* WK = RM + 3 * S;
+  const double* U = RM + 4 * S;
+  auto gemm = [&](const double* A_, int tA, const double* B_, int tB, double* D, double al,
+                  double be, const double* C, int flags) {
+    GemmProblem p = gemm_problem(mp, mp, mp, A_, mp, tA, B_, mp, tB, D, mp, al, be, C, mp, flags);
+    gemm_f64(s, p);
+  };
+  // batch of r products, operand A (or B) stepping through the stack
+  auto gemm_r = [&](const double* A_, long long sA, int tA, const double* B_, long long sB, int tB,
+                    double* D, int flags) {
+    GemmProblem p = gemm_problem(mp, mp, mp, A_, mp, tA, B_, mp, tB, D, mp, 1.0, 0.0, nullptr, 0,
+                                 flags);
+    p.nb1 = r;
+    p.sA[0] = sA;
+    p.sB[0] = sB;
+    p.sD[0] = (long long)S;
+    gemm_f64(s, p);
+  };
+  // sum_j a_j L_j W_j^T over the stacks (K segments of mp), plus beta C
+  auto gemm_seg = [&](const double* L, const double* W, const double* aj, double* D, double be,
+                      const double* C) {
+    GemmProblem p = gemm_problem(mp, mp, r * mp, L, mp, 0, W, mp, 1, D, mp, 1.0, be, C, mp,
+                                 kBLower);
+    p.kseg = mp;
+    p.nseg = r;
+    for (int j = 0; j < r; ++j) p.kscale[j] = aj[j];
+    gemm_f64(s, p);
+  };
+  // ---- sign blocks: g12 = dL/dS12, g21 = dL/dS21; gU = W_M^T g12 R_K^T + R_M g21 W_K
+  adj_seed(s, gSA, gSB, ldg, m, mp, g12, g21);
+  gemm(WM, 1, g12, 0, t1, 1.0, 0.0, nullptr, kALower);
+  gemm(t1, 0, RK, 1, gu1, 1.0, 0.0, nullptr, kBLower);
+  gemm(RM, 0, g21, 0, t2, 1.0, 0.0, nullptr, kAUpper);
+  gemm(t2, 0, WK, 0, gu2, 1.0, 0.0, nullptr, kBUpper);
+  sum_diff_scaled(s, gu1, gu2, G, t1, 1.0, mp);                      // G = gU
+  // ---- the Zolotarev steps in reverse order
+  for (int k = nsteps - 1; k >= 0; --k) {
+    const double* X = st.x(k);
+    const double* W = st.w(k);
+    const double* hk = hdr + 16 + 16 * k;
+    const double scale = hk[0], chat = hk[1];
+    gemm(X, 1, G, 0, t1, 1.0, 0.0, nullptr, 0);                       // X^T G
+    gemm_r(W, (long long)S, 1, t1, 0, 0, sa, kALower);                // W_j^T X^T G
+    gemm_r(sa, (long long)S, 0, W, (long long)S, 0, sb, kBUpper);     // (.) W_j
+    gemm_r(W, (long long)S, 0, sb, (long long)S, 0, sa, kAUpper);     // W_j (.)
+    gemm_seg(sa, W, hk + 2, Z, 0.0, nullptr);                         // Z = sum a_j N_j X^T G N_j
+    gemm_r(G, 0, 0, W, (long long)S, 0, sb, kBUpper);                 // G W_j
+    gemm_seg(sb, W, hk + 2, P, 1.0, G);                               // G (I + sum a_j N_j)
+    sym2(s, Z, t2, mp);                                               // Z + Z^T
+    gemm(X, 0, t2, 0, G, -scale * chat, scale * chat, P, 0);         // gradient of the input
+  }
+  // ---- Y0 = R_M R_K^T (G = dL/dY0), W = R^{-1}:
+  //   gR_M = U W_K^T g21 - gU1 U^T W_M^T + gY0 R_K,  gR_K = U^T W_M^T g12 - gU2^T U W_K^T + gY0^T R_M
+  gemm(U, 0, WK, 1, t1, 1.0, 0.0, nullptr, kBLower);
+  gemm(t1, 0, g21, 0, grm, 1.0, 0.0, nullptr, 0);
+  gemm(gu1, 0, U, 1, t1, 1.0, 0.0, nullptr, 0);
+  gemm(t1, 0, WM, 1, grm, -1.0, 1.0, grm, kBLower);
+  gemm(G, 0, RK, 0, grm, 1.0, 1.0, grm, kBUpper);
+  gemm(U, 1, WM, 1, t1, 1.0, 0.0, nullptr, kBLower);
+  gemm(t1, 0, g12, 0, grk, 1.0, 0.0, nullptr, 0);
+  gemm(gu2, 1, U, 0, t1, 1.0, 0.0, nullptr, 0);
+  gemm(t1, 0, WK, 1, grk, -1.0, 1.0, grk, kBLower);
+  gemm(G, 1, RM, 0, grk, 1.0, 1.0, grk, kBUpper);
+  // ---- Cholesky adjoints: gM = W Phi(R triu(gR)^T) W^T (symmetrized at the output)
+  auto chol_adj = [&](const double* R, const double* Wf, double* gR, double* out) {
+    zero_lower(s, gR, mp, 0, 1);
+    gemm(R, 0, gR, 1, t1, 1.0, 0.0, nullptr, kAUpper | kBLower);
+    phi_lower(s, t1, mp);
+    gemm(Wf, 0, t1, 0, t2, 1.0, 0.0, nullptr, kAUpper | kBLower);
+    gemm(t2, 0, Wf, 1, out, 1.0, 0.0, nullptr, kBLower);
+  };
+  chol_adj(RM, WM, grm, gmm);
+  chol_adj(RK, WK, grk, gkk);
+  adj_out(s, gmm, gkk, mp, m, gA, gB, ldo);
+  PS_HIP(hipStreamSynchronize(s));
+  return PS_OK;
+}
+
 int check_common(ps_handle h, int m, const double* A, int lda, const double* B, int ldb,
                  const ps_opts* o) {
   if (!h) return -1;
@@ -2697,6 +2892,7 @@ size_t ps_workspace_size(int m, const ps_opts* o, int what) {
   if (what == 4) return general_bytes(m, o ? *o : d);
   if (what == 5) return hermitian_bytes(m, o ? *o : d);
   if (what == 6) return tune_bytes(m, o ? *o : d);
+  if (what == 7) return sign_bwd_iter_bytes(m, resolve_r(o ? *o : d));
   if (what >= 3) return adjoint_bytes(m);
   return workspace_bytes(m, o ? *o : d, what < 0 ? 0 : what);
 }
@@ -2995,6 +3191,61 @@ int pseudosym_sign_fwd(ps_handle h, int m, const double* A, int lda, const doubl
   o.basis = PS_BASIS_ALG6;   // the forward returns the sign blocks of that path
   return guarded(h, [&] {
     return run_eig(h, m, A, lda, B, ldb, lambda, V, ldv, o, info, SA, SB, lds);
+  });
+}
+
+size_t ps_sign_store_size(int m, const ps_opts* opts) {
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  if (m < 1 || o.max_restarts < 0 || 2 * (1 + o.max_restarts) > kStoreMaxSteps) return 0;
+  return store_doubles(pad_to(m), resolve_r(o), 2 * (1 + o.max_restarts)) * sizeof(double);
+}
+
+int pseudosym_sign_fwd_iter(ps_handle h, int m, const double* A, int lda, const double* B,
+                            int ldb, double* SA, double* SB, int lds, void* store,
+                            size_t store_bytes, const ps_opts* opts, ps_info* info) {
+  int chk = check_common(h, m, A, lda, B, ldb, opts);
+  if (chk) return chk;
+  if (!SA) return -7;
+  if (!SB) return -8;
+  if (lds < m) return -9;
+  ps_opts o;
+  ps_opts_default(&o);
+  if (opts) o = *opts;
+  if (!store || ((uintptr_t)store % kAlign) != 0) return -10;
+  if (o.max_restarts > kStoreMaxSteps / 2 - 1) return -12;
+  if (store_bytes < ps_sign_store_size(m, &o)) return -11;
+  if (o.precision != PS_PREC_FP64 || o.iteration != PS_ITER_ZOLO) return -12;
+  // the composition the adjoint follows: FP64 Zolotarev steps by factorizations, no
+  // Newton-Schulz pass, a fixed r
+  o.max_steps = 0;
+  o.step2_series = 0;
+  if (o.refine > PS_REFINE_RR) o.refine = PS_REFINE_RR;
+  o.r = resolve_r(o);
+  StepStore keep;
+  keep.base = static_cast<double*>(store);
+  keep.mp = pad_to(m);
+  keep.r = o.r;
+  keep.max_steps = 2 * (1 + o.max_restarts);
+  return guarded(h, [&] {
+    return run(h, m, A, lda, B, ldb, SA, lds, SB, lds, o, info, 0, nullptr, false, &keep);
+  });
+}
+
+int pseudosym_sign_bwd_iter(ps_handle h, int m, const void* store, const double* gSA,
+                            const double* gSB, int ldg, double* gA, double* gB, int ldo) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (!store || ((uintptr_t)store % kAlign) != 0) return -3;
+  if (!gSA) return -4;
+  if (!gSB) return -5;
+  if (ldg < m) return -6;
+  if (!gA) return -7;
+  if (!gB) return -8;
+  if (ldo < m) return -9;
+  return guarded(h, [&] {
+    return run_sign_bwd_iter(h, m, static_cast<const double*>(store), gSA, gSB, ldg, gA, gB, ldo);
   });
 }
 

@@ -260,6 +260,15 @@ void canon_sign(hipStream_t s, double* v, int ldv, int rows, int cols);
 void jacobi_leaves(hipStream_t s, const double* b, int ld, const int* leaf_o, const int* leaf_n,
                    int nleaves, double* z, int ldz, double* lam, int* sweeps_out);
 void fill_int_zero(hipStream_t s, int* x, int n);
+// stored-factor adjoint of the sign blocks (adjoint_f64.hip): seeds g12 = sym(gA - gB)/2,
+// g21 = sym(gA + gB)/2 padded to mp; y = x + x^T; x <- tril(x) with the diagonal halved;
+// gA = sym(gm + gk), gB = sym(gm - gk) on the live block
+void adj_seed(hipStream_t s, const double* ga, const double* gb, int ldg, int m, int mp,
+              double* g12, double* g21);
+void sym2(hipStream_t s, const double* x, double* y, int mp);
+void phi_lower(hipStream_t s, double* x, int mp);
+void adj_out(hipStream_t s, const double* gm, const double* gk, int mp, int m, double* ga,
+             double* gb, int ldo);
 // adjoint of the sign function (divided-difference form in the eigenbasis)
 void build_gbar(hipStream_t s, const double* ga, const double* gb, int ldg, int m, double* g,
                 int np);

@@ -112,3 +112,75 @@ def test_config_m1024_vs_finite_differences_and_oracle():
     print("[adjoint] m=1024 oracle gradient", flush=True)
     ra, rb = gr.projector_loss_grad(a, b, w)
     assert rel(gA, ra) < 1e-10 and rel(gB, rb) < 1e-10
+
+
+# ---- the stored-factor adjoint (pseudosym_sign_fwd_iter / pseudosym_sign_bwd_iter):
+# reverse mode through the forward's own composition (Cholesky of A +- B, Y0 = R_M R_K^T,
+# the Zolotarev steps with their stored inverse factors, the sign-block products).  It
+# differentiates the rational approximation of sign that two steps reach (error below
+# 1e-15), so against the oracle's exact divided differences it agrees to rounding
+# (1e-10 allowed, as for the eigenbasis adjoint).
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (37, 1), (100, 2), (200, 5)])
+def test_sign_bwd_iter_matches_oracle(m, seed):
+    print(f"[adjoint iter] m={m}", flush=True)
+    a, b = inputs.small_dense(m, seed)
+    rng = np.random.default_rng(seed + 10)
+    g_a = rng.standard_normal((m, m))
+    g_b = rng.standard_normal((m, m))
+    SA, SB, store, info = api.sign_fwd_iter(dev(a), dev(b))
+    assert info["status"] == 0 and info["step2_terms"] == 0
+    s = sg.sign_definition(sg.casida_matrix(a, b), sg.casida_sigma(m))
+    assert rel(SA.cpu().numpy(), s[:m, :m]) < 1e-12
+    ga, gb = api.sign_bwd_iter(store, dev(g_a), dev(g_b))
+    ra, rb = gr.sign_block_grad(a, b, g_a, g_b)
+    assert rel(ga.cpu().numpy(), ra) < 1e-10 and rel(gb.cpu().numpy(), rb) < 1e-10
+
+
+def test_sign_bwd_iter_through_a_restart():
+    """An overestimated beta makes the stopping test restart: the store then holds four
+    steps joined by the rescaling X0 = X2 / alpha_2, and the gradient is still the
+    oracle's."""
+    m = 48
+    a, b = inputs.small_dense(m, 5)
+    amax, amin = sg.abs_eig_bounds(sg.casida_matrix(a, b), sg.casida_sigma(m))
+    rng = np.random.default_rng(7)
+    g_a, g_b = rng.standard_normal((m, m)), rng.standard_normal((m, m))
+    SA, SB, store, info = api.sign_fwd_iter(dev(a), dev(b), alpha=amax, beta=0.9 * amax, r=2)
+    assert info["status"] == 0 and info["restarts"] >= 1 and info["steps"] >= 4
+    ga, gb = api.sign_bwd_iter(store, dev(g_a), dev(g_b))
+    ra, rb = gr.sign_block_grad(a, b, g_a, g_b)
+    assert rel(ga.cpu().numpy(), ra) < 1e-9 and rel(gb.cpu().numpy(), rb) < 1e-9
+
+
+def test_sign_iter_arguments():
+    a, b = inputs.small_dense(16, 1)
+    with pytest.raises(api.PseudosymError) as e:
+        api.sign_fwd_iter(dev(a), dev(b), precision="mixed")
+    assert e.value.code == -12
+    with pytest.raises(api.PseudosymError) as e:
+        api.sign_fwd_iter(dev(a), dev(b), max_restarts=4)
+    assert e.value.code == -12
+
+
+@pytest.mark.timeout(600)
+def test_autograd_iter_m1024_vs_oracle_and_eigenbasis_adjoint():
+    """n = 2048 (the gradient workload): the stored-factor backward against the oracle's
+    gradient and against the eigenbasis adjoint."""
+    m = 1024
+    a, b = inputs.casida_like(m, 3)
+    w = inputs.gradient_weight(m, 1003)
+    W = dev(w)
+    print("[adjoint iter] m=1024", flush=True)
+    grads = []
+    for fn in (api.PseudosymSignIter, api.PseudosymSign):
+        A = dev(a).requires_grad_(True)
+        B = dev(b).requires_grad_(True)
+        SA, SB = fn.apply(A, B)
+        L = _projector_loss_torch(SA, SB, W, m)
+        L.backward()
+        grads.append((A.grad.cpu().numpy(), B.grad.cpu().numpy()))
+    (ia, ib), (ea, eb) = grads
+    assert rel(ia, ea) < 1e-10 and rel(ib, eb) < 1e-10
+    ra, rb = gr.projector_loss_grad(a, b, w)
+    assert rel(ia, ra) < 1e-10 and rel(ib, rb) < 1e-10
