@@ -628,13 +628,17 @@ class SignStore:
         self.m = m
 
 
-def sign_fwd_iter(A, B, raise_on_error=True, **kw):
+def sign_fwd_iter(A, B, raise_on_error=True, store=None, **kw):
     """Sign blocks plus the iteration's stored factors, which the adjoint reuses (FP64).
+    `store`: a SignStore of an earlier call to reuse when it is large enough.
     Returns (SA, SB, store, info)."""
     torch = _torch()
     opts = make_opts(**kw)
     lib, st, A, B, m = _call_setup(A, B, opts, 0)
-    store = SignStore(int(lib.ps_sign_store_size(m, ctypes.byref(opts))), A.device, m)
+    need = int(lib.ps_sign_store_size(m, ctypes.byref(opts)))
+    if store is None or store.nbytes < need or store.buffer.device != A.device:
+        store = SignStore(need, A.device, m)
+    store.m = m
     SA = torch.empty((m, m), dtype=torch.float64, device=A.device)
     SB = torch.empty((m, m), dtype=torch.float64, device=A.device)
     info = PsInfo()

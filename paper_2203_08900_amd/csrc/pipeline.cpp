@@ -3229,6 +3229,12 @@ int pseudosym_sign_fwd_iter(ps_handle h, int m, const double* A, int lda, const 
   keep.r = o.r;
   keep.max_steps = 2 * (1 + o.max_restarts);
   return guarded(h, [&] {
+    // the header is written last, on success: until then the store reads as empty, so a
+    // backward after a failed forward is refused instead of using older factors
+    std::memset(h->pinned, 0, kStoreHeader * sizeof(double));
+    PS_HIP(hipMemcpyAsync(store, h->pinned, kStoreHeader * sizeof(double), hipMemcpyHostToDevice,
+                          h->stream));
+    PS_HIP(hipStreamSynchronize(h->stream));
     return run(h, m, A, lda, B, ldb, SA, lds, SB, lds, o, info, 0, nullptr, false, &keep);
   });
 }

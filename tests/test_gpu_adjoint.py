@@ -153,6 +153,22 @@ def test_sign_bwd_iter_through_a_restart():
     assert rel(ga.cpu().numpy(), ra) < 1e-9 and rel(gb.cpu().numpy(), rb) < 1e-9
 
 
+def test_sign_iter_store_after_failed_forward():
+    """A forward that fails (A + B not definite) leaves the store marked empty: the
+    backward refuses it (-3) rather than use the factors of an earlier forward."""
+    m = 16
+    a, b = inputs.small_dense(m, 1)
+    SA, SB, store, info = api.sign_fwd_iter(dev(a), dev(b))
+    assert info["status"] == 0
+    g = dev(np.eye(m))
+    api.sign_bwd_iter(store, g, g)                     # a complete forward: accepted
+    _, _, same, info2 = api.sign_fwd_iter(dev(-a), dev(b), store=store, raise_on_error=False)
+    assert same is store and info2["rc"] == 1          # not definite
+    with pytest.raises(api.PseudosymError) as e:
+        api.sign_bwd_iter(store, g, g)
+    assert e.value.code == -3
+
+
 def test_sign_iter_arguments():
     a, b = inputs.small_dense(16, 1)
     with pytest.raises(api.PseudosymError) as e:
