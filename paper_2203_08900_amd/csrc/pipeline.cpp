@@ -2054,17 +2054,19 @@ int run_sign_bwd(ps_handle h, int m, const double* lam, const double* V, int ldv
   return PS_OK;
 }
 
-// Workspace of the stored-factor backward: 13 matrices and two stacks of r.
+// Workspace of the stored-factor backward: 13 matrices, two stacks of r and the split-K
+// partials.
 size_t sign_bwd_iter_bytes(int m, int r) {
   const size_t S = (size_t)pad_to(m) * pad_to(m);
-  return (13 + 2 * (size_t)r) * S * sizeof(double) + 16 * kAlign;
+  return (13 + 2 * (size_t)r + kMaxSplit) * S * sizeof(double) + 16 * kAlign;
 }
 
 // Reverse mode through the forward that filled `store` (see StepStore):
 //   S12 = W_M U R_K, S21 = R_M^T U W_K^T, S_A = (sym S21 + sym S12)/2,
 //   S_B = (sym S21 - sym S12)/2;
 //   Zolotarev step X' = hat C X (I + sum_j a_j N_j), N_j = (X^T X + c_j I)^{-1} = W_j W_j^T:
-//   gX = hat C (G (I + sum_j a_j N_j) - X (Z + Z^T)), Z = sum_j a_j N_j X^T G N_j;
+//   gX = hat C (G (I + sum_j a_j N_j) - X (Z + Z^T)), Z = sum_j a_j N_j X^T G N_j
+//   (Z + Z^T = sum_j a_j N_j (X^T G + G^T X) N_j);
 //   X_k = scale_k (previous output or Y0), Y0 = R_M R_K^T, W = R^{-1}: gR -= W^T gW W^T;
 //   M = R^T R: gM = sym(W Phi(R triu(gR)^T) W^T), Phi = lower triangle, diagonal halved;
 //   gA = gM + gK, gB = gM - gK.
@@ -2102,6 +2104,7 @@ int run_sign_bwd_iter(ps_handle h, int m, const double* store, const double* gSA
   double* gkk = a.take<double>(S);
   double* sa = a.take<double>((size_t)r * S);
   double* sb = a.take<double>((size_t)r * S);
+  double* sws = a.take<double>((size_t)kMaxSplit * S);   // split-K / stream-K partials
   StepStore st;
   st.base = const_cast<double*>(store);
   st.mp = mp;
@@ -2114,6 +2117,7 @@ int run_sign_bwd_iter(ps_handle h, int m, const double* store, const double* gSA
   auto gemm = [&](const double* A_, int tA, const double* B_, int tB, double* D, double al,
                   double be, const double* C, int flags) {
     GemmProblem p = gemm_problem(mp, mp, mp, A_, mp, tA, B_, mp, tB, D, mp, al, be, C, mp, flags);
+    auto_split(p, sws);
     gemm_f64(s, p);
   };
   // batch of r products, operand A (or B) stepping through the stack
@@ -2129,12 +2133,17 @@ int run_sign_bwd_iter(ps_handle h, int m, const double* store, const double* gSA
   };
   // sum_j a_j L_j W_j^T over the stacks (K segments of mp), plus beta C
   auto gemm_seg = [&](const double* L, const double* W, const double* aj, double* D, double be,
-                      const double* C) {
+                      const double* C, int flags) {
     GemmProblem p = gemm_problem(mp, mp, r * mp, L, mp, 0, W, mp, 1, D, mp, 1.0, be, C, mp,
-                                 kBLower);
+                                 kBLower | flags);
     p.kseg = mp;
     p.nseg = r;
     for (int j = 0; j < r; ++j) p.kscale[j] = aj[j];
+    if (r > 1 && r <= kMaxSplit) {   // one partial per segment, as the forward's N product
+      p.ksplit = r;
+      p.ws = sws;
+      p.ws_slots = kMaxSplit;
+    }
     gemm_f64(s, p);
   };
   // ---- sign blocks: g12 = dL/dS12, g21 = dL/dS21; gU = W_M^T g12 R_K^T + R_M g21 W_K
@@ -2150,14 +2159,17 @@ int run_sign_bwd_iter(ps_handle h, int m, const double* store, const double* gSA
     const double* W = st.w(k);
     const double* hk = hdr + 16 + 16 * k;
     const double scale = hk[0], chat = hk[1];
+    // Z + Z^T = sum_j a_j N_j (X^T G + G^T X) N_j: symmetric, so two of its products
+    // form only their upper triangles
     gemm(X, 1, G, 0, t1, 1.0, 0.0, nullptr, 0);                       // X^T G
-    gemm_r(W, (long long)S, 1, t1, 0, 0, sa, kALower);                // W_j^T X^T G
-    gemm_r(sa, (long long)S, 0, W, (long long)S, 0, sb, kBUpper);     // (.) W_j
+    sym2(s, t1, Z, mp);                                               // X^T G + G^T X
+    gemm_r(W, (long long)S, 1, Z, 0, 0, sa, kALower);                 // W_j^T (.)
+    gemm_r(sa, (long long)S, 0, W, (long long)S, 0, sb,
+           kBUpper | kOutUpper | kMirror);                            // (.) W_j
     gemm_r(W, (long long)S, 0, sb, (long long)S, 0, sa, kAUpper);     // W_j (.)
-    gemm_seg(sa, W, hk + 2, Z, 0.0, nullptr);                         // Z = sum a_j N_j X^T G N_j
+    gemm_seg(sa, W, hk + 2, t2, 0.0, nullptr, kOutUpper | kMirror);   // Z + Z^T
     gemm_r(G, 0, 0, W, (long long)S, 0, sb, kBUpper);                 // G W_j
-    gemm_seg(sb, W, hk + 2, P, 1.0, G);                               // G (I + sum a_j N_j)
-    sym2(s, Z, t2, mp);                                               // Z + Z^T
+    gemm_seg(sb, W, hk + 2, P, 1.0, G, 0);                            // G (I + sum a_j N_j)
     gemm(X, 0, t2, 0, G, -scale * chat, scale * chat, P, 0);         // gradient of the input
   }
   // ---- Y0 = R_M R_K^T (G = dL/dY0), W = R^{-1}:
