@@ -238,7 +238,8 @@ def eig_leg(args):
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic", "config": {"workload": desc, "n": 2 * m, "m": m},
             "rel_eig_err": err, "residual": res, "splits": info["eig_splits"],
-            "leaves": info["eig_leaves"], "max_jacobi_sweeps": info["eig_sweeps"]}
+            "leaves": info["eig_leaves"], "max_jacobi_sweeps": info["eig_sweeps"],
+            "zolotarev_steps": info["eig_steps"], "restarts": info["eig_restarts"]}
 
 
 def adjoint_leg(args):
