@@ -185,7 +185,7 @@ typedef struct {
    * held the singular values of the core; the largest over the attempts of its lower
    * estimate by power steps on the device, and the attempts whose estimate exceeded that
    * bound (plus rounding), whose second step was then redone by factorizations and
-   * followed by a restart. */
+   * followed by a restart (pseudosym_eig: over all its splits). */
   double delta_norm_est;
   int bounds_rejected;
 } ps_info;

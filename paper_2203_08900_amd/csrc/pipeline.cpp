@@ -224,6 +224,14 @@ int auto_r(double ell) {
 
 int resolve_r(const ps_opts& o) { return o.r <= 0 ? 8 : std::min(o.r, 8); }
 
+// Zolotarev degree of the recursion's splits.  The shifted blocks have eigenvalues
+// spread over [l, 1] with l small; with the smallest r that reaches 1 - 1e-15 in two
+// steps, 1 - l_1 after the first step is about u^{1/(2r+1)}, the stopping test's own
+// tolerance, so most splits restarted (26 of 31 at n = 4096); the factorization chains
+// are latency-bound, so r = 8 costs about the same per step and takes 1 - l_1 well
+// below it.
+constexpr int kEigR = 8;
+
 // Device buffers of the eigen-decomposition, placed after the largest divide or
 // subproblem layout (the recursion reuses that region for every subproblem).
 struct EigBuffers {
@@ -1698,9 +1706,11 @@ int eig_split(const SplitCtx& c, const EigBuffers& gl, int m, int o, int n, cons
     scale_copy(s, b.x1, b.y, 1.0, b.S);
     ps_info pinf{};
     Timer tm0{nullptr, false};
-    const int st = polar_iterate(s, b, b.y, alpha, beta, 0, o_, pin, pinf, tm0);
+    const int st = polar_iterate(s, b, b.y, alpha, beta, kEigR, o_, pin, pinf, tm0);
     inf.eig_steps += pinf.steps;
     inf.eig_restarts += pinf.restarts;
+    inf.bounds_rejected += pinf.bounds_rejected;
+    inf.delta_norm_est = std::max(inf.delta_norm_est, pinf.delta_norm_est);
     if (st != PS_OK) {
       rp = -1;
       continue;
