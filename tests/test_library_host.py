@@ -93,6 +93,24 @@ def test_workspace_and_stream_arguments_host_only():
     assert lib.ps_set_worker_streams(None, 0, None) == -1
 
 
+def test_sign_store_and_adjoint_workspace_sizes_host_only():
+    """The stored-factor adjoint's sizes are host computations: the store holds a 256-value
+    header, R_M, R_K, W_M, W_K, U and per Zolotarev step its input and r factors, for
+    2 (1 + max_restarts) steps; its backward's workspace is kind 7."""
+    lib = api.load()
+    o = api.make_opts(r=8, max_restarts=2)
+    mp = 320                                          # m = 300 padded to 64
+    steps = 2 * (1 + 2)
+    assert lib.ps_sign_store_size(300, ctypes.byref(o)) == (256 + (5 + steps * 9) * mp * mp) * 8
+    o0 = api.make_opts(r=0, max_restarts=0)           # r = 0 stores the largest r
+    assert lib.ps_sign_store_size(300, ctypes.byref(o0)) == (256 + (5 + 2 * 9) * mp * mp) * 8
+    assert lib.ps_sign_store_size(0, ctypes.byref(o)) == 0
+    assert lib.ps_sign_store_size(300, ctypes.byref(api.make_opts(max_restarts=4))) == 0
+    w7 = lib.ps_workspace_size(300, ctypes.byref(o), 7)
+    assert w7 >= (13 + 2 * 8 + 8) * mp * mp * 8
+    assert lib.pseudosym_sign_bwd_iter(None, 4, None, None, None, 4, None, None, 4) == -1
+
+
 def _c_struct_fields(name):
     txt = open(HEADER).read()
     body = txt[:txt.index("} " + name + ";")]
