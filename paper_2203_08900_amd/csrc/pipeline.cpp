@@ -330,8 +330,9 @@ struct Timer {
 
 // Golub-Kahan bidiagonalization of two matrices at once: M_0 = mats[0], M_1 = mats[S],
 // transposes in mats_t.  Returns sigma_max of each bidiagonal projection.
+// dinfo_dev: flags to bring back with the same synchronization (to pinned + 512)
 void gk_estimate(hipStream_t s, Buffers& b, const double* mats, const double* mats_t, int steps,
-                 double* pinned, double smax[2]) {
+                 double* pinned, double smax[2], const int* dinfo_dev = nullptr) {
   const int mp = b.mp;
   const long long S = (long long)b.S;
   gk_init(s, b.vv, b.m, mp, 2, 0);
@@ -350,6 +351,8 @@ void gk_estimate(hipStream_t s, Buffers& b, const double* mats, const double* ma
   }
   gk_finish(s, part(2 * steps - 1), mp, b.hist, 2 * steps - 1, 256, 2);
   PS_HIP(hipMemcpyAsync(pinned, b.hist, 2 * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (dinfo_dev)
+    PS_HIP(hipMemcpyAsync(pinned + 512, dinfo_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
   for (int q = 0; q < 2; ++q) {
     double d[128], e[128];
@@ -610,10 +613,11 @@ void zolo_step_series_mixed(hipStream_t s, Buffers& b, const double* x, double* 
 
 // alpha, beta for the core matrix: sigma_max(Y) and 1/sigma_max(Y^{-1}) by Golub-Kahan.
 void estimate_bounds(hipStream_t s, Buffers& b, const double* ymats, int steps, double* pinned,
-                     double* alpha, double* beta, double est[2]) {
+                     double* alpha, double* beta, double est[2],
+                     const int* dinfo_dev = nullptr) {
   transpose(s, ymats, b.yt, b.mp, (long long)b.S, 2);
   double smax[2];
-  gk_estimate(s, b, ymats, b.yt, steps, pinned, smax);
+  gk_estimate(s, b, ymats, b.yt, steps, pinned, smax, dinfo_dev);
   est[0] = smax[0];
   est[1] = smax[1] > 0 ? 1.0 / smax[1] : 0.0;
   *alpha = 1.01 * smax[0];
@@ -803,7 +807,6 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
     ZoloHost c1, c2;
     if (zolotarev_host(ell, r_run, &c1)) return PS_NOT_CONVERGED;
     double ell1 = std::min(c1.ell_next, 1.0 - 1e-15);
-    if (zolotarev_host(ell1, r_run, &c2)) return PS_NOT_CONVERGED;
     if (ell_slot < 4) inf.ell[ell_slot++] = ell;
     if (ell_slot < 4) inf.ell[ell_slot++] = ell1;
     if (mx) {
@@ -822,6 +825,8 @@ int polar_iterate(hipStream_t s, Buffers& b, const double* y, double alpha, doub
       std::swap(b.x1, b.x2);  // the sign assembly reads x2
       break;
     }
+    // the second step's coefficients, on the host while the first step runs
+    if (zolotarev_host(ell1, r_run, &c2)) return PS_NOT_CONVERGED;
     double gam[kMaxSeries];
     const int P = o.step2_series ? series_terms(c2, ell1, gam) : 0;
     inf.step2_terms = P;
@@ -1011,20 +1016,25 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
   // ---- parameter estimation (Alg. 8 step 1)
   double alpha = o.alpha, beta = o.beta;
   inf.sigma_est[0] = inf.sigma_est[1] = 0.0;
+  // a failed setup Cholesky shows up as non-finite estimates; its flag comes back with
+  // the estimator's results (or on its own when the caller gave both bounds)
+  int setup_flag;
   if (!(alpha > 0.0) || !(beta > 0.0)) {
     double a_est, b_est;
     estimate_bounds(s, b, b.y, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a_est, &b_est,
-                    inf.sigma_est);
+                    inf.sigma_est, b.dinfo);
+    setup_flag = ((const int*)(pin + 512))[0];
     if (!(alpha > 0.0)) alpha = a_est;
     if (!(beta > 0.0)) beta = b_est;
+  } else {
+    PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PS_HIP(hipStreamSynchronize(s));
+    setup_flag = ((const int*)pin)[0];
   }
-  // a failed setup Cholesky shows up as non-finite estimates; check the flag now
-  PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
-  PS_HIP(hipStreamSynchronize(s));
-  if (((int*)pin)[0] != 0) {
+  if (setup_flag != 0) {
     inf.status = PS_NOT_DEFINITE;
     inf.failed_step = 0;
-    inf.failed_mask = ((int*)pin)[0];
+    inf.failed_mask = setup_flag;
     if (info) *info = inf;
     return PS_NOT_DEFINITE;
   }
