@@ -452,6 +452,13 @@ int pseudosym_sign_bwd(ps_handle h, int m, const double* lambda, const double* V
                        const double* gSA, const double* gSB, int ldg, double* gA, double* gB,
                        int ldo);
 
+/* The full 2m x 2m sign(H) = [[S_A, S_B], [-S_B, -S_A]] (eq:signDef; the block form of
+ * sign(H) for the Casida structure) from the blocks pseudosym_sign returns (device, m x m,
+ * leading dimension lds), written to S (device, column-major, lds2 >= 2m; caller-owned).
+ * Argument errors: -1 handle, -2 m, -3 SA, -4 SB, -5 lds, -6 S, -7 lds2. */
+int pseudosym_sign_full(ps_handle h, int m, const double* SA, const double* SB, int lds,
+                        double* S, int lds2);
+
 /* Differentiable sign function on the iteration's own factors (no eigen-decomposition).
  * The forward is pseudosym_sign (Alg. 8 on the core Y0 = R_M R_K^T, Sec. 4, in FP64, both
  * steps by factorizations, no Newton-Schulz pass) that also writes into `store` (caller's

@@ -118,6 +118,7 @@ EXPORTS = [
     "pseudosym_divide_static", "pseudosym_divide_general", "pseudosym_eig",
     "pseudosym_divide_batched", "pseudosym_sign_fwd", "pseudosym_sign_bwd",
     "ps_sign_store_size", "pseudosym_sign_fwd_iter", "pseudosym_sign_bwd_iter",
+    "pseudosym_sign_full",
     "pseudosym_sign_hermitian", "pseudosym_divide_hermitian", "pseudosym_sign_bse",
     "ps_status_string",
 ]
@@ -201,6 +202,8 @@ def load():
         lib.pseudosym_sign_fwd.restype = ip
         lib.pseudosym_sign_bwd.argtypes = [hp, ip, vp, vp, ip, vp, vp, ip, vp, vp, ip]
         lib.pseudosym_sign_bwd.restype = ip
+        lib.pseudosym_sign_full.argtypes = [hp, ip, vp, vp, ip, vp, ip]
+        lib.pseudosym_sign_full.restype = ip
         lib.ps_sign_store_size.argtypes = [ip, ctypes.POINTER(PsOpts)]
         lib.ps_sign_store_size.restype = sz
         lib.pseudosym_sign_fwd_iter.argtypes = mat + [vp, vp, ip, vp, sz, ctypes.POINTER(PsOpts),
@@ -339,8 +342,9 @@ def _call_setup(A, B, opts, what):
     return lib, st, A, B, m
 
 
-def sign(A, B, raise_on_error=True, **kw):
-    """Blocks (SA, SB) of sign(H), H = [[A, B], [-B, -A]].  Returns (SA, SB, info)."""
+def sign(A, B, raise_on_error=True, full=False, **kw):
+    """Blocks (SA, SB) of sign(H), H = [[A, B], [-B, -A]].  Returns (SA, SB, info), or with
+    full=True (SA, SB, S, info) with S the whole 2m x 2m sign(H)."""
     torch = _torch()
     opts = make_opts(**kw)
     lib, st, A, B, m = _call_setup(A, B, opts, 0)
@@ -353,7 +357,16 @@ def sign(A, B, raise_on_error=True, **kw):
         raise PseudosymError(rc, info.as_dict())
     # the library writes column-major; SA, SB are symmetric up to rounding, return the
     # column-major view so that entry (i, j) is the library's (i, j)
-    return SA.t(), SB.t(), info.as_dict() | {"rc": rc}
+    out = info.as_dict() | {"rc": rc}
+    if not full:
+        return SA.t(), SB.t(), out
+    St = torch.empty((2 * m, 2 * m), dtype=torch.float64, device=A.device)
+    if rc == 0:
+        rc2 = lib.pseudosym_sign_full(st.handle, m, SA.data_ptr(), SB.data_ptr(), m,
+                                      St.data_ptr(), 2 * m)
+        if rc2 != 0:
+            raise PseudosymError(rc2)
+    return SA.t(), SB.t(), St.t(), out
 
 
 def divide(A, B, raise_on_error=True, **kw):

@@ -620,4 +620,28 @@ void sym_power_norm(hipStream_t s, const double* M, int m, int mp, double shift,
   PS_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------- full sign matrix from its blocks
+// S = [[S_A, S_B], [-S_B, -S_A]] (2m x 2m, ld lds2) from the m x m blocks (ld lds)
+__global__ void sign_full_kernel(const double* sa, const double* sb, int lds, int m, double* S,
+                                 int lds2) {
+  const int n = 2 * m;
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const int bi = i >= m, bj = j >= m;
+    const size_t src = (i - bi * m) + (size_t)(j - bj * m) * lds;
+    // row block 0: (S_A, S_B); row block 1: (-S_B, -S_A)
+    const double v = (bi == bj) ? sa[src] : sb[src];
+    S[i + (size_t)j * lds2] = bi ? -v : v;
+  }
+}
+
+void sign_full(hipStream_t s, const double* sa, const double* sb, int lds, int m, double* S,
+               int lds2) {
+  hipLaunchKernelGGL(sign_full_kernel, dim3(blocks_for((size_t)4 * m * m)), dim3(NT), 0, s, sa, sb,
+                     lds, m, S, lds2);
+  PS_HIP(hipGetLastError());
+}
+
 }  // namespace ps

@@ -3226,6 +3226,22 @@ int pseudosym_sign_fwd(ps_handle h, int m, const double* A, int lda, const doubl
   });
 }
 
+int pseudosym_sign_full(ps_handle h, int m, const double* SA, const double* SB, int lds,
+                        double* S, int lds2) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (!SA) return -3;
+  if (!SB) return -4;
+  if (lds < m) return -5;
+  if (!S) return -6;
+  if (lds2 < 2 * m) return -7;
+  return guarded(h, [&] {
+    sign_full(h->stream, SA, SB, lds, m, S, lds2);
+    PS_HIP(hipStreamSynchronize(h->stream));
+    return PS_OK;
+  });
+}
+
 size_t ps_sign_store_size(int m, const ps_opts* opts) {
   ps_opts o;
   ps_opts_default(&o);

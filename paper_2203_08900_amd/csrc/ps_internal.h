@@ -266,6 +266,9 @@ void fill_int_zero(hipStream_t s, int* x, int n);
 void adj_seed(hipStream_t s, const double* ga, const double* gb, int ldg, int m, int mp,
               double* g12, double* g21);
 void sym2(hipStream_t s, const double* x, double* y, int mp);
+// S = [[S_A, S_B], [-S_B, -S_A]] (2m x 2m, ld lds2) from the blocks (m x m, ld lds)
+void sign_full(hipStream_t s, const double* sa, const double* sb, int lds, int m, double* S,
+               int lds2);
 void phi_lower(hipStream_t s, double* x, int mp);
 void adj_out(hipStream_t s, const double* gm, const double* gk, int mp, int m, double* ga,
              double* gb, int ldo);

@@ -233,6 +233,20 @@ def test_misplaced_beta_caught_mixed():
     assert np.max(np.abs(w - lam) / lam) < 1e-9
 
 
+def test_full_sign_matrix():
+    """pseudosym_sign_full: the whole 2m x 2m sign(H) from the blocks, against the
+    definition, and an involution (S^2 = I)."""
+    m = 70
+    a, b = inputs.small_dense(m, 9)
+    SA, SB, S, info = api.sign(dev(a), dev(b), full=True)
+    assert info["status"] == 0
+    s = sg.sign_definition(sg.casida_matrix(a, b), sg.casida_sigma(m))
+    Sh = S.cpu().numpy()
+    assert rel(Sh, s) < 1e-12
+    assert np.array_equal(Sh[:m, :m], SA.cpu().numpy()) and np.array_equal(Sh[m:, :m], -SB.cpu().numpy())
+    assert np.abs(Sh @ Sh - np.eye(2 * m)).max() < 1e-11
+
+
 def test_bad_arguments():
     a, b = inputs.small_dense(8, 1)
     with pytest.raises(api.PseudosymError):
