@@ -324,6 +324,7 @@ def general_leg(args):
                        "r_plus": int(np.sum(sig > 0))},
             "roofline": roofline(kc, args.steps, ms),
             "steps_taken": info["steps"], "restarts": info["restarts"], "backward_error": bwd,
+            "cond_est": info["cond_est"],
             "backward_error_n250": sweep}
 
 

@@ -188,6 +188,11 @@ typedef struct {
    * followed by a restart (pseudosym_eig: over all its splits). */
   double delta_norm_est;
   int bounds_rejected;
+  /* pseudosym_divide_general: cond(Sigma H) = (sigma_max(R) sigma_max(R^{-1}))^2 for the
+   * Cholesky factor R of Sigma H, by Golub-Kahan (from below), which bounds this form's
+   * accuracy (the backward error grows like cond(Sigma H) u: about 1e-9 at 1e7, 1e-4 at
+   * 1e12). */
+  double cond_est;
 } ps_info;
 
 /* kernel classes of ps_info.kclass_* */
@@ -330,10 +335,12 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
  *   Qm     n x r_- (ldqm >= n): Q_-^T Sigma Q_- = -I, the negative one.
  *   Hp     r_+ x r_+ (ldhp >= r_+): H_+ = Q_+^T Sigma H Q_+, symmetric positive definite.
  *   Hm     r_- x r_- (ldhm >= r_-): H_- = -Q_-^T Sigma H Q_-, negative definite.
- * Outputs of an empty side (r_+ = 0 or r_- = 0) may be NULL.  The Cholesky form of the
- * first step loses its accuracy (or breaks down with PS_SHIFT_BREAKDOWN) when the
- * condition number of M exceeds about 1e7 (the shifted T^2 + c I then have condition
- * numbers near 1/u); the leading blocks of Alg. 6 can be ill-conditioned for an
+ * Outputs of an empty side (r_+ = 0 or r_- = 0) may be NULL.  The congruence with R and
+ * the Cholesky form of the first step make the accuracy fall with the condition number
+ * of M: backward errors ||Q_+^T Sigma H Q_-|| / ||H|| of about 1e-10 at cond(M) = 1e6,
+ * 1e-9 at 1e7, 1e-6 at 1e10 and 1e-4 at 1e12 (n = 250, Sec. 6.1 matrices), or
+ * PS_SHIFT_BREAKDOWN; info->cond_est reports a lower estimate of cond(M), so that the
+ * caller can tell.  The leading blocks of Alg. 6 can be ill-conditioned for an
  * unlucky Sigma, which PS_BASIS_BREAKDOWN reports when their Cholesky fails.
  * opts->basis = PS_BASIS_LDL takes Alg. 7 instead (truncated LDL^T with diagonal
  * pivoting of Sigma P_+ and -Sigma P_-, Q_+- = Sigma C_+-; padded n up to 16384, else

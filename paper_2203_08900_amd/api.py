@@ -89,6 +89,7 @@ class PsInfo(ctypes.Structure):
         ("kclass_flops", ctypes.c_double * 8),
         ("delta_norm_est", ctypes.c_double),
         ("bounds_rejected", ctypes.c_int),
+        ("cond_est", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -107,6 +108,7 @@ class PsInfo(ctypes.Structure):
             "kclass_launches": list(self.kclass_launches),
             "kclass_ms": list(self.kclass_ms), "kclass_flops": list(self.kclass_flops),
             "delta_norm_est": self.delta_norm_est, "bounds_rejected": self.bounds_rejected,
+            "cond_est": self.cond_est,
         }
 
 

@@ -1325,6 +1325,14 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
     if (!(alpha > 0.0)) alpha = a_est;
     if (!(beta > 0.0)) beta = b_est;
   }
+  // cond(M) = (sigma_max(R) sigma_max(R^{-1}))^2, which bounds this form's accuracy:
+  // Golub-Kahan on the pair [R, W] (W copied next to R), estimates from below
+  {
+    PS_HIP(hipMemcpyAsync(R + S, W, S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double est[2], a_r, b_r;
+    estimate_bounds(s, b, R, std::max(4, std::min(o.lanczos_steps, 120)), pin, &a_r, &b_r, est);
+    inf.cond_est = est[1] > 0.0 ? (est[0] / est[1]) * (est[0] / est[1]) : HUGE_VAL;
+  }
   PS_HIP(hipMemcpyAsync(pin, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
   if (((int*)pin)[0] != 0) {

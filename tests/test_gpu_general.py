@@ -38,6 +38,9 @@ def test_general_division_parity(n, seed, kappa):
     H = torch.tensor(h, dtype=torch.float64, device="cuda")
     Qp, Qm, Hp, Hm, S, info = api.divide_general(H, sig, want_sign=True)
     assert info["status"] == 0 and info["steps"] == 2 and info["restarts"] == 0
+    # the condition estimate: cond(Sigma H) = kappa (D spans [1, kappa]), from below
+    print(f"[general] cond_est {info['cond_est']:.3g}", flush=True)
+    assert 0.5 * kappa <= info["cond_est"] <= kappa * (1.0 + 1e-8)
     Qp, Qm, Hp, Hm, S = (x.cpu().numpy() for x in (Qp, Qm, Hp, Hm, S))
     s_def = sg.sign_definition(h, sig)
     assert np.abs(S - s_def).max() < 1e-12 * kappa * np.abs(s_def).max()
