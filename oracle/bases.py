@@ -22,6 +22,14 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
   current Schur complement (ties: lower index) are the candidates, and each pivot is
   the largest Schur diagonal among the remaining candidates (ties: lower index).  With
   `cand` at least the matrix size this is complete diagonal pivoting (LAPACK xPSTRF).
+* ``congruent_bases_general``: for any signature, the bases from the projectors of the
+  congruent symmetric T = R Sigma R^T (M = Sigma H = R^T R): H = R^{-1} T R, so the
+  projectors of H are R^{-1} (I +- sign(T))/2 R and their ranges are W = R^{-1} applied to
+  the ranges of Z_+- = (I +- sign(T))/2, symmetric positive semidefinite of rank r_+-.
+  Z_+- = C C^T by the pivoted LDL^T above, V = W C, and Q = V R_G^{-1} with the Cholesky
+  factor of the Sigma-Gram matrix +-V^T Sigma V (positive definite, Thm. DefDivConq).  Not
+  one of the paper's listings: it avoids forming sign(H), whose projectors lose
+  cond(M) u of accuracy, and is exact in exact arithmetic.
 * ``alg4_orthogonal_bases``: Alg. 4 for a symmetric matrix: r_+ = trace(P_+),
   lower Cholesky factor of the leading r_+ block of P_+ extended by
   P_+(r_++1:n,1:r_+) Q_{1,+}^{-T}; the second half uses P_- throughout (the
@@ -204,6 +212,42 @@ def alg7_pivoted_bases(s: np.ndarray, sigma: np.ndarray, panel: int = 64, cand: 
     cp, _ = pivoted_ldl_factor(zp, p, panel, cand) if p else (np.zeros((s.shape[0], 0)), None)
     cm, _ = pivoted_ldl_factor(zm, q, panel, cand) if q else (np.zeros((s.shape[0], 0)), None)
     return sigma[:, None] * cp, sigma[:, None] * cm
+
+
+def congruent_bases_general(h: np.ndarray, sigma: np.ndarray, u=None):
+    """Bases of the two invariant subspaces of a definite pseudosymmetric H (Sigma H
+    symmetric positive definite, any signature) from the projectors of the congruent
+    symmetric T (module docstring).  Steps: M = sym(Sigma H) = R^T R, W = R^{-1},
+    T = R Sigma R^T, U = sign(T) (given as `u`, else Alg. 8 on T with Cholesky solves);
+    for (a, k) = (+1, r_+) and (-1, r_-): C C^T = (I + a U)/2 (rank k, pivoted 1x1 LDL^T),
+    V = W C, a V^T Sigma V = R_G^T R_G, Q = V R_G^{-1}, and the decoupled block
+    a Q^T Sigma H Q = a (R Q)^T (R Q) = a F^T F with F = C R_G^{-1} (R V = C).
+    Returns (Q_+, Q_-, H_+, H_-)."""
+    from . import sign as sg
+    n = h.shape[0]
+    m = sigma[:, None] * h
+    m = 0.5 * (m + m.T)
+    r = sla.cholesky(m, lower=False)
+    w = sla.solve_triangular(r, np.eye(n), lower=False)
+    if u is None:
+        t = (r * sigma[None, :]) @ r.T
+        u = sg.zolo_pd_symmetric(0.5 * (t + t.T))
+    u = 0.5 * (u + u.T)
+    out = []
+    for a in (1.0, -1.0):
+        k = int(np.sum(sigma * a > 0))
+        if k == 0:
+            out.append((np.zeros((n, 0)), np.zeros((0, 0))))
+            continue
+        c, _ = pivoted_ldl_factor(0.5 * (np.eye(n) + a * u), k)
+        v = w @ c
+        g = a * (v.T @ (sigma[:, None] * v))
+        rg = sla.cholesky(0.5 * (g + g.T), lower=False)
+        d = sla.solve_triangular(rg, np.eye(k), lower=False)
+        f = c @ d
+        out.append((v @ d, a * (f.T @ f)))
+    (qp, hp), (qm, hm) = out
+    return qp, qm, hp, hm
 
 
 def alg4_orthogonal_bases(s: np.ndarray):

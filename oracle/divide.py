@@ -65,12 +65,16 @@ def divide_general(h: np.ndarray, sigma: np.ndarray, r: int = 8, alpha=None, bet
     (Sigma H symmetric positive definite; Sec. 5 and the matrices of Sec. 6.1): sign(H)
     by Alg. 8 with LDL^T solves on H, bases by Alg. 6 as printed (leading indices,
     Q_- with the sign of Thm. HRisLDL) or by Alg. 7 with the pivoted 1x1 LDL^T
-    (basis = "alg7-pivoted"), decoupled blocks and backward error."""
+    (basis = "alg7-pivoted"), or from the projectors of the congruent symmetric T
+    (basis = "congruent", ``bases.congruent_bases_general``, sign(T) by Alg. 8 on T),
+    decoupled blocks and backward error."""
     s, rec = sg.zolo_pd(h, sigma, r=r, alpha=alpha, beta=beta, max_restarts=max_restarts)
     if basis == "alg6":
         qp, qm = bs.alg6_bases_general(s, sigma)
     elif basis == "alg7-pivoted":
         qp, qm = bs.alg7_pivoted_bases(s, sigma)
+    elif basis == "congruent":
+        qp, qm, _, _ = bs.congruent_bases_general(h, sigma)
     else:
         raise ValueError(basis)
     hp, hm, bwd = decouple(h, sigma, qp, qm)
