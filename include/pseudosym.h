@@ -90,8 +90,19 @@ enum {
  *                 It avoids the leading-block Cholesky that Alg. 6 needs; Q_+ differs
  *                 from the Alg. 6 basis by an orthogonal factor.  Padded 2m up to 16384;
  *                 pseudosym_divide and pseudosym_divide_general only.  A non-positive
- *                 retained pivot returns PS_BASIS_BREAKDOWN. */
-enum { PS_BASIS_ALG6 = 0, PS_BASIS_CORE = 1, PS_BASIS_LDL = 2 };
+ *                 retained pivot returns PS_BASIS_BREAKDOWN.
+ *  PS_BASIS_CONGRUENT: pseudosym_divide_general only.  With M = Sigma H = R^T R,
+ *                 W = R^{-1} and T = R Sigma R^T (H = W T R), the projectors of H are
+ *                 W (I +- sign(T))/2 R, so W maps the ranges of the symmetric positive
+ *                 semidefinite Z_+- = (I +- sign(T))/2 onto the invariant subspaces.
+ *                 Z_+- = C C^T by the truncated LDL^T of PS_BASIS_LDL (rank r_+-),
+ *                 V = W C, +-V^T Sigma V = R_G^T R_G (Cholesky), Q_+- = V R_G^{-1}, and
+ *                 H_+- = +-(C R_G^{-1})^T (C R_G^{-1}).  sign(H) is never formed (unless
+ *                 S is asked for), which keeps the backward error at rounding level for
+ *                 any cond(M) that the Cholesky of M survives.  Padded n up to 16384.
+ *                 Not one of the paper's listings: the subspaces are those of Alg. 6
+ *                 and 7, Q differs from their bases by an orthogonal factor. */
+enum { PS_BASIS_ALG6 = 0, PS_BASIS_CORE = 1, PS_BASIS_LDL = 2, PS_BASIS_CONGRUENT = 3 };
 
 typedef struct {
   int precision;       /* PS_PREC_*                                               */
@@ -335,17 +346,22 @@ int pseudosym_divide(ps_handle h, int m, const double* A, int lda, const double*
  *   Qm     n x r_- (ldqm >= n): Q_-^T Sigma Q_- = -I, the negative one.
  *   Hp     r_+ x r_+ (ldhp >= r_+): H_+ = Q_+^T Sigma H Q_+, symmetric positive definite.
  *   Hm     r_- x r_- (ldhm >= r_-): H_- = -Q_-^T Sigma H Q_-, negative definite.
- * Outputs of an empty side (r_+ = 0 or r_- = 0) may be NULL.  The congruence with R and
- * the Cholesky form of the first step make the accuracy fall with the condition number
- * of M: backward errors ||Q_+^T Sigma H Q_-|| / ||H|| of about 1e-10 at cond(M) = 1e6,
- * 1e-9 at 1e7, 1e-6 at 1e10 and 1e-4 at 1e12 (n = 250, Sec. 6.1 matrices), or
- * PS_SHIFT_BREAKDOWN; info->cond_est reports a lower estimate of cond(M), so that the
- * caller can tell.  The leading blocks of Alg. 6 can be ill-conditioned for an
- * unlucky Sigma, which PS_BASIS_BREAKDOWN reports when their Cholesky fails.
- * opts->basis = PS_BASIS_LDL takes Alg. 7 instead (truncated LDL^T with diagonal
- * pivoting of Sigma P_+ and -Sigma P_-, Q_+- = Sigma C_+-; padded n up to 16384, else
- * -16), which needs no leading block to be well conditioned; any other value gives
- * Alg. 6.  opts->max_steps must be 0. */
+ * Outputs of an empty side (r_+ = 0 or r_- = 0) may be NULL.  Bases built from sign(H)
+ * (Alg. 6 and 7) inherit its error, which the similarity with R multiplies by up to
+ * cond(M): backward errors ||Q_+^T Sigma H Q_-|| / ||H|| of about 1e-10 at
+ * cond(M) = 1e6, 1e-9 at 1e7, 1e-6 at 1e10 and 1e-4 at 1e12 (n = 250, Sec. 6.1
+ * matrices); info->cond_est reports a lower estimate of cond(M), so that the caller can
+ * tell.  opts->basis = PS_BASIS_CONGRUENT builds the bases from the projectors of T
+ * instead and keeps the backward error near 1e-15 up to cond(M) = 1e12 (see the enum).
+ * The leading blocks of Alg. 6 can be ill-conditioned for an unlucky Sigma, which
+ * PS_BASIS_BREAKDOWN reports when their Cholesky fails.  opts->basis = PS_BASIS_LDL
+ * takes Alg. 7 instead (truncated LDL^T with diagonal pivoting of Sigma P_+ and
+ * -Sigma P_-, Q_+- = Sigma C_+-), which needs no leading block to be well conditioned;
+ * PS_BASIS_LDL and PS_BASIS_CONGRUENT take padded n up to 16384, else -16; any other
+ * value gives Alg. 6.  PS_BASIS_BREAKDOWN under PS_BASIS_CONGRUENT: a non-positive
+ * retained pivot or a failed Cholesky of the Sigma-Gram matrix.  The Cholesky of M can
+ * still fail (PS_NOT_DEFINITE) or the iteration break down (PS_SHIFT_BREAKDOWN) at a
+ * large enough cond(M).  opts->max_steps must be 0. */
 int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const double* sigma,
                              double* S, int lds, double* Qp, int ldqp, double* Qm, int ldqm,
                              double* Hp, int ldhp, double* Hm, int ldhm, const ps_opts* opts,

@@ -24,6 +24,7 @@ PS_PREC_MIXED = 1
 PS_BASIS_ALG6 = 0
 PS_BASIS_CORE = 1
 PS_BASIS_LDL = 2
+PS_BASIS_CONGRUENT = 3
 # kernel classes of info["kclass_*"] (PS_KC_* in the header)
 KERNEL_CLASSES = ["chol_step_kernel<double,wide>", "chol_step_kernel<double,narrow>",
                   "chol_step_kernel<float>", "gemm_mfma_kernel<double,128x128>",
@@ -253,7 +254,8 @@ def make_opts(precision="fp64", r=8, max_restarts=2, max_steps=0, lanczos_steps=
     o.beta = float(beta or 0.0)
     o.mixed_kappa = float(mixed_kappa)
     o.step2_series = 1 if step2_series else 0
-    o.basis = {"alg6": PS_BASIS_ALG6, "core": PS_BASIS_CORE, "ldl": PS_BASIS_LDL}[basis] \
+    o.basis = {"alg6": PS_BASIS_ALG6, "core": PS_BASIS_CORE, "ldl": PS_BASIS_LDL,
+               "congruent": PS_BASIS_CONGRUENT}[basis] \
         if isinstance(basis, str) else int(basis)
     o.iteration = ITERATIONS[iteration] if isinstance(iteration, str) else int(iteration)
     o.refine = REFINES[refine] if isinstance(refine, str) else int(refine)

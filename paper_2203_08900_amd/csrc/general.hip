@@ -103,4 +103,41 @@ void chol_top(hipStream_t s, const double* c, int kp, const double* sg, int k, d
   PS_HIP(hipGetLastError());
 }
 
+// Upper triangle of the projector Z = (I + a sym(U))/2 of the symmetric T, U = sign(T)
+// (n x n in np x np, a = +-1): positive semidefinite of rank r_+ (a = +1) or r_- (a = -1);
+// zero below the diagonal and in the padding
+__global__ void proj_form_kernel(const double* U, int n, int np, double a, double* Z) {
+  PS_GEN_LOOP(e, (size_t)np * np) {
+    const int i = (int)(e % np), j = (int)(e / np);
+    double v = 0.0;
+    if (i <= j && j < n) {
+      v = 0.25 * a * (U[e] + U[j + (size_t)i * np]);
+      if (i == j) v += 0.5;
+    }
+    Z[e] = v;
+  }
+}
+
+void proj_form(hipStream_t s, const double* U, int n, int np, double a, double* Z) {
+  hipLaunchKernelGGL(proj_form_kernel, dim3(grid_for((size_t)np * np)), dim3(NT), 0, s, U, n, np,
+                     a, Z);
+  PS_HIP(hipGetLastError());
+}
+
+// x(i, j) = 1 if i == j else 0 wherever i >= k or j >= k (kp x kp, ld kp): the padding
+// of a k x k Gram matrix made the identity, so that its Cholesky factor and inverse are
+// the identity there
+__global__ void unit_pad_kernel(double* x, int k, int kp) {
+  PS_GEN_LOOP(e, (size_t)kp * kp) {
+    const int i = (int)(e % kp), j = (int)(e / kp);
+    if (i >= k || j >= k) x[e] = i == j ? 1.0 : 0.0;
+  }
+}
+
+void unit_pad(hipStream_t s, double* x, int k, int kp) {
+  if (k == kp) return;
+  hipLaunchKernelGGL(unit_pad_kernel, dim3(grid_for((size_t)kp * kp)), dim3(NT), 0, s, x, k, kp);
+  PS_HIP(hipGetLastError());
+}
+
 }  // namespace ps

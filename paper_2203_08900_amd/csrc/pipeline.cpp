@@ -1355,8 +1355,9 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
     if (info) *info = inf;
     return status;
   }
-  // ---- sign(H) = W U R (s12), zero padding
-  {
+  const bool congruent = o.basis == PS_BASIS_CONGRUENT;
+  // ---- sign(H) = W U R (s12), zero padding; the congruent bases do not need it
+  if (S_out || !congruent) {
     GemmProblem p1 = gemm_problem(np, np, np, W, np, 0, b.x2, np, 0, b.t1, np, 1.0, 0.0, nullptr,
                                   0, kAUpper);
     auto_split(p1, b.splitws);
@@ -1410,9 +1411,52 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
     copy_out(s, Q, np, Qout, ldqo, n, k);
     copy_out(s, b.hp, kp, Hout, ldho, k, k);
   };
-  basis(p, 1.0, 1.0, 1.0, Qp, ldqp, Hp, ldhp, 4);
-  tm.mark(6);
-  basis(q, -1.0, -1.0, -1.0, Qm, ldqm, Hm, ldhm, 5);
+  // ---- bases from the projectors of T: (I + a U)/2 (rank k) = C C^T by the truncated
+  // LDL^T with diagonal pivoting, V = W C spans the invariant subspace of H, its
+  // Sigma-Gram matrix a V^T Sigma V = R_G^T R_G, Q = V R_G^{-1}, and the decoupled block
+  // a (R Q)^T (R Q) = a F^T F with F = C R_G^{-1} (R V = C).  No product with sign(H),
+  // whose projectors carry cond(M) u of error.
+  auto cbasis = [&](int k, double a, double* Qout, int ldqo, double* Hout, int ldho, int slot) {
+    if (k == 0) return;
+    const int kp = pad_to(k);
+    double* C = b.w;    // np x kp
+    double* V = b.t1;   // np x kp
+    double* Q = b.ab;   // np x kp (Sigma V first)
+    double* D = b.wc;   // kp x kp, R_G^{-1}
+    int* iw = reinterpret_cast<int*>(b.t2);
+    const LdlScratch lw{b.wc, iw, iw + kp};
+    proj_form(s, b.x2, n, np, a, b.z);
+    ldl_factor(s, b.z, n, np, k, C, lw, b.dinfo + slot);
+    GemmProblem pv = gemm_problem(np, kp, np, W, np, 0, C, np, 0, V, np, 1.0, 0.0, nullptr, 0,
+                                  kAUpper);
+    gemm_f64(s, pv);
+    ldl_scale_rows(s, V, np, kp, sg, n, Q);
+    GemmProblem pg = gemm_problem(kp, kp, np, V, np, 1, Q, np, 0, b.p11, kp, a, 0.0, nullptr, 0,
+                                  kOutUpper | kMirror);
+    auto_split(pg, b.splitws);
+    gemm_f64(s, pg);
+    unit_pad(s, b.p11, k, kp);
+    potrf_inv_f64(s, b.p11, 0, D, 0, b.tmp, kp, 1, b.dinfo + slot, true, nullptr, b.t2, 0);
+    GemmProblem pq[2];
+    pq[0] = gemm_problem(np, kp, kp, V, np, 0, D, kp, 0, Q, np, 1.0, 0.0, nullptr, 0, kBUpper);
+    pq[1] = gemm_problem(np, kp, kp, C, np, 0, D, kp, 0, b.F, np, 1.0, 0.0, nullptr, 0, kBUpper);
+    gemm_f64(s, pq, 2);
+    GemmProblem ph = gemm_problem(kp, kp, np, b.F, np, 1, b.F, np, 0, b.hp, kp, a, 0.0, nullptr,
+                                  0, kOutUpper | kMirror);
+    auto_split(ph, b.splitws);
+    gemm_f64(s, ph);
+    copy_out(s, Q, np, Qout, ldqo, n, k);
+    copy_out(s, b.hp, kp, Hout, ldho, k, k);
+  };
+  if (congruent) {
+    cbasis(p, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    tm.mark(6);
+    cbasis(q, -1.0, Qm, ldqm, Hm, ldhm, 5);
+  } else {
+    basis(p, 1.0, 1.0, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    tm.mark(6);
+    basis(q, -1.0, -1.0, -1.0, Qm, ldqm, Hm, ldhm, 5);
+  }
   tm.mark(7);
   PS_HIP(hipMemcpyAsync(pin + 8, b.dinfo, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
@@ -3068,7 +3112,8 @@ int pseudosym_divide_general(ps_handle h, int n, const double* H, int ldh, const
   if (n > kPinned) return -2;
   if (opts && (opts->r < 0 || opts->r > 8 || opts->max_restarts < 0 || opts->max_steps != 0 ||
                (opts->precision != PS_PREC_FP64 && opts->precision != PS_PREC_MIXED) ||
-               (opts->basis == PS_BASIS_LDL && pad_to(n) > kLdlMaxN)))
+               ((opts->basis == PS_BASIS_LDL || opts->basis == PS_BASIS_CONGRUENT) &&
+                pad_to(n) > kLdlMaxN)))
     return -16;
   ps_opts o;
   ps_opts_default(&o);

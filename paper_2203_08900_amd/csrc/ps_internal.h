@@ -288,6 +288,9 @@ void lead_block(hipStream_t s, const double* S, int lds, const double* sg, int k
                 double* out);   // upper(sym(Sigma (a I + S)/2)) on the leading k x k, pad diag 1
 void chol_top(hipStream_t s, const double* c, int kp, const double* sg, int k, double t,
               double* top);     // top(i, j) = t sigma_i C(j, i)
+void proj_form(hipStream_t s, const double* U, int n, int np, double a,
+               double* Z);      // upper((I + a sym(U))/2), zero padding
+void unit_pad(hipStream_t s, double* x, int k, int kp);   // identity outside the leading k x k
 
 // Golub-Kahan bidiagonalization (batch of two matrices M_b with transposes Mt_b).
 void gk_init(hipStream_t s, double* v, int m, int mp, int batch, unsigned seed);

@@ -97,3 +97,106 @@ def test_general_bad_signs():
     H = torch.tensor(h, dtype=torch.float64, device="cuda")
     with pytest.raises(api.PseudosymError):
         api.divide_general(H, sig)
+
+
+# ---- bases from the projectors of the congruent symmetric T (opts.basis = "congruent")
+# Pivot order and factors follow from sign(T), so at moderate cond(M) the bases and
+# blocks are compared with the oracle's element by element; the two sides compute sign(T)
+# by their own iterations, whose difference grows with cond(T) ~ cond(M), hence the
+# tolerance.  At cond(M) up to 1e12 the properties that any valid basis has are checked:
+# the backward error at rounding level, Sigma-orthonormality and the eigenvalues.
+CONGRUENT_CASES = [(2, 7, 10.0), (17, 1, 10.0), (100, 3, 1e4), (250, 5, 1e6), (700, 6, 1e3)]
+
+
+@pytest.mark.parametrize("n,seed,kappa", CONGRUENT_CASES)
+def test_congruent_bases_parity(n, seed, kappa):
+    print(f"[general congruent] n={n} seed={seed} kappa={kappa:g}", flush=True)
+    h, sig = inputs.general_sigma(n, seed, kappa)
+    p = int(np.sum(sig > 0))
+    q = n - p
+    H = torch.tensor(h, dtype=torch.float64, device="cuda")
+    Qp, Qm, Hp, Hm, S, info = api.divide_general(H, sig, want_sign=True, basis="congruent")
+    assert info["status"] == 0 and info["restarts"] == 0
+    Qp, Qm, Hp, Hm, S = (x.cpu().numpy() for x in (Qp, Qm, Hp, Hm, S))
+    s_def = sg.sign_definition(h, sig)
+    assert np.abs(S - s_def).max() < 1e-12 * kappa * np.abs(s_def).max()
+    qp_ref, qm_ref, hp_ref, hm_ref = bs.congruent_bases_general(h, sig)
+    tol = 1e-14 * kappa
+    errs = []
+    for x, y, k in ((Qp, qp_ref, p), (Hp, hp_ref, p), (Qm, qm_ref, q), (Hm, hm_ref, q)):
+        if k:
+            errs.append(rel(x, y))
+            assert errs[-1] < tol
+    print(f"[general congruent] element-wise {max(errs):.2e}", flush=True)
+    if p and q:
+        bwd = np.linalg.norm(Qp.T @ (sig[:, None] * h) @ Qm) / np.linalg.norm(h)
+        assert bwd < 1e-13
+
+
+@pytest.mark.parametrize("kappa,seed", [(1e8, 21), (1e10, 22), (1e12, 23)])
+def test_congruent_bases_ill_conditioned(kappa, seed):
+    n = 250
+    print(f"[general congruent] n={n} seed={seed} kappa={kappa:g}", flush=True)
+    h, sig = inputs.general_sigma(n, seed, kappa)
+    p = int(np.sum(sig > 0))
+    q = n - p
+    H = torch.tensor(h, dtype=torch.float64, device="cuda")
+    Qp, Qm, Hp, Hm, _, info = api.divide_general(H, sig, basis="congruent")
+    assert info["status"] == 0
+    assert 0.5 * kappa <= info["cond_est"] <= kappa * (1.0 + 1e-8)
+    Qp, Qm, Hp, Hm = (x.cpu().numpy() for x in (Qp, Qm, Hp, Hm))
+    bwd = np.linalg.norm(Qp.T @ (sig[:, None] * h) @ Qm) / np.linalg.norm(h)
+    eo_p = np.abs(Qp.T @ (sig[:, None] * Qp) - np.eye(p)).max()
+    eo_m = np.abs(Qm.T @ (sig[:, None] * Qm) + np.eye(q)).max()
+    # eigenvalues of H_+- against LAPACK's nonsymmetric solver on H (which agrees with
+    # the eigenvalues of T = R Sigma R^T to 1e-14 here).  The bases reach rounding level
+    # in the backward error, but the eigenvalues of the blocks lose more: about 1e-11 of
+    # the largest at cond(M) = 1e12, in the oracle too, also with sign(T) from an
+    # eigendecomposition; the bound below follows that growth
+    lam = np.sort(np.linalg.eigvals(h).real)
+    scale = np.abs(lam).max()
+    ev = lambda x: np.sort(np.linalg.eigvalsh(0.5 * (x + x.T)))
+    e_gpu = max(np.abs(ev(Hp) - lam[lam > 0]).max(), np.abs(ev(Hm) - lam[lam < 0]).max()) / scale
+    _, _, hp_ref, hm_ref = bs.congruent_bases_general(h, sig)
+    e_ref = max(np.abs(ev(hp_ref) - lam[lam > 0]).max(),
+                np.abs(ev(hm_ref) - lam[lam < 0]).max()) / scale
+    print(f"[general congruent] backward error {bwd:.2e} Sigma-orth {max(eo_p, eo_m):.2e} "
+          f"eigenvalues gpu {e_gpu:.2e} oracle {e_ref:.2e}", flush=True)
+    assert bwd < 1e-13
+    assert max(eo_p, eo_m) < 1e-12
+    etol = max(1e-13, 1e-21 * kappa)
+    assert e_ref < etol and e_gpu < etol
+    # the same matrix through Alg. 6 on sign(H): the accuracy the congruent bases recover
+    Qp6, Qm6, _, _, _, _ = api.divide_general(H, sig, raise_on_error=False)
+    if Qp6.numel() and Qm6.numel():
+        Qp6, Qm6 = Qp6.cpu().numpy(), Qm6.cpu().numpy()
+        bwd6 = np.linalg.norm(Qp6.T @ (sig[:, None] * h) @ Qm6) / np.linalg.norm(h)
+        print(f"[general congruent] Alg. 6 backward error {bwd6:.2e}", flush=True)
+
+
+def test_congruent_one_signed():
+    """Sigma = I: one orthonormal basis of R^n, H_+ orthogonally similar to H."""
+    n = 70
+    hg, sg_gen = inputs.general_sigma(n, 9, 50.0)
+    h = sg_gen[:, None] * hg
+    h = 0.5 * (h + h.T)
+    H = torch.tensor(h, dtype=torch.float64, device="cuda")
+    Qp, Qm, Hp, Hm, _, info = api.divide_general(H, np.ones(n), basis="congruent")
+    assert info["status"] == 0 and Qm.shape == (n, 0) and Hm.shape == (0, 0)
+    Qp, Hp = Qp.cpu().numpy(), Hp.cpu().numpy()
+    assert np.abs(Qp.T @ Qp - np.eye(n)).max() < 1e-13
+    assert np.abs(Qp @ Hp @ Qp.T - h).max() < 1e-12 * np.abs(h).max()
+
+
+def test_congruent_option_checks():
+    # the Casida entry points take no congruent basis
+    a, b = inputs.small_dense(8, 1)
+    A = torch.tensor(a, dtype=torch.float64, device="cuda")
+    B = torch.tensor(b, dtype=torch.float64, device="cuda")
+    with pytest.raises(api.PseudosymError) as e:
+        api.divide(A, B, basis="congruent")
+    assert e.value.code == -11
+    h, sig = inputs.general_sigma(10, 1, 5.0)
+    H = torch.tensor(h, dtype=torch.float64, device="cuda")
+    Qp, Qm, Hp, Hm, _, info = api.divide_general(H, sig, basis="congruent")
+    assert info["status"] == 0
