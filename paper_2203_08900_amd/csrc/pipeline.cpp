@@ -1263,7 +1263,7 @@ int run(ps_handle h, int m, const double* A, int lda, const double* B, int ldb, 
 size_t general_bytes(int n, const ps_opts& o) {
   Arena a;
   Buffers b;
-  carve(a, b, n, resolve_r(o), 1, mixed_arith(o, n));
+  carve(a, b, n, resolve_r(o), 1, false);   // FP64 only, see run_general
   a.take<double>(pad_to(n));   // the signs
   return a.off + kAlign;
 }
@@ -1279,7 +1279,7 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
   ar.base = base;
   ar.dry = false;
   Buffers b;
-  carve(ar, b, n, r, 1, mixed_arith(o, n));
+  carve(ar, b, n, r, 1, false);
   double* sg = ar.take<double>(pad_to(n));
   const int np = b.mp;
   const long long S = (long long)b.S;
@@ -1346,9 +1346,11 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
   inf.beta = beta;
   tm.mark(1);
   // ---- sign(T) by the Zolotarev iteration with the stopping test of Alg. 8
+  // FP64 steps whatever opts.precision says: cond(T) = cond(M), far above the shifted
+  // conditions the FP32 bulk is chosen for, and the invariant subspaces an FP32 step
+  // leaves about cond(T) u_32 off are not rotated back by an FP64 polish of U
   MixedCtx mxc{h->side, h->fork, h->join, o.mixed_kappa > 1.0 ? o.mixed_kappa : 20.0};
-  const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm,
-                                   mixed_arith(o, n) ? &mxc : nullptr, &mxc);
+  const int status = polar_iterate(s, b, b.y, alpha, beta, o.r, o, pin, inf, tm, nullptr, &mxc);
   if (status != PS_OK) {
     inf.status = status;
     tm.finish(inf.phase_ms);

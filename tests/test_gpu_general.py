@@ -200,3 +200,30 @@ def test_congruent_option_checks():
     H = torch.tensor(h, dtype=torch.float64, device="cuda")
     Qp, Qm, Hp, Hm, _, info = api.divide_general(H, sig, basis="congruent")
     assert info["status"] == 0
+
+
+@pytest.mark.parametrize("basis", ["alg6", "congruent"])
+def test_general_mixed_request_runs_fp64(basis):
+    """Padded n >= 1024, where the Casida form would take the FP32 bulk: the general path
+    runs its steps in FP64 whatever the precision option (cond(T) = cond(M)), so a
+    "mixed" request gives the FP64 result bit for bit, at the FP64 accuracy."""
+    n, seed, kappa = 1100, 8, 1e3
+    print(f"[general mixed] n={n} seed={seed} kappa={kappa:g} basis={basis}", flush=True)
+    h, sig = inputs.general_sigma(n, seed, kappa)
+    H = torch.tensor(h, dtype=torch.float64, device="cuda")
+    Qp, Qm, Hp, Hm, _, info = api.divide_general(H, sig, precision="mixed", basis=basis)
+    assert info["status"] == 0
+    ref = api.divide_general(H, sig, precision="fp64", basis=basis)
+    for x, y in zip((Qp, Qm, Hp, Hm), ref[:4]):
+        assert torch.equal(x, y)
+    Qp, Qm, Hp, Hm = (x.cpu().numpy() for x in (Qp, Qm, Hp, Hm))
+    if basis == "alg6":
+        qp_ref, qm_ref = bs.alg6_bases_general(sg.sign_definition(h, sig), sig)
+        hp_ref, hm_ref, _ = dv.decouple(h, sig, qp_ref, qm_ref)
+    else:
+        qp_ref, qm_ref, hp_ref, hm_ref = bs.congruent_bases_general(h, sig)
+    err = max(rel(Qp, qp_ref), rel(Qm, qm_ref), rel(Hp, hp_ref), rel(Hm, hm_ref))
+    bwd = np.linalg.norm(Qp.T @ (sig[:, None] * h) @ Qm) / np.linalg.norm(h)
+    print(f"[general mixed] element-wise {err:.2e} backward {bwd:.2e}", flush=True)
+    assert err < 1e-14 * kappa * (100.0 if basis == "alg6" else 1.0)
+    assert bwd < (1e-11 if basis == "alg6" else 1e-13)
