@@ -1418,42 +1418,61 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
   // Sigma-Gram matrix a V^T Sigma V = R_G^T R_G, Q = V R_G^{-1}, and the decoupled block
   // a (R Q)^T (R Q) = a F^T F with F = C R_G^{-1} (R V = C).  No product with sign(H),
   // whose projectors carry cond(M) u of error.
-  auto cbasis = [&](int k, double a, double* Qout, int ldqo, double* Hout, int ldho, int slot) {
+  // The two sides are independent chains of latency-bound LDL^T panels: with a side
+  // stream the negative one runs there, on its own buffers, while the positive one runs
+  // on the caller's stream (split-K only on the latter, whose workspace is not shared).
+  struct CBuf {
+    hipStream_t st;
+    double *Z, *C, *V, *Q, *G, *D, *F, *Hb, *tmp, *pv, *ws, *L;
+    int* iw;
+  };
+  auto cbasis = [&](const CBuf& u, int k, double a, double* Qout, int ldqo, double* Hout,
+                    int ldho, int slot) {
     if (k == 0) return;
+    const hipStream_t st = u.st;
     const int kp = pad_to(k);
-    double* C = b.w;    // np x kp
-    double* V = b.t1;   // np x kp
-    double* Q = b.ab;   // np x kp (Sigma V first)
-    double* D = b.wc;   // kp x kp, R_G^{-1}
-    int* iw = reinterpret_cast<int*>(b.t2);
-    const LdlScratch lw{b.wc, iw, iw + kp};
-    proj_form(s, b.x2, n, np, a, b.z);
-    ldl_factor(s, b.z, n, np, k, C, lw, b.dinfo + slot);
-    GemmProblem pv = gemm_problem(np, kp, np, W, np, 0, C, np, 0, V, np, 1.0, 0.0, nullptr, 0,
-                                  kAUpper);
-    gemm_f64(s, pv);
-    ldl_scale_rows(s, V, np, kp, sg, n, Q);
-    GemmProblem pg = gemm_problem(kp, kp, np, V, np, 1, Q, np, 0, b.p11, kp, a, 0.0, nullptr, 0,
-                                  kOutUpper | kMirror);
-    auto_split(pg, b.splitws);
-    gemm_f64(s, pg);
-    unit_pad(s, b.p11, k, kp);
-    potrf_inv_f64(s, b.p11, 0, D, 0, b.tmp, kp, 1, b.dinfo + slot, true, nullptr, b.t2, 0);
-    GemmProblem pq[2];
-    pq[0] = gemm_problem(np, kp, kp, V, np, 0, D, kp, 0, Q, np, 1.0, 0.0, nullptr, 0, kBUpper);
-    pq[1] = gemm_problem(np, kp, kp, C, np, 0, D, kp, 0, b.F, np, 1.0, 0.0, nullptr, 0, kBUpper);
-    gemm_f64(s, pq, 2);
-    GemmProblem ph = gemm_problem(kp, kp, np, b.F, np, 1, b.F, np, 0, b.hp, kp, a, 0.0, nullptr,
+    const LdlScratch lw{u.L, u.iw, u.iw + kp};
+    proj_form(st, b.x2, n, np, a, u.Z);
+    ldl_factor(st, u.Z, n, np, k, u.C, lw, b.dinfo + slot);
+    GemmProblem pv = gemm_problem(np, kp, np, W, np, 0, u.C, np, 0, u.V, np, 1.0, 0.0, nullptr,
+                                  0, kAUpper);
+    gemm_f64(st, pv);
+    ldl_scale_rows(st, u.V, np, kp, sg, n, u.Q);   // Sigma V
+    GemmProblem pg = gemm_problem(kp, kp, np, u.V, np, 1, u.Q, np, 0, u.G, kp, a, 0.0, nullptr,
                                   0, kOutUpper | kMirror);
-    auto_split(ph, b.splitws);
-    gemm_f64(s, ph);
-    copy_out(s, Q, np, Qout, ldqo, n, k);
-    copy_out(s, b.hp, kp, Hout, ldho, k, k);
+    if (u.ws) auto_split(pg, u.ws);
+    gemm_f64(st, pg);
+    unit_pad(st, u.G, k, kp);
+    potrf_inv_f64(st, u.G, 0, u.D, 0, u.tmp, kp, 1, b.dinfo + slot, true, nullptr, u.pv, 0);
+    GemmProblem pq[2];
+    pq[0] = gemm_problem(np, kp, kp, u.V, np, 0, u.D, kp, 0, u.Q, np, 1.0, 0.0, nullptr, 0,
+                         kBUpper);
+    pq[1] = gemm_problem(np, kp, kp, u.C, np, 0, u.D, kp, 0, u.F, np, 1.0, 0.0, nullptr, 0,
+                         kBUpper);
+    gemm_f64(st, pq, 2);
+    GemmProblem ph = gemm_problem(kp, kp, np, u.F, np, 1, u.F, np, 0, u.Hb, kp, a, 0.0, nullptr,
+                                  0, kOutUpper | kMirror);
+    if (u.ws) auto_split(ph, u.ws);
+    gemm_f64(st, ph);
+    copy_out(st, u.Q, np, Qout, ldqo, n, k);
+    copy_out(st, u.Hb, kp, Hout, ldho, k, k);
   };
   if (congruent) {
-    cbasis(p, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    const hipStream_t t = (h->side && p > 0 && q > 0) ? h->side : s;
+    const CBuf pos{s,     b.z,   b.w,    b.t1,   b.ab,  b.p11, b.wc, b.F, b.hp,
+                   b.tmp, b.t2,  b.splitws, b.wc, reinterpret_cast<int*>(b.t2)};
+    const CBuf neg{t,         b.z + S,  b.w + S, b.z + 2 * S, b.ab + S, b.s21, b.top, b.F + S,
+                   b.as,      b.tmp + (size_t)np * kNb, b.bs, t == s ? b.splitws : nullptr,
+                   b.top,     reinterpret_cast<int*>(b.qbot)};
+    if (t != s) {
+      PS_HIP(hipEventRecord(h->fork, s));
+      PS_HIP(hipStreamWaitEvent(t, h->fork, 0));
+    }
+    cbasis(neg, q, -1.0, Qm, ldqm, Hm, ldhm, 5);
+    if (t != s) PS_HIP(hipEventRecord(h->join, t));
+    cbasis(pos, p, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    if (t != s) PS_HIP(hipStreamWaitEvent(s, h->join, 0));
     tm.mark(6);
-    cbasis(q, -1.0, Qm, ldqm, Hm, ldhm, 5);
   } else {
     basis(p, 1.0, 1.0, 1.0, Qp, ldqp, Hp, ldhp, 4);
     tm.mark(6);
