@@ -1380,15 +1380,6 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
     if (k == 0) return;
     const int kp = pad_to(k), rp = pad_to(std::max(n - k, 1));
     double* Q = b.ab;   // np x kp, ld np
-    if (o.basis == PS_BASIS_LDL) {
-      // Alg. 7: a Sigma P_a = (Sigma S + a Sigma)/2 (rank k) = C C^T by the truncated
-      // LDL^T with diagonal pivoting, Q = Sigma C
-      int* iw = reinterpret_cast<int*>(b.t2);
-      const LdlScratch lw{b.wc, iw, iw + kp};
-      ldl_form_general(s, Sg, sg, n, np, a, b.z);
-      ldl_factor(s, b.z, n, np, k, b.w, lw, b.dinfo + slot);
-      ldl_scale_rows(s, b.w, np, kp, sg, n, Q);
-    } else {
     lead_block(s, Sg, np, sg, k, kp, a, b.p11);
     potrf_inv_f64(s, b.p11, 0, b.wc, 0, b.tmp, kp, 1, b.dinfo + slot, true, nullptr, b.t2, 0);
     chol_top(s, b.p11, kp, sg, k, t, b.top);
@@ -1401,7 +1392,6 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
       copy_pad(s, b.t1, rp, n - k, k, Q + k, np, np - k, kp);
     } else if (np > k) {
       copy_pad(s, b.t1, rp, 0, 0, Q + k, np, np - k, kp);   // zero padding rows
-    }
     }
     GemmProblem pf = gemm_problem(np, kp, np, R, np, 0, Q, np, 0, b.F, np, 1.0, 0.0, nullptr, 0,
                                   kAUpper);
@@ -1457,7 +1447,28 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
     copy_out(st, u.Q, np, Qout, ldqo, n, k);
     copy_out(st, u.Hb, kp, Hout, ldho, k, k);
   };
-  if (congruent) {
+  // Alg. 7 on the same per-side buffers: a Sigma P_a = (Sigma S + a Sigma)/2 = C C^T,
+  // Q = Sigma C, and the decoupled block hs (R Q)^T (R Q)
+  auto lbasis = [&](const CBuf& u, int k, double a, double hs, double* Qout, int ldqo,
+                    double* Hout, int ldho, int slot) {
+    if (k == 0) return;
+    const hipStream_t st = u.st;
+    const int kp = pad_to(k);
+    const LdlScratch lw{u.L, u.iw, u.iw + kp};
+    ldl_form_general(st, Sg, sg, n, np, a, u.Z);
+    ldl_factor(st, u.Z, n, np, k, u.C, lw, b.dinfo + slot);
+    ldl_scale_rows(st, u.C, np, kp, sg, n, u.Q);
+    GemmProblem pf = gemm_problem(np, kp, np, R, np, 0, u.Q, np, 0, u.F, np, 1.0, 0.0, nullptr,
+                                  0, kAUpper);
+    gemm_f64(st, pf);
+    GemmProblem ph = gemm_problem(kp, kp, np, u.F, np, 1, u.F, np, 0, u.Hb, kp, hs, 0.0, nullptr,
+                                  0, kOutUpper | kMirror);
+    if (u.ws) auto_split(ph, u.ws);
+    gemm_f64(st, ph);
+    copy_out(st, u.Q, np, Qout, ldqo, n, k);
+    copy_out(st, u.Hb, kp, Hout, ldho, k, k);
+  };
+  if (congruent || o.basis == PS_BASIS_LDL) {
     const hipStream_t t = (h->side && p > 0 && q > 0) ? h->side : s;
     const CBuf pos{s,     b.z,   b.w,    b.t1,   b.ab,  b.p11, b.wc, b.F, b.hp,
                    b.tmp, b.t2,  b.splitws, b.wc, reinterpret_cast<int*>(b.t2)};
@@ -1468,9 +1479,15 @@ int run_general(ps_handle h, int n, const double* H, int ldh, const double* sigm
       PS_HIP(hipEventRecord(h->fork, s));
       PS_HIP(hipStreamWaitEvent(t, h->fork, 0));
     }
-    cbasis(neg, q, -1.0, Qm, ldqm, Hm, ldhm, 5);
-    if (t != s) PS_HIP(hipEventRecord(h->join, t));
-    cbasis(pos, p, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    if (congruent) {
+      cbasis(neg, q, -1.0, Qm, ldqm, Hm, ldhm, 5);
+      if (t != s) PS_HIP(hipEventRecord(h->join, t));
+      cbasis(pos, p, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    } else {
+      lbasis(neg, q, -1.0, -1.0, Qm, ldqm, Hm, ldhm, 5);
+      if (t != s) PS_HIP(hipEventRecord(h->join, t));
+      lbasis(pos, p, 1.0, 1.0, Qp, ldqp, Hp, ldhp, 4);
+    }
     if (t != s) PS_HIP(hipStreamWaitEvent(s, h->join, 0));
     tm.mark(6);
   } else {
