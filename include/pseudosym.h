@@ -129,7 +129,8 @@ typedef struct {
                        /* (the same rational function to below 1e-17)               */
   int basis;           /* pseudosym_divide / pseudosym_eig: PS_BASIS_ALG6 (default) */
                        /* or PS_BASIS_CORE, see below; PS_BASIS_LDL for           */
-                       /* pseudosym_divide and pseudosym_divide_general          */
+                       /* pseudosym_divide and pseudosym_divide_general;         */
+                       /* PS_BASIS_CONGRUENT for pseudosym_divide_general        */
   int iteration;       /* PS_ITER_ZOLO (Alg. 8, default) or one of the comparison  */
                        /* iterations of Sec. 6, see below (FP64 only)             */
   int refine;          /* what follows the iteration, PS_REFINE_*:               */
