@@ -227,3 +227,29 @@ def test_general_mixed_request_runs_fp64(basis):
     print(f"[general mixed] element-wise {err:.2e} backward {bwd:.2e}", flush=True)
     assert err < 1e-14 * kappa * (100.0 if basis == "alg6" else 1.0)
     assert bwd < (1e-11 if basis == "alg6" else 1e-13)
+
+
+def test_congruent_on_casida_form_matches_casida_path():
+    """The Casida matrix H = [[A, B], [-B, -A]] (Sigma = diag(I, -I)) through the general
+    entry with the congruent bases and through the Casida entry (half-size core, Alg. 6):
+    the same positive invariant subspace (projector Q_+ Q_+^T Sigma, unique) and the same
+    eigenvalues of H_+ (Thm. DefDivConq)."""
+    m = 300
+    a, b = inputs.small_dense(m, 17)
+    h = np.block([[a, b], [-b, -a]])
+    sig = np.concatenate([np.ones(m), -np.ones(m)])
+    print(f"[general congruent vs casida] m={m}", flush=True)
+    Qg, _, Hg, _, _, info = api.divide_general(torch.tensor(h, dtype=torch.float64, device="cuda"),
+                                               sig, basis="congruent")
+    assert info["status"] == 0 and Qg.shape == (2 * m, m)
+    Qc, Hc, ic = api.divide(torch.tensor(a, dtype=torch.float64, device="cuda"),
+                            torch.tensor(b, dtype=torch.float64, device="cuda"))
+    assert ic["status"] == 0
+    Qg, Hg, Qc, Hc = (x.cpu().numpy() for x in (Qg, Hg, Qc, Hc))
+    pg = Qg @ (sig[:, None] * Qg).T
+    pc = Qc @ (sig[:, None] * Qc).T
+    d = np.abs(pg - pc).max()
+    ev = lambda x: np.sort(np.linalg.eigvalsh(0.5 * (x + x.T)))
+    e = np.abs(ev(Hg) - ev(Hc)).max() / np.abs(ev(Hc)).max()
+    print(f"[general congruent vs casida] projector {d:.2e} eigenvalues {e:.2e}", flush=True)
+    assert d < 1e-12 and e < 1e-13
