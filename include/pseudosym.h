@@ -228,7 +228,7 @@ int ps_create(ps_handle* h, void* stream);
 int ps_destroy(ps_handle h);
 int ps_set_stream(ps_handle h, void* stream);
 
-/* Batched division (the benchmark spec batching, Alg. 2's independent problems): after the bounds
+/* Batched division (Alg. 2's independent problems): after the bounds
  * and coefficients of a class are known, its launch sequence (both Zolotarev steps, the
  * stopping-test norms, the bases and the decoupled blocks) is captured once as a HIP
  * graph and replayed when a class with the same sizes, options and workspace comes again
@@ -239,7 +239,7 @@ int ps_set_stream(ps_handle h, void* stream);
  * Returns 0, -1 (no handle) or -2 (enable not 0 or 1). */
 int ps_set_graphs(ps_handle h, int enable);
 
-/* GEMM autotuning (the benchmark spec batching: tile shapes chosen by measurement).  Every launch
+/* GEMM autotuning (tile shapes chosen by measurement).  Every launch
  * of the matrix-core GEMM is identified by a key hashed from the sizes, transposes, flags,
  * batch layout and split of its problems.  A tuning entry tells the launcher which tile
  * (64 x 64 or 128 x 128), split-K factor and schedule (stream-K or not) to use for that
